@@ -1,0 +1,159 @@
+"""Oracle: tonal optimisation (test infrastructure only).
+
+Paper Sec. 5, eq. (tonal-opt-minimisation): for a fixed mask, the inpainting
+operator B = A^{-1} C is linear in the stored values, and tonal optimisation
+finds
+
+    g* = argmin_g || f - B g ||_2^2,   g_i = 0 for i not in K,
+
+whose minimiser satisfies the normal equations (eq. tonal-normal-equations)
+B^T B g = B^T f. Restricted to the mask entries this matrix is the identity
+plus a positive semi-definite term, so the minimiser is unique for a non-empty
+mask (Sec. 1) and every method converges to the same values (Sec. 6.3).
+
+B g and B^T y are applied by their definitions, B g = A^{-1}(C g) and
+B^T y = C A^{-T} y, with one SuperLU factorisation of A reused for both.
+For grids too large for a direct factorisation the symmetric reduced form is
+used instead (Sec. 5.1, symmetrised system): B g equals g on K and solves
+L_UU u_U = -L_UK g_K on U, and B^T y equals y_K - L_KU z_U on K with
+L_UU z_U = y_U, solved by conjugate gradients to a tight tolerance.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from .inpaint import DIRECT_LIMIT, ReducedSystem, _as_chw, _check_mask, system_matrix
+
+
+class TonalOperator:
+    """B and B^T for one mask, acting on flat length-N vectors."""
+
+    def __init__(self, mask: np.ndarray, method: str = "auto"):
+        self.shape = mask.shape
+        self.K = _check_mask(mask)
+        self.c = self.K.astype(np.float64)
+        N = mask.size
+        if method == "auto":
+            method = "direct" if N <= DIRECT_LIMIT else "cg"
+        self.method = method
+        if method == "direct":
+            self.lu = spla.splu(system_matrix(mask).tocsc())
+        else:
+            self.rs = ReducedSystem(mask, "cg")
+
+    def B(self, g: np.ndarray) -> np.ndarray:
+        """u = A^{-1} C g."""
+        if self.method == "direct":
+            return self.lu.solve(self.c * g)
+        return self.rs.solve(g)
+
+    def Bt(self, y: np.ndarray) -> np.ndarray:
+        """C A^{-T} y (zero off the mask)."""
+        if self.method == "direct":
+            return self.c * self.lu.solve(np.ascontiguousarray(y, dtype=np.float64), trans="T")
+        rs = self.rs
+        z = np.zeros_like(y)
+        zU = rs.solve_UU(y[rs.U])
+        z[rs.K] = y[rs.K] - rs.LKU @ zU
+        return z
+
+    def normal(self, gK: np.ndarray) -> np.ndarray:
+        """(B^T B) restricted to the mask entries."""
+        g = np.zeros(self.K.size)
+        g[self.K] = gK
+        return self.Bt(self.B(g))[self.K]
+
+
+def _cg(matvec, rhs, x0, rtol, maxiter):
+    """Textbook conjugate gradients for a symmetric positive definite operator."""
+    x = x0.copy()
+    r = rhs - matvec(x)
+    p = r.copy()
+    rr = r @ r
+    stop = (rtol * np.linalg.norm(rhs)) ** 2
+    it = 0
+    while rr > stop and it < maxiter:
+        q = matvec(p)
+        a = rr / (p @ q)
+        x += a * p
+        r -= a * q
+        rr_new = r @ r
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    return x, it
+
+
+def tonal_optimize(f: np.ndarray, mask: np.ndarray, rtol: float = 1e-12, maxiter: int = 5000,
+                   method: str = "auto") -> np.ndarray:
+    """g* per channel by CG on the normal equations restricted to K, started at
+    g = f on K (the usual start, Sec. 5.3). Returns (C,H,W) with zeros off K."""
+    f = _as_chw(f)
+    op = TonalOperator(mask, method)
+    out = []
+    for fc in f:
+        fl = fc.ravel()
+        rhs = op.Bt(fl)[op.K]
+        gK, _ = _cg(op.normal, rhs, fl[op.K].copy(), rtol, maxiter)
+        g = np.zeros(fl.size)
+        g[op.K] = gK
+        out.append(g.reshape(mask.shape))
+    return np.stack(out)
+
+
+def tonal_dense(f: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """Brute force for tiny images: B = A^{-1} C[:, K] as a dense matrix, then
+    numpy.linalg.lstsq(B, f) per channel."""
+    f = _as_chw(f)
+    K = _check_mask(mask)
+    if mask.size > 4096:
+        raise ValueError("dense brute force is for N <= 4096")
+    A = system_matrix(mask).toarray()
+    Bd = np.linalg.solve(A, np.eye(mask.size)[:, K])
+    out = []
+    for fc in f:
+        gK = np.linalg.lstsq(Bd, fc.ravel(), rcond=None)[0]
+        g = np.zeros(mask.size)
+        g[K] = gK
+        out.append(g.reshape(mask.shape))
+    return np.stack(out)
+
+
+def reconstruct(g: np.ndarray, mask: np.ndarray, method: str = "auto") -> np.ndarray:
+    """B g per channel, (C,H,W)."""
+    g = _as_chw(g)
+    op = TonalOperator(mask, method)
+    return np.stack([op.B(gc.ravel()).reshape(mask.shape) for gc in g])
+
+
+def mse(g: np.ndarray, f: np.ndarray, mask: np.ndarray, method: str = "auto") -> float:
+    """||f - B g||^2 / (C N) over all channels (the paper's error measure)."""
+    f = _as_chw(f)
+    u = reconstruct(g, mask, method)
+    return float(((f - u) ** 2).sum() / f.size)
+
+
+def psnr(m: float) -> float:
+    """10 log10(255^2 / MSE)."""
+    return float(10.0 * np.log10(255.0 ** 2 / m))
+
+
+def normal_residual(g: np.ndarray, f: np.ndarray, mask: np.ndarray, method: str = "auto") -> np.ndarray:
+    """||B^T (f - B g)|| / ||B^T f|| per channel (relative normal-equation residual)."""
+    g, f = _as_chw(g), _as_chw(f)
+    op = TonalOperator(mask, method)
+    out = []
+    for gc, fc in zip(g, f):
+        fl = fc.ravel()
+        r = op.Bt(fl - op.B(gc.ravel()))
+        out.append(np.linalg.norm(r) / max(np.linalg.norm(op.Bt(fl)), 1e-300))
+    return np.array(out)
+
+
+def error_bound(g: np.ndarray, f: np.ndarray, mask: np.ndarray, method: str = "auto") -> np.ndarray:
+    """Certificate: on K, B^T B = I + (positive semi-definite), so its smallest
+    eigenvalue is at least 1 and ||g - g*|| <= ||B^T (f - B g)|| per channel."""
+    g, f = _as_chw(g), _as_chw(f)
+    op = TonalOperator(mask, method)
+    return np.array([np.linalg.norm(op.Bt(fc.ravel() - op.B(gc.ravel()))) for gc, fc in zip(g, f)])

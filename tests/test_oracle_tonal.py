@@ -1,0 +1,138 @@
+"""Pins for the tonal-optimisation oracle (Sec. 5, eqs. tonal-opt-minimisation and
+tonal-normal-equations): closed forms, brute force and the optimality certificate."""
+import numpy as np
+
+from oracle import inpaint as oi
+from oracle import tonal as ot
+
+
+def _rand_mask(rng, H, W, p):
+    m = (rng.random((H, W)) < p).astype(np.uint8)
+    if m.sum() == 0:
+        m[rng.integers(H), rng.integers(W)] = 1
+    return m
+
+
+def test_full_mask_returns_f_with_zero_error():
+    rng = np.random.default_rng(0)
+    f = rng.uniform(0, 255, (7, 9))
+    m = np.ones((7, 9), np.uint8)
+    g = ot.tonal_optimize(f, m)
+    np.testing.assert_allclose(g[0], f, atol=1e-9)
+    assert ot.mse(g, f, m) < 1e-18
+
+
+def test_constant_image():
+    rng = np.random.default_rng(1)
+    m = _rand_mask(rng, 20, 25, 0.05)
+    f = np.full((20, 25), 42.0)
+    g = ot.tonal_optimize(f, m)
+    np.testing.assert_allclose(g[0][m != 0], 42.0, atol=1e-9)
+    assert np.all(g[0][m == 0] == 0)
+    assert ot.mse(g, f, m) < 1e-18
+
+
+def test_single_pixel_gives_mean_and_variance():
+    """One known pixel reconstructs a flat image, so the best value is the mean
+    of f and the error is its population variance."""
+    f = np.random.default_rng(2).uniform(0, 255, (12, 10))
+    m = np.zeros((12, 10), np.uint8)
+    m[5, 2] = 1
+    g = ot.tonal_optimize(f, m)
+    assert abs(g[0, 5, 2] - f.mean()) < 1e-9
+    assert abs(ot.mse(g, f, m) - f.var()) < 1e-8
+
+
+def test_1d_is_least_squares_linear_spline_fit():
+    """H = 1: B's columns are hat functions over the mask positions with flat
+    ends (piecewise-linear interpolation), so g* is the least-squares fit of f in
+    that spline space. The basis is built with np.interp, not with the oracle."""
+    rng = np.random.default_rng(3)
+    W = 80
+    f = rng.uniform(0, 255, W)
+    pos = np.sort(rng.choice(W, 9, replace=False))
+    m = np.zeros((1, W), np.uint8)
+    m[0, pos] = 1
+    basis = np.stack([np.interp(np.arange(W), pos, np.eye(len(pos))[j]) for j in range(len(pos))], axis=1)
+    ref = np.linalg.lstsq(basis, f, rcond=None)[0]
+    g = ot.tonal_optimize(f[None], m)[0, 0]
+    np.testing.assert_allclose(g[pos], ref, atol=1e-8)
+    # the normal matrix of hat functions is tridiagonal
+    BtB = basis.T @ basis
+    assert np.all(np.abs(np.triu(BtB, 2)) < 1e-12)
+
+
+def test_dense_lstsq_agrees():
+    rng = np.random.default_rng(4)
+    for H, W, p in [(8, 9, 0.15), (16, 16, 0.05), (30, 31, 0.04), (1, 40, 0.2), (3, 3, 0.4)]:
+        m = _rand_mask(rng, H, W, p)
+        f = rng.uniform(0, 255, (2, H, W))
+        g = ot.tonal_optimize(f, m)
+        gd = ot.tonal_dense(f, m)
+        np.testing.assert_allclose(g, gd, rtol=1e-8, atol=1e-7)
+
+
+def test_normal_matrix_lambda_min_at_least_one():
+    """On the mask entries B^T B = I + H^T H, so its smallest eigenvalue is >= 1;
+    this is what makes the certificate ||g - g*|| <= ||B^T(f - B g)|| valid."""
+    rng = np.random.default_rng(5)
+    m = _rand_mask(rng, 14, 15, 0.08)
+    K = m.ravel() != 0
+    A = oi.system_matrix(m).toarray()
+    Bd = np.linalg.solve(A, np.eye(m.size)[:, K])
+    lam = np.linalg.eigvalsh(Bd.T @ Bd)
+    assert lam.min() >= 1 - 1e-12
+    f = rng.uniform(0, 255, (14, 15))
+    gs = ot.tonal_optimize(f, m)
+    g = gs.copy()
+    g[0][m != 0] += rng.standard_normal(int(K.sum()))
+    assert np.linalg.norm(g - gs) <= ot.error_bound(g, f, m)[0] + 1e-9
+
+
+def test_bt_definition_matches_reduced_gather():
+    """B^T y = C A^{-T} y equals y_K + sum over unknown 4-neighbours j of z_j,
+    with L_UU z_U = y_U (the symmetrised form of Sec. 5.1)."""
+    rng = np.random.default_rng(6)
+    m = _rand_mask(rng, 11, 13, 0.1)
+    y = rng.standard_normal(m.size)
+    direct = ot.TonalOperator(m, "direct").Bt(y)
+    reduced = ot.TonalOperator(m, "cg").Bt(y)
+    np.testing.assert_allclose(direct, reduced, atol=1e-9)
+    # gather written out by neighbours
+    rs = oi.ReducedSystem(m)
+    z = np.zeros(m.size)
+    z[rs.U] = rs.solve_UU(y[rs.U])
+    H, W = m.shape
+    g = np.zeros(m.size)
+    for i in np.flatnonzero(rs.K):
+        yy, xx = divmod(i, W)
+        s = y[i]
+        for dy, dx in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+            qy, qx = yy + dy, xx + dx
+            if 0 <= qy < H and 0 <= qx < W and not rs.K[qy * W + qx]:
+                s += z[qy * W + qx]
+        g[i] = s
+    np.testing.assert_allclose(direct, g, atol=1e-9)
+
+
+def test_optimum_beats_perturbations_and_plain_values():
+    rng = np.random.default_rng(7)
+    m = _rand_mask(rng, 24, 24, 0.05)
+    f = rng.uniform(0, 255, (24, 24))
+    g = ot.tonal_optimize(f, m)
+    best = ot.mse(g, f, m)
+    assert best <= ot.mse(f * (m != 0), f, m) + 1e-12
+    for _ in range(3):
+        d = np.zeros_like(g)
+        d[0][m != 0] = rng.standard_normal(int(m.sum()))
+        assert best < ot.mse(g + 0.1 * d, f, m)
+    assert ot.normal_residual(g, f, m)[0] < 1e-10
+
+
+def test_cg_path_matches_direct_path():
+    rng = np.random.default_rng(8)
+    m = _rand_mask(rng, 40, 33, 0.04)
+    f = rng.uniform(0, 255, (40, 33))
+    a = ot.tonal_optimize(f, m, method="direct")
+    b = ot.tonal_optimize(f, m, method="cg")
+    np.testing.assert_allclose(a, b, atol=1e-7)
