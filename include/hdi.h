@@ -1,0 +1,129 @@
+/* hdi.h -- C ABI of libhdi: homogeneous diffusion inpainting and its data
+ * optimisation on AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the masked 5-point Laplace system of the paper's
+ * Sec. 2.1, eq. (inp-discrete-lsi):
+ *
+ *     A u = C f,   A = C + (I - C) L,
+ *
+ * C = diag(c) for a binary mask c, L the negated 5-point Laplacian with
+ * reflecting boundary (the 4-neighbour grid-graph Laplacian, unit spacing).
+ * On top of that solve it offers tonal optimisation (Sec. 5) and one step of
+ * Delaunay densification (Sec. 4.1, Alg. 1).
+ *
+ * Conventions shared by every entry point
+ *   Layout     planar C x H x W, row-major, x fastest: element (c, y, x) is at
+ *              index c*H*W + y*W + x. Masks are H x W uint8, nonzero = known.
+ *   Memory     every array argument is DEVICE memory owned by the caller
+ *              (for example torch tensors). The library never allocates or
+ *              frees device memory on these paths: scratch space comes from the
+ *              caller's workspace buffer, whose size the *_workspace_bytes query
+ *              gives. Report structs and n_added are HOST memory.
+ *   Streams    `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *              Calls are host-synchronous: they return once outputs and reports
+ *              are final.
+ *   Errors     arguments are checked before any launch; on failure nothing is
+ *              launched, outputs are untouched and hdi_last_error() (per thread)
+ *              describes the problem. A HIP failure maps to HDI_ERR_HIP. The
+ *              library never aborts or exits.
+ *   Threads    calls on distinct workspaces may run concurrently.
+ */
+#ifndef HDI_H
+#define HDI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HDI_OK = 0,
+    HDI_ERR_ARG = 1,             /* bad size, pointer, parameter or non-finite input */
+    HDI_ERR_EMPTY_MASK = 2,      /* c = 0: A is singular (Sec. 2.1) */
+    HDI_ERR_NO_CONVERGENCE = 3,  /* tolerance not met within the iteration cap;
+                                    outputs hold the last iterate, the report the
+                                    achieved residual */
+    HDI_ERR_WORKSPACE = 4,       /* workspace missing or smaller than the query */
+    HDI_ERR_HIP = 5,             /* a HIP runtime call failed */
+    HDI_ERR_BUDGET = 6           /* a server job can never fit the arena */
+} hdi_status;
+
+typedef struct {
+    int32_t width, height;   /* >= 1 */
+    int32_t channels;        /* 1 or 3: colour channels are independent systems
+                                sharing one matrix (Sec. 2.1) */
+} hdi_image;
+
+/* Inner solver parameters. A zero field selects the default.
+ *   rel_tol      stop when max_c ||C f - A u||_2 / ||C f||_2 <= rel_tol
+ *                (FP64 residual; default 1e-6)
+ *   max_outer    cap on refinement rounds (default 40)
+ *   overlap      overlap of the 32x32 subdomain blocks of the Schwarz smoother
+ *                (Sec. 3.1, 3.3; default 4, valid 2..16, even)
+ *   local_iters  conjugate-gradient iterations per block and smoothing step
+ *                (Sec. 3.3; default 8)
+ *   coarse_iters CG iterations on the coarsest level, which is a single block
+ *                (Sec. 3.3; default 64)
+ *   flags        HDI_FLAG_* bits
+ * Each refinement round applies one V-cycle with one pre- and one
+ * post-smoothing step (Sec. 3.3).                                            */
+typedef struct {
+    double rel_tol;
+    int32_t max_outer, overlap, local_iters, coarse_iters, flags;
+} hdi_solve_params;
+
+#define HDI_FLAG_NO_FMG 1   /* cold start from u = C f instead of the reduced
+                               full-multigrid initialisation (Sec. 3.2) */
+
+typedef struct {
+    double rel_residual[3];  /* achieved FP64 relative residual per channel */
+    int32_t outer_iters;     /* refinement rounds */
+    int32_t vcycles;         /* V-cycles applied in total */
+    float ms;                /* device time of the call (HIP events) */
+} hdi_solve_report;
+
+/* Bytes of workspace inpaint_solve needs for this image. 0 on bad sizes. */
+size_t hdi_inpaint_workspace_bytes(hdi_image img);
+
+/* Homogeneous diffusion inpainting, Sec. 2.1 eq. (inp-discrete-lsi), solved
+ * with the multigrid Schwarz method of Sec. 3 in FP32 inside an FP64
+ * iterative refinement.
+ *   mask  H x W uint8, nonzero = known (device)
+ *   f     C x H x W float32 image; only values on the mask are read (device)
+ *   u     C x H x W float64 output; u = f exactly on the mask (device)
+ *   u0    optional C x H x W float64 warm start (device), NULL for none
+ *   ws    workspace of at least hdi_inpaint_workspace_bytes(img) (device)
+ *   params, report  host, both nullable
+ * Returns HDI_ERR_EMPTY_MASK for an all-zero mask and HDI_ERR_NO_CONVERGENCE
+ * when rel_tol is not reached within max_outer rounds. */
+int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double *u,
+                      const double *u0, void *ws, size_t ws_bytes,
+                      const hdi_solve_params *params, hdi_solve_report *report, void *stream);
+
+/* Number of 32x32 Schwarz blocks with the given overlap on one level of one
+ * channel: per dimension ceil((n - 32) / (32 - overlap)) + 1 (1 if n <= 32),
+ * the last block shifted to end at the border (Sec. 3.3). Host-only. */
+int64_t hdi_block_count(int32_t width, int32_t height, int32_t overlap);
+
+/* Kernel timing (host-only switches; the numbers come from HIP events recorded
+ * around each launch on the caller's stream while enabled). Kernel ids:
+ *   0 FP64 residual (finest level)     1 Schwarz pre-smoothing (finest level)
+ *   2 Schwarz post-smoothing (finest)  3 residual restriction (finest level)
+ *   4 FP64 refinement update           5 all coarser levels and the FMG start
+ * For each id the library accumulates the number of launches, their summed
+ * device time in ms and the algorithmic bytes those launches must move (every
+ * input element read once, every output element written once). */
+#define HDI_NUM_KERNEL_IDS 6
+void hdi_stats_enable(int32_t on);
+void hdi_stats_reset(void);
+int32_t hdi_stats_get(int32_t kernel_id, int64_t *launches, double *total_ms, double *alg_bytes);
+
+const char *hdi_status_string(int32_t status);
+const char *hdi_last_error(void);   /* thread-local message of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDI_H */

@@ -1,0 +1,71 @@
+"""ctypes view of libhdi.so: the structs and signatures of include/hdi.h."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhdi.so")
+
+HDI_OK, HDI_ERR_ARG, HDI_ERR_EMPTY_MASK, HDI_ERR_NO_CONVERGENCE, HDI_ERR_WORKSPACE, HDI_ERR_HIP, HDI_ERR_BUDGET = range(7)
+HDI_FLAG_NO_FMG = 1
+
+
+class hdi_image(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("channels", ctypes.c_int32)]
+
+
+class hdi_solve_params(ctypes.Structure):
+    _fields_ = [("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("local_iters", ctypes.c_int32), ("coarse_iters", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class hdi_solve_report(ctypes.Structure):
+    _fields_ = [("rel_residual", ctypes.c_double * 3), ("outer_iters", ctypes.c_int32),
+                ("vcycles", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "hdi_inpaint_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
+    "inpaint_solve": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                       ctypes.POINTER(hdi_solve_params), ctypes.POINTER(hdi_solve_report), _P]),
+    "hdi_block_count": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "hdi_stats_enable": (None, [ctypes.c_int32]),
+    "hdi_stats_reset": (None, []),
+    "hdi_stats_get": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "hdi_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "hdi_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libhdi.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_2401_06747_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+class HdiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lib().hdi_status_string(status).decode()}: {msg}")
+        self.status = status
+
+
+def check(status):
+    if status != HDI_OK:
+        raise HdiError(status, lib().hdi_last_error().decode())

@@ -1,0 +1,117 @@
+// Internal declarations shared by the host driver and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string>
+
+#include "../../include/hdi.h"
+
+namespace hdi {
+
+constexpr int TILE = 32;          // Schwarz block edge (Sec. 3.3 uses 32x32)
+constexpr int MAX_LEVELS = 16;
+constexpr int RED_THREADS = 256;  // threads of the reduction kernels
+
+void set_error(const char *fmt, ...);
+
+// Geometry of the overlapping 32x32 blocks along one dimension (Sec. 3.1, 3.3).
+struct Blocks1D {
+    int n;       // pixels along the dimension
+    int count;   // number of blocks
+    int stride;  // start of block i is min(i*stride, n-32)
+};
+
+inline Blocks1D make_blocks(int n, int overlap) {
+    Blocks1D b;
+    b.n = n;
+    if (n <= TILE) {
+        b.count = 1;
+        b.stride = TILE;
+    } else {
+        b.stride = TILE - overlap;
+        b.count = (n - TILE + b.stride - 1) / b.stride + 1;
+    }
+    return b;
+}
+
+struct Level {
+    int W, H;
+    Blocks1D bx, by;
+    uint8_t *mask;   // level mask (level 0: the caller's mask)
+    float *r;        // right-hand side of the correction equation, C x H x W
+    float *ea, *eb;  // correction ping-pong buffers, C x H x W
+    float *aux;      // FMG: restricted data on this level, C x H x W
+};
+
+// Bump allocator over the caller's workspace.
+struct Arena {
+    char *base;
+    size_t size, used;
+    void *take(size_t bytes) {
+        size_t off = (used + 255) & ~size_t(255);
+        if (!base) { used = off + bytes; return nullptr; }
+        if (off + bytes > size) return nullptr;
+        used = off + bytes;
+        return base + off;
+    }
+};
+
+// A laid-out multigrid hierarchy for one image shape.
+struct Hierarchy {
+    int C, nlev;
+    Level lev[MAX_LEVELS];
+    double *partials;   // [C][nblk][2] block partial sums of the residual kernel
+    double *norms;      // [C][2] (||r||^2, ||b||^2)
+    int nblk;           // blocks of the residual kernel
+};
+
+// Lay out the hierarchy in the arena (base == nullptr: size query only).
+bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask0);
+
+struct SolveCfg {
+    double rel_tol;
+    int max_outer, local_iters, coarse_iters, vcycles, flags;
+    int64_t known;   // number of known pixels (for the byte accounting)
+};
+
+// Optional per-kernel event timing (hdi_stats_*). One Prof per call; records
+// are resolved after the call's final synchronisation.
+struct Prof {
+    bool on = false;
+    struct Rec { int id; double bytes; hipEvent_t a, b; };
+    Rec recs[4096];
+    int n = 0;
+    void begin(int id, double bytes, hipStream_t s);
+    void end(hipStream_t s);
+    void flush();   // accumulate into the global counters and free the events
+};
+Prof *prof_for_call();   // nullptr when timing is off
+
+// Kernel launchers (solver_kernels.hip).
+void launch_mask_restrict(const Level &fine, const Level &coarse, hipStream_t s);
+template <typename TD>
+void launch_init_u(int W, int H, int C, const uint8_t *mask, const TD *data, const double *u0, double *u, hipStream_t s);
+template <typename TD>
+void launch_residual(int W, int H, int C, const uint8_t *mask, const double *u, const TD *data,
+                     const double *src, float *r, double *partials, int nblk, double *norms, hipStream_t s);
+void launch_update(int W, int H, int C, const uint8_t *mask, const float *e, double *u, hipStream_t s);
+void launch_smooth_pre(const Level &L, int C, int iters, float *e_out, hipStream_t s);
+void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, const float *e_in,
+                        const float *ec, float *e_out, hipStream_t s);
+void launch_restrict_residual(const Level &L, const Level &Lc, int C, const float *e, hipStream_t s);
+// FMG helpers
+template <typename TD>
+void launch_data_restrict0(int W, int H, int C, const uint8_t *mask, const TD *data, const Level &Lc, hipStream_t s);
+void launch_data_restrict(const Level &L, const Level &Lc, int C, hipStream_t s);
+void launch_fmg_prolong(const Level &L, const Level &Lc, int C, const float *ec, float *out, hipStream_t s);
+void launch_fmg_prolong0(int W, int H, int C, const uint8_t *mask, const Level &Lc, const float *ec, double *u, hipStream_t s);
+void launch_smooth_fmg(const Level &L, int C, int iters, const float *e_in, float *e_out, hipStream_t s);
+
+// Host driver: solve A x = C data + (I - C) src on the caller's buffers.
+template <typename TD>
+int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, const TD *data,
+                     const double *src, double *u, bool warm, const SolveCfg &cfg,
+                     hdi_solve_report *rep, hipStream_t s, Prof *prof = nullptr);
+
+}  // namespace hdi

@@ -1,0 +1,381 @@
+// Host driver of the inpainting solve and the C-ABI entry points.
+//
+// Solve of eq. (inp-discrete-lsi) (Sec. 2.1): an FP64 iterative refinement
+// around an FP32 multigrid V-cycle whose smoother is the restricted additive
+// Schwarz step on overlapping 32x32 blocks with local conjugate gradients
+// (Sec. 3.1-3.3). Cold starts use the reduced full multigrid of Sec. 3.2:
+// solve on the coarsest level (a single block), then prolongate and apply one
+// smoothing step per finer level.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <atomic>
+#include <mutex>
+#include <vector>
+
+#include "hdi_internal.h"
+
+namespace hdi {
+
+// ------------------------------------------------------------------ kernel timing
+
+struct KStats { int64_t launches; double ms, bytes; };
+static std::mutex g_stats_mu;
+static KStats g_stats[HDI_NUM_KERNEL_IDS];
+static std::atomic<int> g_stats_on{0};
+
+void Prof::begin(int id, double bytes, hipStream_t s) {
+    if (!on || n >= (int)(sizeof recs / sizeof recs[0])) return;
+    Rec &r = recs[n];
+    r.id = id;
+    r.bytes = bytes;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    (void)hipEventRecord(r.a, s);
+}
+void Prof::end(hipStream_t s) {
+    if (!on || n >= (int)(sizeof recs / sizeof recs[0])) return;
+    (void)hipEventRecord(recs[n].b, s);
+    ++n;
+}
+void Prof::flush() {
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        if (hipEventSynchronize(recs[i].b) == hipSuccess && hipEventElapsedTime(&ms, recs[i].a, recs[i].b) == hipSuccess) {
+            g_stats[recs[i].id].launches += 1;
+            g_stats[recs[i].id].ms += ms;
+            g_stats[recs[i].id].bytes += recs[i].bytes;
+        }
+        (void)hipEventDestroy(recs[i].a);
+        (void)hipEventDestroy(recs[i].b);
+    }
+    n = 0;
+}
+Prof *prof_for_call() {
+    if (!g_stats_on.load()) return nullptr;
+    Prof *p = new Prof;
+    p->on = true;
+    return p;
+}
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return HDI_ERR_HIP;                                                                \
+        }                                                                                      \
+    } while (0)
+
+bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask0) {
+    h.C = C;
+    int l = 0;
+    int w = W, hh = H;
+    for (;;) {
+        Level &L = h.lev[l];
+        L.W = w;
+        L.H = hh;
+        L.bx = make_blocks(w, overlap);
+        L.by = make_blocks(hh, overlap);
+        const size_t n = (size_t)w * hh;
+        L.mask = l == 0 ? const_cast<uint8_t *>(mask0) : (uint8_t *)a.take(n);
+        L.r = (float *)a.take(n * C * sizeof(float));
+        L.ea = (float *)a.take(n * C * sizeof(float));
+        L.eb = (float *)a.take(n * C * sizeof(float));
+        L.aux = l == 0 ? nullptr : (float *)a.take(n * C * sizeof(float));
+        ++l;
+        if ((w <= TILE && hh <= TILE) || l == MAX_LEVELS) break;
+        w = (w + 1) / 2;
+        hh = (hh + 1) / 2;
+    }
+    h.nlev = l;
+    h.nblk = (int)(((size_t)W * H + RED_THREADS - 1) / RED_THREADS);
+    h.partials = (double *)a.take((size_t)C * h.nblk * 2 * sizeof(double));
+    h.norms = (double *)a.take((size_t)C * 2 * sizeof(double));
+    return a.base == nullptr || a.used <= a.size;
+}
+
+// One V-cycle for A e = r on level l (r in lev[l].r); returns the buffer with e.
+// With `prof`, the finest level's launches are timed one by one and the whole
+// coarse recursion as one record.
+static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Prof *prof = nullptr) {
+    Level &L = h.lev[l];
+    const int C = h.C;
+    if (l == h.nlev - 1) {
+        launch_smooth_pre(L, C, cfg.coarse_iters, L.ea, s);
+        return L.ea;
+    }
+    Level &Lc = h.lev[l + 1];
+    const double N = (double)L.W * L.H, Nc = (double)Lc.W * Lc.H;
+    if (prof) prof->begin(1, N * (1 + 8.0 * C), s);
+    launch_smooth_pre(L, C, cfg.local_iters, L.ea, s);
+    if (prof) { prof->end(s); prof->begin(3, N * (1 + 8.0 * C) + Nc * (1 + 4.0 * C), s); }
+    launch_restrict_residual(L, Lc, C, L.ea, s);
+    if (prof) { prof->end(s); prof->begin(5, 0.0, s); }
+    const float *ec = vcycle(h, l + 1, cfg, s);
+    if (prof) { prof->end(s); prof->begin(2, N * (1 + 12.0 * C) + 4.0 * C * Nc, s); }
+    launch_smooth_post(L, Lc, C, cfg.local_iters, L.ea, ec, L.eb, s);
+    if (prof) prof->end(s);
+    return L.eb;
+}
+
+// Reduced full multigrid initial guess (Sec. 3.2, Fig. multigrid_reduced).
+template <typename TD>
+static void fmg_init(Hierarchy &h, int W, int H, int C, const uint8_t *mask, const TD *data, double *u,
+                     const SolveCfg &cfg, hipStream_t s) {
+    launch_data_restrict0<TD>(W, H, C, mask, data, h.lev[1], s);
+    for (int l = 2; l < h.nlev; ++l) launch_data_restrict(h.lev[l - 1], h.lev[l], C, s);
+    Level &Lc = h.lev[h.nlev - 1];
+    launch_smooth_fmg(Lc, C, cfg.coarse_iters, Lc.aux, Lc.ea, s);
+    const float *cur = Lc.ea;
+    for (int l = h.nlev - 2; l >= 1; --l) {
+        Level &L = h.lev[l];
+        launch_fmg_prolong(L, h.lev[l + 1], C, cur, L.eb, s);
+        launch_smooth_fmg(L, C, cfg.local_iters, L.eb, L.ea, s);
+        cur = L.ea;
+    }
+    launch_fmg_prolong0(W, H, C, mask, h.lev[1], cur, u, s);
+}
+
+template <typename TD>
+int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, const TD *data, const double *src,
+                     double *u, bool warm, const SolveCfg &cfg, hdi_solve_report *rep, hipStream_t s, Prof *prof) {
+    hipEvent_t ev0, ev1;
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    HIP_TRY(hipEventRecord(ev0, s));
+    const double N = (double)W * H, nK = (double)cfg.known, nU = N - nK;
+    if (prof) prof->begin(5, 0.0, s);
+    for (int l = 1; l < h.nlev; ++l) launch_mask_restrict(h.lev[l - 1], h.lev[l], s);
+    launch_init_u<TD>(W, H, C, mask, data, warm ? u : nullptr, u, s);
+    if (!warm && !(cfg.flags & HDI_FLAG_NO_FMG) && src == nullptr && h.nlev > 1)
+        fmg_init<TD>(h, W, H, C, mask, data, u, cfg, s);
+    if (prof) prof->end(s);
+    HIP_TRY(hipGetLastError());
+
+    int32_t status = HDI_OK;
+    int rounds = 0, vcycles = 0;
+    double rel[3] = {0, 0, 0};
+    double norms[6];
+    const double res_bytes = N * (1 + 12.0 * C) + C * nK * sizeof(TD) + (src ? 8.0 * C * nU : 0.0);
+    for (;;) {
+        if (prof) prof->begin(0, res_bytes, s);
+        launch_residual<TD>(W, H, C, mask, u, data, src, h.lev[0].r, h.partials, h.nblk, h.norms, s);
+        if (prof) prof->end(s);
+        HIP_TRY(hipMemcpyAsync(norms, h.norms, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double worst = 0.0;
+        bool finite = true;
+        for (int c = 0; c < C; ++c) {
+            const double rr = norms[2 * c], bb = norms[2 * c + 1];
+            finite = finite && std::isfinite(rr) && std::isfinite(bb);
+            rel[c] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+            worst = std::fmax(worst, rel[c]);
+        }
+        if (!finite) {
+            set_error("non-finite residual: the input holds NaN/Inf or the iteration diverged");
+            status = HDI_ERR_ARG;
+            break;
+        }
+        if (worst <= cfg.rel_tol) break;
+        if (rounds >= cfg.max_outer) {
+            set_error("relative residual %.3e above tolerance %.3e after %d rounds", worst, cfg.rel_tol, rounds);
+            status = HDI_ERR_NO_CONVERGENCE;
+            break;
+        }
+        const float *e = vcycle(h, 0, cfg, s, prof);
+        if (prof) prof->begin(4, N + 20.0 * C * nU, s);
+        launch_update(W, H, C, mask, e, u, s);
+        if (prof) prof->end(s);
+        ++rounds;
+        ++vcycles;
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ev1, s));
+    HIP_TRY(hipEventSynchronize(ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (prof) prof->flush();
+    if (rep) {
+        for (int c = 0; c < 3; ++c) rep->rel_residual[c] = c < C ? rel[c] : 0.0;
+        rep->outer_iters = rounds;
+        rep->vcycles = vcycles;
+        rep->ms = ms;
+    }
+    return status;
+}
+
+template int32_t solve_system<float>(Hierarchy &, int, int, int, const uint8_t *, const float *, const double *,
+                                     double *, bool, const SolveCfg &, hdi_solve_report *, hipStream_t, Prof *);
+template int32_t solve_system<double>(Hierarchy &, int, int, int, const uint8_t *, const double *, const double *,
+                                      double *, bool, const SolveCfg &, hdi_solve_report *, hipStream_t, Prof *);
+
+bool check_image(const hdi_image &img) {
+    if (img.width < 1 || img.height < 1 || (img.channels != 1 && img.channels != 3)) {
+        set_error("bad image shape %dx%dx%d (need width, height >= 1 and 1 or 3 channels)", img.width, img.height,
+                  img.channels);
+        return false;
+    }
+    if ((int64_t)img.width * img.height > (int64_t)1 << 30) {
+        set_error("image of %lld pixels exceeds the 2^30 limit", (long long)img.width * img.height);
+        return false;
+    }
+    return true;
+}
+
+int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap) {
+    cfg.rel_tol = (p && p->rel_tol > 0) ? p->rel_tol : 1e-6;
+    cfg.max_outer = (p && p->max_outer > 0) ? p->max_outer : 40;
+    cfg.local_iters = (p && p->local_iters > 0) ? p->local_iters : 8;
+    cfg.coarse_iters = (p && p->coarse_iters > 0) ? p->coarse_iters : 64;
+    cfg.vcycles = 1;
+    cfg.flags = p ? p->flags : 0;
+    overlap = (p && p->overlap > 0) ? p->overlap : 4;
+    if (overlap < 2 || overlap > 16 || (overlap & 1)) {
+        set_error("overlap %d outside 2..16 or odd", overlap);
+        return HDI_ERR_ARG;
+    }
+    if (!(cfg.rel_tol < 1.0) || cfg.local_iters > 256 || cfg.coarse_iters > 4096 || cfg.max_outer > 100000) {
+        set_error("parameter out of range (rel_tol < 1, local_iters <= 256, coarse_iters <= 4096)");
+        return HDI_ERR_ARG;
+    }
+    return HDI_OK;
+}
+
+__global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
+
+// Count known pixels (device), so that an empty mask is rejected (Sec. 2.1).
+__global__ void k_count_mask(int N, const uint8_t *__restrict__ m, unsigned int *__restrict__ cnt) {
+    unsigned int local = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) local += m[i] != 0;
+    for (int o = 32; o >= 1; o >>= 1) local += __shfl_xor(local, o, 64);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(cnt, local);
+}
+
+int32_t count_mask(const uint8_t *mask, int N, unsigned int *dev_counter, unsigned int *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, dev_counter);
+    int blocks = (N + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_count_mask, dim3(blocks), dim3(256), 0, s, N, mask, dev_counter);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, dev_counter, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HDI_OK;
+}
+
+size_t inpaint_ws_bytes(int W, int H, int C) {
+    Hierarchy h;
+    Arena a{nullptr, 0, 0};
+    plan_hierarchy(h, a, W, H, C, 4, nullptr);
+    a.take(sizeof(unsigned int));
+    return a.used + 256;
+}
+
+}  // namespace hdi
+
+using namespace hdi;
+
+extern "C" {
+
+size_t hdi_inpaint_workspace_bytes(hdi_image img) {
+    if (img.width < 1 || img.height < 1 || (img.channels != 1 && img.channels != 3)) return 0;
+    return inpaint_ws_bytes(img.width, img.height, img.channels);
+}
+
+int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double *u, const double *u0, void *ws,
+                      size_t ws_bytes, const hdi_solve_params *params, hdi_solve_report *report, void *stream) {
+    if (!check_image(img)) return HDI_ERR_ARG;
+    if (!mask || !f || !u) {
+        set_error("mask, f and u must be non-null device pointers");
+        return HDI_ERR_ARG;
+    }
+    SolveCfg cfg;
+    int overlap;
+    int32_t st = fill_cfg(params, cfg, overlap);
+    if (st) return st;
+    const size_t need = inpaint_ws_bytes(img.width, img.height, img.channels);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
+        return HDI_ERR_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Arena a{(char *)ws, ws_bytes, 0};
+    Hierarchy h;
+    plan_hierarchy(h, a, img.width, img.height, img.channels, overlap, mask);
+    unsigned int *counter = (unsigned int *)a.take(sizeof(unsigned int));
+    unsigned int known = 0;
+    st = count_mask(mask, img.width * img.height, counter, &known, s);
+    if (st) return st;
+    if (known == 0) {
+        set_error("empty mask: the inpainting matrix is singular");
+        return HDI_ERR_EMPTY_MASK;
+    }
+    const int C = img.channels;
+    if (u0 && u0 != u) {
+        hipError_t e = hipMemcpyAsync(u, u0, sizeof(double) * C * img.width * img.height, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) {
+            set_error("hipMemcpyAsync: %s", hipGetErrorString(e));
+            return HDI_ERR_HIP;
+        }
+    }
+    cfg.known = known;
+    Prof *prof = prof_for_call();
+    st = solve_system<float>(h, img.width, img.height, C, mask, f, nullptr, u, u0 != nullptr, cfg, report, s, prof);
+    delete prof;
+    return st;
+}
+
+int64_t hdi_block_count(int32_t width, int32_t height, int32_t overlap) {
+    if (width < 1 || height < 1 || overlap < 0 || overlap >= TILE) return -1;
+    return (int64_t)make_blocks(width, overlap).count * make_blocks(height, overlap).count;
+}
+
+void hdi_stats_enable(int32_t on) { g_stats_on.store(on ? 1 : 0); }
+
+void hdi_stats_reset(void) {
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    for (auto &k : g_stats) k = KStats{0, 0.0, 0.0};
+}
+
+int32_t hdi_stats_get(int32_t id, int64_t *launches, double *total_ms, double *alg_bytes) {
+    if (id < 0 || id >= HDI_NUM_KERNEL_IDS) {
+        set_error("kernel id %d outside 0..%d", id, HDI_NUM_KERNEL_IDS - 1);
+        return HDI_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    if (launches) *launches = g_stats[id].launches;
+    if (total_ms) *total_ms = g_stats[id].ms;
+    if (alg_bytes) *alg_bytes = g_stats[id].bytes;
+    return HDI_OK;
+}
+
+const char *hdi_status_string(int32_t s) {
+    switch (s) {
+        case HDI_OK: return "ok";
+        case HDI_ERR_ARG: return "invalid argument";
+        case HDI_ERR_EMPTY_MASK: return "empty mask";
+        case HDI_ERR_NO_CONVERGENCE: return "no convergence";
+        case HDI_ERR_WORKSPACE: return "workspace too small";
+        case HDI_ERR_HIP: return "HIP runtime error";
+        case HDI_ERR_BUDGET: return "exceeds memory budget";
+        default: return "unknown status";
+    }
+}
+
+const char *hdi_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

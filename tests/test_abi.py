@@ -1,0 +1,81 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and its host-only helpers follow the paper's conventions."""
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hdi.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def _lib():
+    from paper_2401_06747_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libhdi.so not built")
+    return _lib
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["inpaint_solve", "hdi_inpaint_workspace_bytes", "hdi_block_count", "hdi_status_string", "hdi_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib().lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+    # the binding wraps exactly what the header declares
+    assert sorted(_lib().exported_symbols()) == _declared()
+
+
+def test_block_count_matches_paper():
+    """Sec. 3.3: 32x32 blocks with overlap 6 give 36852 local problems for a 4K
+    colour image on the finest level (3 channels)."""
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_numbers.json")))["oras_local_problems_4k_rgb"]
+    from paper_2401_06747_amd import hdi_block_count
+    _lib()
+    n = hdi_block_count(g["width"], g["height"], g["overlap"]) * g["channels"]
+    assert n == g["value"]
+    assert hdi_block_count(32, 32, 6) == 1 and hdi_block_count(33, 1, 6) == 2
+
+
+def test_workspace_query_and_status_strings():
+    L = _lib()
+    lib = L.lib()
+    assert lib.hdi_inpaint_workspace_bytes(L.hdi_image(0, 5, 1)) == 0
+    assert lib.hdi_inpaint_workspace_bytes(L.hdi_image(5, 5, 2)) == 0
+    small = lib.hdi_inpaint_workspace_bytes(L.hdi_image(64, 64, 1))
+    big = lib.hdi_inpaint_workspace_bytes(L.hdi_image(3840, 2160, 3))
+    assert 0 < small < big
+    # FP32 buffers dominate: 3 per level and channel plus the coarse pyramid
+    assert big < 3840 * 2160 * 3 * 4 * 3 * 1.5 + 2 ** 24
+    assert lib.hdi_status_string(2) == b"empty mask"
+
+
+def test_argument_errors_need_no_gpu():
+    """Bad shapes and null pointers are rejected before any HIP call."""
+    import ctypes
+    L = _lib()
+    lib = L.lib()
+    rep = L.hdi_solve_report()
+    st = lib.inpaint_solve(L.hdi_image(4, 4, 2), None, None, None, None, None, 0, None, ctypes.byref(rep), None)
+    assert st == L.HDI_ERR_ARG
+    st = lib.inpaint_solve(L.hdi_image(4, 4, 1), None, None, None, None, None, 0, None, ctypes.byref(rep), None)
+    assert st == L.HDI_ERR_ARG and b"non-null" in lib.hdi_last_error()
+    p = L.hdi_solve_params(0.0, 0, 3, 0, 0, 0)   # odd overlap
+    st = lib.inpaint_solve(L.hdi_image(4, 4, 1), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                           None, None, 0, ctypes.byref(p), ctypes.byref(rep), None)
+    assert st == L.HDI_ERR_ARG
+    st = lib.inpaint_solve(L.hdi_image(4, 4, 1), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                           None, None, 0, None, ctypes.byref(rep), None)
+    assert st == L.HDI_ERR_WORKSPACE

@@ -1,0 +1,151 @@
+"""GPU parity of inpaint_solve (through the C ABI) against the FP64 oracle.
+
+Bar: relative L2 error <= 1e-5 per channel against the oracle's solution, the
+FP64 relative residual (computed by the oracle's own matrix) <= the requested
+tolerance, and the known pixels copied exactly (Sec. 2.1, eq. inp-discrete-lsi)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2401_06747_amd as hdi
+from oracle import inpaint as oi
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL_ERR = 1e-5
+
+
+def _run(f, m, **kw):
+    ft = torch.tensor(f, dtype=torch.float32, device=DEV).contiguous()
+    mt = torch.tensor(m, dtype=torch.uint8, device=DEV).contiguous()
+    u, rep = hdi.inpaint_solve(ft, mt, params=hdi.SolveParams(**kw) if kw else None)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), rep
+
+
+def _check(f, m, u, rep, tol=1e-6):
+    f = np.asarray(f, np.float64)
+    assert rep["status"] == 0, rep
+    ref = oi.inpaint(f, m)
+    err = oi.rel_l2(u, ref)
+    rr = oi.relres(u, f, m)
+    K = m != 0
+    for c in range(f.shape[0]):
+        assert np.array_equal(u[c][K], f[c][K].astype(np.float32).astype(np.float64))
+    assert rr.max() <= tol * 1.0001, (rr, rep)
+    assert err.max() <= TOL_ERR, (err, rr, rep)
+    return err, rr
+
+
+def _rand(seed, C, H, W, p):
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0, 255, (C, H, W)).astype(np.float32).astype(np.float64)
+    m = (rng.random((H, W)) < p).astype(np.uint8)
+    if m.sum() == 0:
+        m[H // 2, W // 2] = 1
+    return f, m
+
+
+def test_config1_gray_256():
+    inst = synth.config1()
+    u, rep = _run(inst.f, inst.mask)
+    err, rr = _check(inst.f, inst.mask, u, rep)
+    print("config1", err, rr, rep)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 50), (1, 40, 1), (1, 2, 2), (1, 3, 5), (3, 31, 33), (1, 33, 31),
+                                   (1, 64, 65), (3, 97, 130), (1, 1, 1)])
+def test_small_and_ragged_shapes(shape):
+    C, H, W = shape
+    f, m = _rand(sum(shape), C, H, W, 0.08)
+    u, rep = _run(f, m)
+    _check(f, m, u, rep)
+
+
+def test_textured_rgb_fs_mask_several_levels():
+    inst = synth.config2(270, 480, 3, 0.03)
+    u, rep = _run(inst.f, inst.mask)
+    err, rr = _check(inst.f, inst.mask, u, rep)
+    print("textured 480x270 RGB", err, rr, rep)
+
+
+def test_sparse_mask_big_holes():
+    inst = synth.config2(300, 500, 1, 0.005, item=3)
+    u, rep = _run(inst.f, inst.mask)
+    _check(inst.f, inst.mask, u, rep)
+
+
+def test_cold_start_without_fmg_and_overlap_6():
+    inst = synth.config2(200, 330, 3, 0.05, item=4)
+    u, rep = _run(inst.f, inst.mask, flags=1, overlap=6)
+    _check(inst.f, inst.mask, u, rep)
+
+
+def test_single_pixel_and_full_mask():
+    f, _ = _rand(5, 1, 40, 70, 0.0)
+    m = np.zeros((40, 70), np.uint8)
+    m[7, 50] = 1
+    u, rep = _run(f, m)
+    assert rep["status"] == 0
+    np.testing.assert_allclose(u[0], np.float32(f[0, 7, 50]), rtol=2e-6)
+    u, rep = _run(f, np.ones((40, 70), np.uint8))
+    assert rep["status"] == 0 and np.array_equal(u[0], f[0])
+
+
+def test_empty_mask_is_an_error():
+    f, _ = _rand(6, 1, 16, 16, 0.0)
+    with pytest.raises(hdi.HdiError) as ei:
+        _run(f, np.zeros((16, 16), np.uint8))
+    assert ei.value.status == 2
+
+
+def test_no_convergence_reports_last_iterate():
+    inst = synth.config2(128, 160, 1, 0.03, item=5)
+    u, rep = _run(inst.f, inst.mask, max_outer=1, flags=1)
+    assert rep["status"] == 3 and rep["outer_iters"] == 1
+    assert np.isfinite(u).all()
+
+
+def test_warm_start_from_solution_needs_no_round_and_is_deterministic():
+    inst = synth.config2(150, 260, 3, 0.03, item=6)
+    ft = torch.tensor(inst.f, dtype=torch.float32, device=DEV)
+    mt = torch.tensor(inst.mask, device=DEV)
+    u1, r1 = hdi.inpaint_solve(ft, mt)
+    u2, r2 = hdi.inpaint_solve(ft, mt)
+    assert torch.equal(u1, u2)
+    u3, r3 = hdi.inpaint_solve(ft, mt, u0=u1)
+    assert r3["outer_iters"] == 0 and torch.equal(u3, u1)
+
+
+def test_4k_rgb_full_size_properties():
+    """The benchmark's workload at full size: the oracle's FP64 residual of the
+    GPU solution meets 1e-6 per channel, known pixels are exact and the
+    min-max principle holds."""
+    inst = synth.config2()
+    u, rep = _run(inst.f, inst.mask)
+    assert rep["status"] == 0
+    rr = oi.relres(u, inst.f, inst.mask)
+    assert rr.max() <= 1e-6 * 1.0001, rr
+    K = inst.mask != 0
+    for c in range(3):
+        assert np.array_equal(u[c][K], inst.f[c][K])
+        assert u[c].min() >= inst.f[c][K].min() - 1e-3 and u[c].max() <= inst.f[c][K].max() + 1e-3
+    print("4k", rr, rep)
+
+
+def test_poisoned_workspace_gives_identical_results():
+    """Every workspace byte the solve reads was written by the solve itself: a
+    workspace filled with NaN bit patterns changes nothing (regression test for
+    the reduced-FMG smoothing step, whose right-hand side is zero)."""
+    inst = synth.config2(97, 130, 3, 0.08, item=9)
+    ft = torch.tensor(inst.f, dtype=torch.float32, device=DEV)
+    mt = torch.tensor(inst.mask, device=DEV)
+    from paper_2401_06747_amd import _lib
+    n = _lib.lib().hdi_inpaint_workspace_bytes(_lib.hdi_image(130, 97, 3))
+    ws0 = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    ws1 = torch.full((n,), 0xFF, dtype=torch.uint8, device=DEV)
+    u0, r0 = hdi.inpaint_solve(ft, mt, ws=ws0)
+    u1, r1 = hdi.inpaint_solve(ft, mt, ws=ws1)
+    assert r0["status"] == 0 and r1["status"] == 0
+    assert torch.equal(u0, u1)
