@@ -34,6 +34,24 @@ def kernel_stats(L):
     return out
 
 
+def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: a plain device-to-device copy of 1 GiB (read
+    1 GiB + write 1 GiB per launch), timed with events on the current stream.
+    Its FETCH_SIZE/WRITE_SIZE under rocprofv3 also calibrate the counters."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_per_launch": 2 * nbytes, "avg_us": round(ms * 1e3, 1), "GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(inst, crop=(540, 960)):
     """Oracle (SuperLU, FP64) on a bounded crop of the same image and mask, one
     channel; scaled to 4K RGB solves/s by pixel count (linear scaling, which
@@ -59,6 +77,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
@@ -119,6 +138,10 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom,
                 "avg_us": round(ms / n * 1e3, 2), "alg_bytes_per_launch": round(by / n)}
+    copy = None
+    if not args.no_copy_calibration:
+        copy = copy_calibration(torch, dev)
+        log(f"copy calibration: {copy}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst)
@@ -130,7 +153,7 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "inpaint_solve 3840x2160x3, 3% FS-gradient mask, FP64 rel-res 1e-6, plain form",
                    "known_pixels": int(inst.mask.sum()), "rounds": reps[-1]["outer_iters"]},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "copy_calibration": copy,
     }
     print(json.dumps(out), flush=True)
 

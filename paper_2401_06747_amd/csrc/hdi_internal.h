@@ -63,7 +63,11 @@ struct Hierarchy {
     Level lev[MAX_LEVELS];
     double *partials;   // [C][nblk][2] block partial sums of the residual kernel
     double *norms;      // [C][2] (||r||^2, ||b||^2)
+    double *u_alt;      // C x H x W FP64 second iterate buffer (fused refinement step)
+    unsigned int *counts;  // [MAX_LEVELS] known pixels per level
     int nblk;           // blocks of the residual kernel
+    int nlev_full;      // levels down to one block
+    unsigned int known[MAX_LEVELS];  // host copy of counts
 };
 
 // Lay out the hierarchy in the arena (base == nullptr: size query only).
@@ -89,12 +93,13 @@ struct Prof {
 Prof *prof_for_call();   // nullptr when timing is off
 
 // Kernel launchers (solver_kernels.hip).
-void launch_mask_restrict(const Level &fine, const Level &coarse, hipStream_t s);
+
 template <typename TD>
 void launch_init_u(int W, int H, int C, const uint8_t *mask, const TD *data, const double *u0, double *u, hipStream_t s);
+dim3 residual_grid(int W, int H);
 template <typename TD>
-void launch_residual(int W, int H, int C, const uint8_t *mask, const double *u, const TD *data,
-                     const double *src, float *r, double *partials, int nblk, double *norms, hipStream_t s);
+void launch_residual(int W, int H, int C, const uint8_t *mask, const double *u_in, const float *e, double *u_out,
+                     const TD *data, const double *src, float *r, double *partials, double *norms, hipStream_t s);
 void launch_update(int W, int H, int C, const uint8_t *mask, const float *e, double *u, hipStream_t s);
 void launch_smooth_pre(const Level &L, int C, int iters, float *e_out, hipStream_t s);
 void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, const float *e_in,
@@ -107,6 +112,13 @@ void launch_data_restrict(const Level &L, const Level &Lc, int C, hipStream_t s)
 void launch_fmg_prolong(const Level &L, const Level &Lc, int C, const float *ec, float *out, hipStream_t s);
 void launch_fmg_prolong0(int W, int H, int C, const uint8_t *mask, const Level &Lc, const float *ec, double *u, hipStream_t s);
 void launch_smooth_fmg(const Level &L, int C, int iters, const float *e_in, float *e_out, hipStream_t s);
+
+// Build the coarse masks of levels 1..nlev-1 and count known pixels per level
+// into counts[0..nlev) (counts must hold MAX_LEVELS entries).
+void launch_mask_pyramid(const Hierarchy &h, int nlev, unsigned int *counts, hipStream_t s);
+
+// Coarse masks, known counts and the number of levels for a new mask.
+int32_t prepare_mask(Hierarchy &h, hipStream_t s);
 
 // Host driver: solve A x = C data + (I - C) src on the caller's buffers.
 template <typename TD>

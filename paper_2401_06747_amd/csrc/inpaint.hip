@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <vector>
@@ -100,8 +101,11 @@ bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, co
         w = (w + 1) / 2;
         hh = (hh + 1) / 2;
     }
-    h.nlev = l;
-    h.nblk = (int)(((size_t)W * H + RED_THREADS - 1) / RED_THREADS);
+    h.nlev = h.nlev_full = l;
+    h.counts = (unsigned int *)a.take(MAX_LEVELS * sizeof(unsigned int));
+    const dim3 g = residual_grid(W, H);
+    h.nblk = (int)(g.x * g.y);
+    h.u_alt = (double *)a.take((size_t)W * H * C * sizeof(double));
     h.partials = (double *)a.take((size_t)C * h.nblk * 2 * sizeof(double));
     h.norms = (double *)a.take((size_t)C * 2 * sizeof(double));
     return a.base == nullptr || a.used <= a.size;
@@ -157,8 +161,8 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipEventRecord(ev0, s));
     const double N = (double)W * H, nK = (double)cfg.known, nU = N - nK;
+    (void)nU;
     if (prof) prof->begin(5, 0.0, s);
-    for (int l = 1; l < h.nlev; ++l) launch_mask_restrict(h.lev[l - 1], h.lev[l], s);
     launch_init_u<TD>(W, H, C, mask, data, warm ? u : nullptr, u, s);
     if (!warm && !(cfg.flags & HDI_FLAG_NO_FMG) && src == nullptr && h.nlev > 1)
         fmg_init<TD>(h, W, H, C, mask, data, u, cfg, s);
@@ -169,11 +173,18 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     int rounds = 0, vcycles = 0;
     double rel[3] = {0, 0, 0};
     double norms[6];
-    const double res_bytes = N * (1 + 12.0 * C) + C * nK * sizeof(TD) + (src ? 8.0 * C * nU : 0.0);
+    // The refinement step u += e is fused into the next residual pass, which
+    // reads the iterate with a halo, so the iterate alternates between the
+    // caller's u and the workspace copy.
+    double *cur = u, *oth = h.u_alt;
+    const float *e = nullptr;
     for (;;) {
+        const double res_bytes = N * (1 + 12.0 * C) + C * nK * sizeof(TD) + (src ? 8.0 * C * nU : 0.0) +
+                                 (e ? 12.0 * C * N : 0.0);
         if (prof) prof->begin(0, res_bytes, s);
-        launch_residual<TD>(W, H, C, mask, u, data, src, h.lev[0].r, h.partials, h.nblk, h.norms, s);
+        launch_residual<TD>(W, H, C, mask, cur, e, e ? oth : nullptr, data, src, h.lev[0].r, h.partials, h.norms, s);
         if (prof) prof->end(s);
+        if (e) std::swap(cur, oth);
         HIP_TRY(hipMemcpyAsync(norms, h.norms, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         double worst = 0.0;
@@ -195,13 +206,11 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
             status = HDI_ERR_NO_CONVERGENCE;
             break;
         }
-        const float *e = vcycle(h, 0, cfg, s, prof);
-        if (prof) prof->begin(4, N + 20.0 * C * nU, s);
-        launch_update(W, H, C, mask, e, u, s);
-        if (prof) prof->end(s);
+        e = vcycle(h, 0, cfg, s, prof);
         ++rounds;
         ++vcycles;
     }
+    if (cur != u) HIP_TRY(hipMemcpyAsync(u, cur, sizeof(double) * C * W * H, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(ev1, s));
     HIP_TRY(hipEventSynchronize(ev1));
@@ -256,24 +265,28 @@ int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap) {
     return HDI_OK;
 }
 
-__global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
-
-// Count known pixels (device), so that an empty mask is rejected (Sec. 2.1).
-__global__ void k_count_mask(int N, const uint8_t *__restrict__ m, unsigned int *__restrict__ cnt) {
-    unsigned int local = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) local += m[i] != 0;
-    for (int o = 32; o >= 1; o >>= 1) local += __shfl_xor(local, o, 64);
-    if ((threadIdx.x & 63) == 0 && local) atomicAdd(cnt, local);
-}
-
-int32_t count_mask(const uint8_t *mask, int N, unsigned int *dev_counter, unsigned int *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, dev_counter);
-    int blocks = (N + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_count_mask, dim3(blocks), dim3(256), 0, s, N, mask, dev_counter);
+// Coarse masks and per-level known counts for a new mask (one readback). Picks
+// the number of levels used: coarsening stops at the first level whose mask is
+// at least 99% known (with the "any of four" rule coarse masks fill up fast, and
+// a smoothing step with local CG is then an almost exact solve there), and in
+// any case at the level that is a single 32x32 block (Sec. 3.3).
+int32_t prepare_mask(Hierarchy &h, hipStream_t s) {
+    launch_mask_pyramid(h, h.nlev_full, h.counts, s);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(out, dev_counter, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h.known, h.counts, sizeof(unsigned int) * MAX_LEVELS, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (h.known[0] == 0) {
+        set_error("empty mask: the inpainting matrix is singular");
+        return HDI_ERR_EMPTY_MASK;
+    }
+    h.nlev = h.nlev_full;
+    for (int l = 1; l < h.nlev_full; ++l) {
+        const double n = (double)h.lev[l].W * h.lev[l].H;
+        if (n - (double)h.known[l] <= 0.01 * n) {
+            h.nlev = l + 1;
+            break;
+        }
+    }
     return HDI_OK;
 }
 
@@ -281,7 +294,6 @@ size_t inpaint_ws_bytes(int W, int H, int C) {
     Hierarchy h;
     Arena a{nullptr, 0, 0};
     plan_hierarchy(h, a, W, H, C, 4, nullptr);
-    a.take(sizeof(unsigned int));
     return a.used + 256;
 }
 
@@ -316,14 +328,8 @@ int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double
     Arena a{(char *)ws, ws_bytes, 0};
     Hierarchy h;
     plan_hierarchy(h, a, img.width, img.height, img.channels, overlap, mask);
-    unsigned int *counter = (unsigned int *)a.take(sizeof(unsigned int));
-    unsigned int known = 0;
-    st = count_mask(mask, img.width * img.height, counter, &known, s);
+    st = prepare_mask(h, s);
     if (st) return st;
-    if (known == 0) {
-        set_error("empty mask: the inpainting matrix is singular");
-        return HDI_ERR_EMPTY_MASK;
-    }
     const int C = img.channels;
     if (u0 && u0 != u) {
         hipError_t e = hipMemcpyAsync(u, u0, sizeof(double) * C * img.width * img.height, hipMemcpyDeviceToDevice, s);
@@ -332,7 +338,7 @@ int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double
             return HDI_ERR_HIP;
         }
     }
-    cfg.known = known;
+    cfg.known = h.known[0];
     Prof *prof = prof_for_call();
     st = solve_system<float>(h, img.width, img.height, C, mask, f, nullptr, u, u0 != nullptr, cfg, report, s, prof);
     delete prof;

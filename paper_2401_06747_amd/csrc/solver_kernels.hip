@@ -5,6 +5,9 @@
 //   (A v)_p = v_p if p is known, (L v)_p otherwise                 (eq. inp-discrete-lsi)
 // The correction equation A e = r with r = 0 on known pixels pins e = 0 there,
 // so every FP32 kernel below works on the unknown pixels only.
+#include <algorithm>
+#include <cfloat>
+
 #include "hdi_internal.h"
 
 namespace hdi {
@@ -15,17 +18,44 @@ __device__ __forceinline__ int deg_of(int x, int y, int W, int H) {
     return (x > 0) + (x < W - 1) + (y > 0) + (y < H - 1);
 }
 
-// Sum over the 64 lanes of a wavefront. XOR butterfly: every lane ends with the
-// same bits (each step adds the same two operands in either order).
+// Sum over the 64 lanes of a wavefront with DPP lane moves (no LDS traffic):
+// pairs and quads, then shifts by 4 and 8 inside each row of 16, then the
+// row broadcasts of lane 15 and lane 31. Lane 63 ends with the total; its value
+// is broadcast, so every lane returns the same bits and the order of the
+// additions is fixed (deterministic).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(x)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double x) {
+    const int lo = dpp_i<CTRL, ROWS>(__double2loint(x));
+    const int hi = dpp_i<CTRL, ROWS>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_f<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v += dpp_d<0xB1, 0xF>(v);
+    v += dpp_d<0x4E, 0xF>(v);
+    v += dpp_d<0x114, 0xF>(v);
+    v += dpp_d<0x118, 0xF>(v);
+    v += dpp_d<0x142, 0xA>(v);
+    v += dpp_d<0x143, 0xC>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Map the hardware workgroup id to a block index so that each of the 8 XCDs
@@ -52,74 +82,159 @@ __global__ void k_init_u(int N, int C, const uint8_t *__restrict__ mask, const T
     }
 }
 
-// r = b - A u in FP64 (b = data on known pixels, src (or 0) elsewhere), stored
-// as FP32 for the inner solve, plus per-block FP64 partial sums of r^2 and b^2.
-// One thread per pixel serves all channels, so the mask is read once (Sec. 2.1:
-// the colour channels share the matrix).
-template <typename TD>
+// Fused refinement step and FP64 residual. With e != nullptr the iterate is
+// first advanced, u_out = u_in + e (e is exactly 0 on known pixels, so known
+// values stay bit-exact), and the residual is taken at u_out; u_out must not
+// alias u_in because neighbours read u_in. Then r = b - A u in FP64 with
+// b = data on known pixels and src (or 0) elsewhere, stored as FP32 for the
+// inner solve, plus per-workgroup FP64 partial sums of r^2 and b^2 per channel.
+//
+// Access pattern: each wave owns 62 columns (its 64 lanes minus one halo lane
+// on each side) and sweeps RES_BAND rows downwards, keeping the rows y-1, y,
+// y+1 of every channel in registers and prefetching row y+2, so each element
+// is read from memory once (plus two halo rows per band). Left and right
+// neighbours come from the adjacent lanes by whole-wave DPP shifts. One thread
+// serves all channels, so the mask is read once (Sec. 2.1: the colour channels
+// share the matrix).
+constexpr int RES_BAND = 32;
+constexpr int RES_COLS = 62;
+
+__device__ __forceinline__ double wave_from_left(double v) {   // value of lane - 1
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_from_right(double v) {  // value of lane + 1
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <typename TD, int C>
 __global__ void __launch_bounds__(RED_THREADS)
-k_residual(int W, int H, int C, const uint8_t *__restrict__ mask, const double *__restrict__ u,
-           const TD *__restrict__ data, const double *__restrict__ src, float *__restrict__ r,
-           double *__restrict__ partials, int nblk) {
+k_residual(int W, int H, const uint8_t *__restrict__ mask, const double *__restrict__ u_in,
+           const float *__restrict__ e, double *__restrict__ u_out, const TD *__restrict__ data,
+           const double *__restrict__ src, float *__restrict__ r, double *__restrict__ partials, int nblk) {
     const int N = W * H;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    __shared__ double s_red[RED_THREADS / 64][2];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int x = (blockIdx.x * (RED_THREADS / 64) + wid) * RES_COLS + lane - 1;
+    const int xs = min(max(x, 0), W - 1);
+    const bool owner = lane >= 1 && lane <= RES_COLS && x < W;
+    const double wl = x > 0, wr = x < W - 1;
+    const int y0 = blockIdx.y * RES_BAND, y1 = min(y0 + RES_BAND, H);
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+
+    // Rows of u (+ e) at column xs: prev (y-1), cur (y), next (y+1), and the
+    // prefetched y+2; mask rows y and y+1; data/src of row y. Loads are issued
+    // one or two rows ahead, and everything row y needs was issued in an
+    // earlier iteration, so the in-order memory counter never makes the wave
+    // wait for its own prefetch.
+    auto fetch = [&](int c, int y, double &uv, float &ev) {
+        const int yc = min(max(y, 0), H - 1);
+        const size_t j = (size_t)c * N + (size_t)yc * W + xs;
+        uv = u_in[j];
+        ev = e ? e[j] : 0.f;
+    };
+    auto fetch_mask = [&](int y) -> int { return mask[(size_t)min(y, H - 1) * W + xs]; };
+    // right-hand side of row y (data on known pixels, src elsewhere), loaded
+    // without a per-pixel branch and selected at use, so no load of a later
+    // row has to complete before row y is computed
+    auto fetch_b = [&](int y, TD *dk, double *sv) {
+        const size_t i = (size_t)min(y, H - 1) * W + xs;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            dk[c] = data ? data[(size_t)c * N + i] : TD(0);
+            sv[c] = src ? src[(size_t)c * N + i] : 0.0;
+        }
+    };
+    double pu[C], cu[C], nu[C], qu[C];
+    float pe[C], ce[C], ne[C], qe[C];
+    TD dcur[C], dnxt[C];
+    double scur[C], snxt[C];
+#pragma unroll
     for (int c = 0; c < C; ++c) {
-        double rr = 0.0, bb = 0.0;
-        if (i < N) {
-            const int x = i % W, y = i / W;
+        fetch(c, y0 - 1, pu[c], pe[c]);
+        fetch(c, y0, cu[c], ce[c]);
+        fetch(c, y0 + 1, nu[c], ne[c]);
+    }
+    int mcur = fetch_mask(y0), mnxt = fetch_mask(y0 + 1);
+    fetch_b(y0, dcur, scur);
+    double rr[C], bb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) rr[c] = bb[c] = 0.0;
+    for (int y = y0; y < y1; ++y) {
+        // issue the loads for later rows first
+#pragma unroll
+        for (int c = 0; c < C; ++c) fetch(c, y + 2, qu[c], qe[c]);
+        const int mq = fetch_mask(y + 2);
+        fetch_b(y + 1, dnxt, snxt);
+        // then compute row y from registers
+        const size_t i = (size_t)y * W + xs;
+        const bool known = mcur != 0;
+        const double wu = y > 0, wd = y < H - 1;
+        const double dgv = wl + wr + wu + wd;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
             const size_t o = (size_t)c * N;
-            const double *uc = u + o;
-            double res, b;
-            if (mask[i]) {
-                b = data ? (double)data[o + i] : 0.0;
-                res = b - uc[i];
-            } else {
-                b = src ? src[o + i] : 0.0;
-                double s = 0.0;
-                int d = 0;
-                if (x > 0) { s += uc[i - 1]; ++d; }
-                if (x < W - 1) { s += uc[i + 1]; ++d; }
-                if (y > 0) { s += uc[i - W]; ++d; }
-                if (y < H - 1) { s += uc[i + W]; ++d; }
-                res = b - (d * uc[i] - s);
+            const double u0 = cu[c] + (double)ce[c];
+            const double ul = wave_from_left(u0), ur = wave_from_right(u0);
+            const double uu = pu[c] + (double)pe[c], ud = nu[c] + (double)ne[c];
+            const double au = dgv * u0 - (wl * ul + wr * ur + wu * uu + wd * ud);
+            const double b = known ? (double)dcur[c] : scur[c];
+            const double res = known ? b - u0 : b - au;
+            if (owner) {
+                if (e) u_out[o + i] = u0;
+                r[o + i] = (float)res;
+                rr[c] += res * res;
+                bb[c] += b * b;
             }
-            r[o + i] = (float)res;
-            rr = res * res;
-            bb = b * b;
+            pu[c] = cu[c]; pe[c] = ce[c];
+            cu[c] = nu[c]; ce[c] = ne[c];
+            nu[c] = qu[c]; ne[c] = qe[c];
+            dcur[c] = dnxt[c];
+            scur[c] = snxt[c];
         }
-        rr = wave_sum_d(rr);
-        bb = wave_sum_d(bb);
-        const int wid = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) { s_red[wid][0] = rr; s_red[wid][1] = bb; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double a = 0.0, bsum = 0.0;
-            for (int w = 0; w < RED_THREADS / 64; ++w) { a += s_red[w][0]; bsum += s_red[w][1]; }
-            partials[((size_t)c * nblk + blockIdx.x) * 2 + 0] = a;
-            partials[((size_t)c * nblk + blockIdx.x) * 2 + 1] = bsum;
-        }
-        __syncthreads();
+        mcur = mnxt;
+        mnxt = mq;
+    }
+    __shared__ double s_red[RED_THREADS / 64][2 * C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double a = wave_sum_d(rr[c]);
+        const double b = wave_sum_d(bb[c]);
+        if (lane == 0) { s_red[wid][2 * c] = a; s_red[wid][2 * c + 1] = b; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * C) {
+        double acc = 0.0;
+        for (int w = 0; w < RED_THREADS / 64; ++w) acc += s_red[w][threadIdx.x];
+        const int c = threadIdx.x >> 1;
+        partials[((size_t)c * nblk + bid) * 2 + (threadIdx.x & 1)] = acc;
     }
 }
 
-// Second stage of the fixed-order reduction: one workgroup per channel.
-__global__ void __launch_bounds__(RED_THREADS)
+// Second stage of the fixed-order reduction: one workgroup of 1024 threads per
+// channel; thread t sums partials t, t+1024, ... in order, then waves and the
+// 16 wave sums are combined in a fixed order.
+__global__ void __launch_bounds__(1024)
 k_reduce_partials(int nblk, const double *__restrict__ partials, double *__restrict__ norms) {
     const int c = blockIdx.x;
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += RED_THREADS) {
-        a += partials[((size_t)c * nblk + k) * 2 + 0];
-        b += partials[((size_t)c * nblk + k) * 2 + 1];
+    const double2 *pp = reinterpret_cast<const double2 *>(partials) + (size_t)c * nblk;
+#pragma unroll 4
+    for (int k = threadIdx.x; k < nblk; k += 1024) {
+        const double2 v = pp[k];
+        a += v.x;
+        b += v.y;
     }
     a = wave_sum_d(a);
     b = wave_sum_d(b);
-    __shared__ double s[RED_THREADS / 64][2];
+    __shared__ double s[16][2];
     if ((threadIdx.x & 63) == 0) { s[threadIdx.x >> 6][0] = a; s[threadIdx.x >> 6][1] = b; }
     __syncthreads();
     if (threadIdx.x == 0) {
         double x = 0.0, y = 0.0;
-        for (int w = 0; w < RED_THREADS / 64; ++w) { x += s[w][0]; y += s[w][1]; }
+        for (int w = 0; w < 16; ++w) { x += s[w][0]; y += s[w][1]; }
         norms[c * 2 + 0] = x;
         norms[c * 2 + 1] = y;
     }
@@ -135,20 +250,51 @@ __global__ void k_update(int N, int C, const uint8_t *__restrict__ mask, const f
 
 // ------------------------------------------------------------------ grid transfers
 
+// Workgroup total of a per-thread count, added with one atomic per workgroup
+// (integer atomics: exact and order independent).
+__device__ __forceinline__ void block_count_add(unsigned int local, unsigned int *count) {
+    __shared__ unsigned int s_cnt[4];
+    for (int o = 32; o >= 1; o >>= 1) local += __shfl_xor(local, o, 64);
+    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int t = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        if (t) atomicAdd(count, t);
+    }
+}
+
 // Coarse mask: a coarse pixel is known if any of its (up to) four fine pixels
-// is known (Sec. 3.3).
-__global__ void k_mask_restrict(int W, int H, const uint8_t *__restrict__ m, int Wc, int Hc,
-                                uint8_t *__restrict__ mc) {
+// is known (Sec. 3.3). Also counts the known coarse pixels. Grid-stride loop
+// over coarse pixels, 256 threads per workgroup.
+__global__ void __launch_bounds__(256)
+k_mask_restrict(int W, int H, const uint8_t *__restrict__ m, int Wc, int Hc, uint8_t *__restrict__ mc,
+                unsigned int *__restrict__ count) {
+    unsigned int local = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Wc * Hc; i += gridDim.x * blockDim.x) {
+        const int X = i % Wc, Y = i / Wc;
+        uint8_t k = 0;
+        for (int j = 0; j < 2; ++j)
+            for (int q = 0; q < 2; ++q) {
+                const int x = 2 * X + q, y = 2 * Y + j;
+                if (x < W && y < H) k |= (m[y * W + x] != 0);
+            }
+        mc[i] = k;
+        local += k;
+    }
+    block_count_add(local, count);
+}
+
+// Known pixels of the finest mask.
+__global__ void __launch_bounds__(256)
+k_count_known(int N, const uint8_t *__restrict__ m, unsigned int *__restrict__ count) {
+    unsigned int local = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) local += m[i] != 0;
+    block_count_add(local, count);
+}
+
+__global__ void k_zero_u32(int n, unsigned int *p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Wc * Hc) return;
-    const int X = i % Wc, Y = i / Wc;
-    uint8_t k = 0;
-    for (int j = 0; j < 2; ++j)
-        for (int q = 0; q < 2; ++q) {
-            const int x = 2 * X + q, y = 2 * Y + j;
-            if (x < W && y < H) k |= (m[y * W + x] != 0);
-        }
-    mc[i] = k;
+    if (i < n) p[i] = 0u;
 }
 
 // Coarse right-hand side: sum over the unknown fine children of the fine
@@ -229,6 +375,7 @@ k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
     __shared__ __attribute__((aligned(16))) float s_p[TILE + 2][LDS_W];
     __shared__ __attribute__((aligned(16))) float s_e[TILE + 2][LDS_W];
     __shared__ uint8_t s_m[TILE + 2][TILE + 2];
+    __shared__ float s_c[20][20];   // coarse correction around the block (MODE 1)
 
     const int ntiles = ntx * nty;
     const int t = xcd_remap(blockIdx.x, ntiles);
@@ -240,25 +387,70 @@ k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
     const float *rc = r + (size_t)c * N;
     const int lane = threadIdx.x;
 
-    // Stage mask and (MODE 1/2) the current correction, with a 1-pixel halo.
-    // s_m: 0 unknown, 1 known, 2 outside the image.
-    for (int k = lane; k < (TILE + 2) * (TILE + 2); k += 64) {
-        const int ly = k / (TILE + 2), lx = k % (TILE + 2);
-        const int x = x0 + lx - 1, y = y0 + ly - 1;
-        const bool in = (x >= 0 && x < W && y >= 0 && y < H);
-        const int p = y * W + x;
-        const uint8_t mk = in ? (mask[p] != 0) : 2;
-        s_m[ly][lx] = mk;
-        if (MODE != 0) {
-            float v = 0.f;
-            if (in && (mk == 0 || MODE == 2)) {
-                v = e_in[(size_t)c * N + p];
-                if (MODE == 1) v += prolong_at(ec + (size_t)c * Wc * Hc, Wc, Hc, x, y);
-            }
-            s_e[ly][COL0 - 1 + lx] = v;
+    // MODE 1: stage the coarse correction around the block with clamped
+    // coordinates, so that the clamped bilinear lookup becomes plain indexing.
+    const int X0 = ((x0 - 1) >> 1) - 1, Y0 = ((y0 - 1) >> 1) - 1;
+    if (MODE == 1) {
+        const float *ecc = ec + (size_t)c * Wc * Hc;
+        for (int k = lane; k < 400; k += 64) {
+            const int j = k / 20, i = k % 20;
+            const int X = min(max(X0 + i, 0), Wc - 1), Y = min(max(Y0 + j, 0), Hc - 1);
+            s_c[j][i] = ecc[Y * Wc + X];
         }
-        // zero halo ring of the search-direction tile
-        s_p[ly][COL0 - 1 + lx] = 0.f;
+        __syncthreads();
+    }
+    // Stage mask, right-hand side and (MODE 1/2) the current correction for the
+    // block and a 1-pixel halo, in coalesced rows of 34. Addresses are clamped
+    // into the image so that no load sits behind a branch: all loads of a lane
+    // are in flight before the first is used. s_m: 0 unknown, 1 known,
+    // 2 outside the image. The right-hand side goes to the interior of s_p
+    // (free until the CG starts) and the ring of s_p is zeroed (Dirichlet
+    // values outside the block). In MODE 1, e_in is exactly 0 on known pixels;
+    // in MODE 2 it holds the data there.
+    constexpr int NST = (TILE + 2) * (TILE + 2);
+    constexpr int NIT = (NST + 63) / 64;     // 19 rounds of 64 lanes
+    constexpr int HALF = (NIT + 1) / 2;      // staged in two batches to bound register use
+#pragma unroll
+    for (int batch = 0; batch < 2; ++batch) {
+        int mraw[HALF];
+        float ev[HALF], rv[HALF];
+#pragma unroll
+        for (int h = 0; h < HALF; ++h) {
+            const int k = lane + 64 * (batch * HALF + h);
+            const int ly = k / (TILE + 2), lx = k % (TILE + 2);
+            const int xc = min(max(x0 + lx - 1, 0), W - 1), yc = min(max(y0 + ly - 1, 0), H - 1);
+            const int pc = yc * W + xc;
+            mraw[h] = mask[pc];
+            ev[h] = MODE != 0 ? e_in[(size_t)c * N + pc] : 0.f;
+            rv[h] = r ? rc[pc] : 0.f;
+        }
+#pragma unroll
+        for (int h = 0; h < HALF; ++h) {
+            const int k = lane + 64 * (batch * HALF + h);
+            if (k < NST) {
+                const int ly = k / (TILE + 2), lx = k % (TILE + 2);
+                const int x = x0 + lx - 1, y = y0 + ly - 1;
+                const bool in = x >= 0 && x < W && y >= 0 && y < H;
+                const int mk = in ? (mraw[h] != 0) : 2;
+                s_m[ly][lx] = (uint8_t)mk;
+                if (MODE != 0) {
+                    float v = in ? ev[h] : 0.f;
+                    if (MODE == 1) {
+                        if (mk == 0) {
+                            // cell-centred bilinear: 3/4 parent, 1/4 next cell on each side of x and y
+                            const int X = (x >> 1) - X0, Y = (y >> 1) - Y0;
+                            const int Xn = (x & 1) ? X + 1 : X - 1, Yn = (y & 1) ? Y + 1 : Y - 1;
+                            v += 0.5625f * s_c[Y][X] + 0.1875f * (s_c[Y][Xn] + s_c[Yn][X]) + 0.0625f * s_c[Yn][Xn];
+                        } else {
+                            v = 0.f;
+                        }
+                    }
+                    s_e[ly][COL0 - 1 + lx] = v;
+                }
+                const bool interior = lx >= 1 && lx <= TILE && ly >= 1 && ly <= TILE;
+                s_p[ly][COL0 - 1 + lx] = interior ? rv[h] : 0.f;
+            }
+        }
     }
     __syncthreads();
 
@@ -266,7 +458,9 @@ k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
     float v[16], rl[16], p[16], dg[16];
     float rr = 0.f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+        const float4 r4 = *reinterpret_cast<const float4 *>(&s_p[4 * by + j + 1][COL0 + 4 * bx]);
+        const float rj[4] = {r4.x, r4.y, r4.z, r4.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int lx = 4 * bx + i, ly = 4 * by + j, k = j * 4 + i;
@@ -274,11 +468,11 @@ k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
             float res = 0.f, d = 0.f;
             if (lx < Tx && ly < Ty && s_m[ly + 1][lx + 1] == 0) {
                 d = (float)deg_of(x, y, W, H);
-                res = r ? rc[y * W + x] : 0.f;
+                res = rj[i];
                 if (MODE != 0) {
-                    const float s = s_e[ly][COL0 + lx] + s_e[ly + 2][COL0 + lx] +
-                                    s_e[ly + 1][COL0 + lx - 1] + s_e[ly + 1][COL0 + lx + 1];
-                    res -= d * s_e[ly + 1][COL0 + lx] - s;
+                    const float sn = s_e[ly][COL0 + lx] + s_e[ly + 2][COL0 + lx] +
+                                     s_e[ly + 1][COL0 + lx - 1] + s_e[ly + 1][COL0 + lx + 1];
+                    res -= d * s_e[ly + 1][COL0 + lx] - sn;
                 }
             }
             dg[k] = d;
@@ -287,9 +481,15 @@ k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
             p[k] = res;
             rr += res * res;
         }
+    }
+    __syncthreads();   // every lane has read its right-hand side before p overwrites s_p
     rr = wave_sum(rr);
+    // Local CG stops after `iters` steps or once the block residual has fallen
+    // to the FP32 rounding floor (squared norm 1e-14 of the start); the
+    // reciprocal below also needs a normal (not denormal) divisor.
+    const float rr_floor = rr * 1e-14f;
 
-    for (int it = 0; it < iters && rr > 0.f; ++it) {
+    for (int it = 0; it < iters && rr > rr_floor && rr >= FLT_MIN; ++it) {
         // publish p
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -320,8 +520,8 @@ k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
                 pq += p[k] * q[k];
             }
         pq = wave_sum(pq);
-        if (!(pq > 0.f)) break;
-        const float alpha = rr / pq;
+        if (!(pq >= FLT_MIN)) break;
+        const float alpha = rr * __builtin_amdgcn_rcpf(pq);
         float rr2 = 0.f;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -330,7 +530,7 @@ k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
             rr2 += rl[k] * rl[k];
         }
         rr2 = wave_sum(rr2);
-        const float beta = rr2 / rr;
+        const float beta = rr2 * __builtin_amdgcn_rcpf(rr);
         rr = rr2;
 #pragma unroll
         for (int k = 0; k < 16; ++k) p[k] = rl[k] + beta * p[k];
@@ -405,8 +605,16 @@ __global__ void k_fmg_prolong0(int W, int H, int C, const uint8_t *__restrict__ 
 
 static inline dim3 grid1(long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
-void launch_mask_restrict(const Level &f, const Level &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_mask_restrict, grid1((long)c.W * c.H, 256), dim3(256), 0, s, f.W, f.H, f.mask, c.W, c.H, c.mask);
+void launch_mask_pyramid(const Hierarchy &h, int nlev, unsigned int *counts, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, MAX_LEVELS, counts);
+    const long N = (long)h.lev[0].W * h.lev[0].H;
+    auto nb = [](long n) { return (int)std::min<long>((n + 255) / 256, 1024); };
+    hipLaunchKernelGGL(k_count_known, dim3(nb(N)), dim3(256), 0, s, (int)N, h.lev[0].mask, counts);
+    for (int l = 1; l < nlev; ++l) {
+        const Level &f = h.lev[l - 1], &c = h.lev[l];
+        hipLaunchKernelGGL(k_mask_restrict, dim3(nb((long)c.W * c.H)), dim3(256), 0, s, f.W, f.H, f.mask, c.W, c.H,
+                           c.mask, counts + l);
+    }
 }
 
 template <typename TD>
@@ -414,11 +622,23 @@ void launch_init_u(int W, int H, int C, const uint8_t *mask, const TD *data, con
     hipLaunchKernelGGL(k_init_u<TD>, grid1((long)W * H, 256), dim3(256), 0, s, W * H, C, mask, data, u0, u);
 }
 
+dim3 residual_grid(int W, int H) {
+    const int cols = (RED_THREADS / 64) * RES_COLS;
+    return dim3((W + cols - 1) / cols, (H + RES_BAND - 1) / RES_BAND);
+}
+
 template <typename TD>
-void launch_residual(int W, int H, int C, const uint8_t *mask, const double *u, const TD *data, const double *src,
-                     float *r, double *partials, int nblk, double *norms, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual<TD>, dim3(nblk), dim3(RED_THREADS), 0, s, W, H, C, mask, u, data, src, r, partials, nblk);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(C), dim3(RED_THREADS), 0, s, nblk, partials, norms);
+void launch_residual(int W, int H, int C, const uint8_t *mask, const double *u_in, const float *e, double *u_out,
+                     const TD *data, const double *src, float *r, double *partials, double *norms, hipStream_t s) {
+    const dim3 g = residual_grid(W, H);
+    const int nblk = g.x * g.y;
+    if (C == 3)
+        hipLaunchKernelGGL((k_residual<TD, 3>), g, dim3(RED_THREADS), 0, s, W, H, mask, u_in, e, u_out, data, src, r,
+                           partials, nblk);
+    else
+        hipLaunchKernelGGL((k_residual<TD, 1>), g, dim3(RED_THREADS), 0, s, W, H, mask, u_in, e, u_out, data, src, r,
+                           partials, nblk);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(C), dim3(1024), 0, s, nblk, partials, norms);
 }
 
 void launch_update(int W, int H, int C, const uint8_t *mask, const float *e, double *u, hipStream_t s) {
@@ -473,10 +693,10 @@ void launch_fmg_prolong0(int W, int H, int C, const uint8_t *mask, const Level &
 
 template void launch_init_u<float>(int, int, int, const uint8_t *, const float *, const double *, double *, hipStream_t);
 template void launch_init_u<double>(int, int, int, const uint8_t *, const double *, const double *, double *, hipStream_t);
-template void launch_residual<float>(int, int, int, const uint8_t *, const double *, const float *, const double *,
-                                     float *, double *, int, double *, hipStream_t);
-template void launch_residual<double>(int, int, int, const uint8_t *, const double *, const double *, const double *,
-                                      float *, double *, int, double *, hipStream_t);
+template void launch_residual<float>(int, int, int, const uint8_t *, const double *, const float *, double *,
+                                     const float *, const double *, float *, double *, double *, hipStream_t);
+template void launch_residual<double>(int, int, int, const uint8_t *, const double *, const float *, double *,
+                                      const double *, const double *, float *, double *, double *, hipStream_t);
 template void launch_data_restrict0<float>(int, int, int, const uint8_t *, const float *, const Level &, hipStream_t);
 template void launch_data_restrict0<double>(int, int, int, const uint8_t *, const double *, const Level &, hipStream_t);
 

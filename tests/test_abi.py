@@ -57,8 +57,9 @@ def test_workspace_query_and_status_strings():
     small = lib.hdi_inpaint_workspace_bytes(L.hdi_image(64, 64, 1))
     big = lib.hdi_inpaint_workspace_bytes(L.hdi_image(3840, 2160, 3))
     assert 0 < small < big
-    # FP32 buffers dominate: 3 per level and channel plus the coarse pyramid
-    assert big < 3840 * 2160 * 3 * 4 * 3 * 1.5 + 2 ** 24
+    # per pixel and channel: three FP32 level buffers (plus a fourth on coarse
+    # levels, about 1/3 more in total) and one FP64 iterate copy
+    assert big < 3840 * 2160 * 3 * (12 * 4 / 3 + 4 / 3 + 8) + 2 ** 24
     assert lib.hdi_status_string(2) == b"empty mask"
 
 
