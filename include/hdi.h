@@ -102,6 +102,60 @@ int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double
                       const double *u0, void *ws, size_t ws_bytes,
                       const hdi_solve_params *params, hdi_solve_report *report, void *stream);
 
+/* ------------------------------------------------------------------ tonal */
+
+#define HDI_TONAL_PCG_RAS 0   /* flexible CG, one RAS sweep as preconditioner (default) */
+#define HDI_TONAL_RAS 1       /* stationary RAS iteration, Alg. 2 */
+#define HDI_TONAL_CGNR 2      /* CG on the normal equations, Sec. 5.1 */
+#define HDI_TONAL_INIT_FROM_F 1   /* flags: start from g = f on the mask (g input ignored) */
+#define HDI_TONAL_TRACE 2         /* flags: print one line per outer iteration to stderr */
+
+/* Tonal optimisation parameters. A zero field selects the default.
+ *   rel_tol      stop when max_c ||B^T(f - B g)||_2 / ||B^T f||_2 <= rel_tol,
+ *                recomputed with tight inner solves (default 1e-6)
+ *   max_outer    outer iteration cap (default 500)
+ *   mode         HDI_TONAL_PCG_RAS / HDI_TONAL_RAS / HDI_TONAL_CGNR
+ *   overlap      overlap of the 32x32 blocks of the RAS sweep (default 6,
+ *                Sec. 5.2 uses 6)
+ *   local_outer  CG steps on each block's local normal equations (default 4)
+ *   local_inner  CG steps of each local inpainting inside them (default 32;
+ *                fewer steps truncate the local echoes, which makes the
+ *                stationary RAS iteration overshoot)
+ *   flags        HDI_TONAL_INIT_FROM_F
+ *   inner        parameters of the global inpainting solves (rel_tol is set
+ *                per solve by the outer method)                              */
+typedef struct {
+    double rel_tol;
+    int32_t max_outer, mode, overlap, local_outer, local_inner, flags;
+    hdi_solve_params inner;
+} hdi_tonal_params;
+
+typedef struct {
+    double mse_initial;          /* ||f - B g0||^2 / (C N) at the start */
+    double mse_final;            /* the same at the returned g */
+    double rel_normal_residual;  /* true relative normal residual, max over channels */
+    int32_t outer_iters, inner_solves, inner_vcycles;
+    float ms;
+} hdi_tonal_report;
+
+/* Bytes of workspace tonal_optimize needs for this image. 0 on bad sizes. */
+size_t hdi_tonal_workspace_bytes(hdi_image img);
+
+/* Tonal optimisation, Sec. 5, eq. (tonal-opt-minimisation): the values g on
+ * the mask minimising ||f - B g||_2^2 with B = A^{-1} C, found by solving the
+ * normal equations B^T B g = B^T f (eq. tonal-normal-equations) matrix-free.
+ *   mask  H x W uint8 (device);  f  C x H x W float32 image (device)
+ *   g     C x H x W float64 (device). In: the starting values on the mask
+ *         (ignored with HDI_TONAL_INIT_FROM_F). Out: the optimised values on
+ *         the mask, 0 elsewhere (Sec. 5).
+ *   u     nullable C x H x W float64 output: the reconstruction B g (device)
+ *   ws    workspace of at least hdi_tonal_workspace_bytes(img) (device)
+ * Returns HDI_ERR_EMPTY_MASK for an all-zero mask and HDI_ERR_NO_CONVERGENCE
+ * (with the last iterate in g) when the tolerance is not met. */
+int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, double *g, double *u,
+                       void *ws, size_t ws_bytes, const hdi_tonal_params *params,
+                       hdi_tonal_report *report, void *stream);
+
 /* Number of 32x32 Schwarz blocks with the given overlap on one level of one
  * channel: per dimension ceil((n - 32) / (32 - overlap)) + 1 (1 if n <= 32),
  * the last block shifted to end at the border (Sec. 3.3). Host-only. */

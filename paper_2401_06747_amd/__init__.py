@@ -15,7 +15,10 @@ import torch
 from . import _lib
 from ._lib import HdiError, check
 
-__all__ = ["inpaint_solve", "hdi_block_count", "SolveParams", "HdiError"]
+__all__ = ["inpaint_solve", "tonal_optimize", "hdi_block_count", "SolveParams", "TonalParams", "HdiError",
+           "PCG_RAS", "RAS", "CGNR"]
+
+PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
 
 
 @dataclass
@@ -30,6 +33,22 @@ class SolveParams:
     def c(self):
         return _lib.hdi_solve_params(self.rel_tol, self.max_outer, self.overlap, self.local_iters,
                                      self.coarse_iters, self.flags)
+
+
+@dataclass
+class TonalParams:
+    rel_tol: float = 0.0       # 0 -> 1e-6
+    max_outer: int = 0         # 0 -> 500
+    mode: int = 0              # PCG_RAS, RAS or CGNR
+    overlap: int = 0           # 0 -> 6
+    local_outer: int = 0       # 0 -> 4
+    local_inner: int = 0       # 0 -> 32
+    flags: int = 0
+    inner: SolveParams | None = None
+
+    def c(self):
+        return _lib.hdi_tonal_params(self.rel_tol, self.max_outer, self.mode, self.overlap, self.local_outer,
+                                     self.local_inner, self.flags, (self.inner or SolveParams()).c())
 
 
 def _stream_ptr(dev) -> ctypes.c_void_p:
@@ -79,6 +98,8 @@ def inpaint_solve(f: torch.Tensor, mask: torch.Tensor, u0: torch.Tensor | None =
                          ctypes.byref(p), ctypes.byref(rep), _stream_ptr(f.device))
     report = {"status": st, "rel_residual": list(rep.rel_residual)[:f.shape[0]],
               "outer_iters": rep.outer_iters, "vcycles": rep.vcycles, "ms": rep.ms}
+    if st != _lib.HDI_OK:
+        report["message"] = L.hdi_last_error().decode()
     if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
         check(st)
     return u, report
@@ -86,3 +107,36 @@ def inpaint_solve(f: torch.Tensor, mask: torch.Tensor, u0: torch.Tensor | None =
 
 def hdi_block_count(width: int, height: int, overlap: int) -> int:
     return int(_lib.lib().hdi_block_count(width, height, overlap))
+
+
+def tonal_optimize(f: torch.Tensor, mask: torch.Tensor, g0: torch.Tensor | None = None,
+                   params: TonalParams | None = None, ws: torch.Tensor | None = None,
+                   want_u: bool = False, out: torch.Tensor | None = None):
+    """Optimal values on the mask (eq. tonal-opt-minimisation). Starts from f on
+    the mask unless g0 is given. Returns (g float64, report dict[, u = B g])."""
+    _check_inputs(f, mask)
+    L = _lib.lib()
+    img = _img(f.shape)
+    p = params or TonalParams()
+    if g0 is None:
+        p = TonalParams(**{**p.__dict__, "flags": p.flags | _lib.HDI_TONAL_INIT_FROM_F})
+        g = out if out is not None else torch.empty(f.shape, dtype=torch.float64, device=f.device)
+    else:
+        if g0.shape != f.shape or g0.dtype != torch.float64:
+            raise ValueError("g0 must be float64 shaped like f")
+        g = g0.clone() if out is None else out.copy_(g0)
+    if ws is None:
+        ws = workspace(L.hdi_tonal_workspace_bytes(img), f.device)
+    u = torch.empty(f.shape, dtype=torch.float64, device=f.device) if want_u else None
+    rep = _lib.hdi_tonal_report()
+    pc = p.c()
+    st = L.tonal_optimize(img, _ptr(mask), _ptr(f), _ptr(g), _ptr(u), _ptr(ws), ws.numel(), ctypes.byref(pc),
+                          ctypes.byref(rep), _stream_ptr(f.device))
+    report = {"status": st, "mse_initial": rep.mse_initial, "mse_final": rep.mse_final,
+              "rel_normal_residual": rep.rel_normal_residual, "outer_iters": rep.outer_iters,
+              "inner_solves": rep.inner_solves, "inner_vcycles": rep.inner_vcycles, "ms": rep.ms}
+    if st != _lib.HDI_OK:
+        report["message"] = L.hdi_last_error().decode()
+    if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
+        check(st)
+    return (g, report, u) if want_u else (g, report)

@@ -23,11 +23,30 @@ class hdi_solve_report(ctypes.Structure):
                 ("vcycles", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
+class hdi_tonal_params(ctypes.Structure):
+    _fields_ = [("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("overlap", ctypes.c_int32), ("local_outer", ctypes.c_int32), ("local_inner", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("inner", hdi_solve_params)]
+
+
+class hdi_tonal_report(ctypes.Structure):
+    _fields_ = [("mse_initial", ctypes.c_double), ("mse_final", ctypes.c_double),
+                ("rel_normal_residual", ctypes.c_double), ("outer_iters", ctypes.c_int32),
+                ("inner_solves", ctypes.c_int32), ("inner_vcycles", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+HDI_TONAL_PCG_RAS, HDI_TONAL_RAS, HDI_TONAL_CGNR = 0, 1, 2
+HDI_TONAL_INIT_FROM_F = 1
+HDI_TONAL_TRACE = 2
+
 _P = ctypes.c_void_p
 _SIGS = {
     "hdi_inpaint_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
     "inpaint_solve": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                        ctypes.POINTER(hdi_solve_params), ctypes.POINTER(hdi_solve_report), _P]),
+    "hdi_tonal_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
+    "tonal_optimize": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                        ctypes.POINTER(hdi_tonal_params), ctypes.POINTER(hdi_tonal_report), _P]),
     "hdi_block_count": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hdi_stats_enable": (None, [ctypes.c_int32]),
     "hdi_stats_reset": (None, []),

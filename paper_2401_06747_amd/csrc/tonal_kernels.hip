@@ -1,0 +1,492 @@
+// Kernels of tonal optimisation (paper Sec. 5) for gfx950.
+//
+// The unknowns are the values on the mask K (eq. tonal-opt-minimisation; off
+// the mask g = 0), stored as compact FP64 vectors [C][m] in ascending pixel
+// order. B g = A^{-1} C g is an inpainting solve; B^T y, by the symmetrised
+// form of Sec. 5.1, is y_k + sum_{j in N4(k), j unknown} w_j with
+// L_UU w_U = y_U (an inpainting solve with a source term and zero data).
+#include <cfloat>
+
+#include "hdi_internal.h"
+
+namespace hdi {
+
+// ------------------------------------------------------------------ helpers (local copies)
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int t_dpp_i(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xF, false);
+}
+__device__ __forceinline__ float t_wave_sum(float v) {
+    v += __int_as_float(t_dpp_i<0xB1, 0xF>(__float_as_int(v)));
+    v += __int_as_float(t_dpp_i<0x4E, 0xF>(__float_as_int(v)));
+    v += __int_as_float(t_dpp_i<0x114, 0xF>(__float_as_int(v)));
+    v += __int_as_float(t_dpp_i<0x118, 0xF>(__float_as_int(v)));
+    v += __int_as_float(t_dpp_i<0x142, 0xA>(__float_as_int(v)));
+    v += __int_as_float(t_dpp_i<0x143, 0xC>(__float_as_int(v)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double t_dpp_d(double x) {
+    const int lo = t_dpp_i<CTRL, ROWS>(__double2loint(x));
+    const int hi = t_dpp_i<CTRL, ROWS>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double t_wave_sum_d(double v) {
+    v += t_dpp_d<0xB1, 0xF>(v);
+    v += t_dpp_d<0x4E, 0xF>(v);
+    v += t_dpp_d<0x114, 0xF>(v);
+    v += t_dpp_d<0x118, 0xF>(v);
+    v += t_dpp_d<0x142, 0xA>(v);
+    v += t_dpp_d<0x143, 0xC>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int t_xcd_remap(int bid, int n) {
+    const int q = n >> 3, rem = n & 7;
+    const int x = bid & 7, k = bid >> 3;
+    return x * q + min(x, rem) + k;
+}
+
+// ------------------------------------------------------------------ mask compaction
+
+constexpr int CMP_THREADS = 1024;
+
+// Known pixels per workgroup chunk of CMP_THREADS pixels.
+__global__ void __launch_bounds__(CMP_THREADS)
+k_compact_count(int N, const uint8_t *__restrict__ m, int *__restrict__ chunk_cnt) {
+    const int i = blockIdx.x * CMP_THREADS + threadIdx.x;
+    const int k = (i < N && m[i]) ? 1 : 0;
+    __shared__ int s[CMP_THREADS / 64];
+    const unsigned long long b = __ballot(k);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < CMP_THREADS / 64; ++w) t += s[w];
+        chunk_cnt[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the chunk counts (one workgroup; sequential over blocks of
+// 1024 with a workgroup scan inside), plus the total.
+__global__ void __launch_bounds__(CMP_THREADS)
+k_compact_scan(int nchunks, const int *__restrict__ cnt, int *__restrict__ off, int *__restrict__ total) {
+    __shared__ int s[CMP_THREADS];
+    int carry = 0;
+    for (int base = 0; base < nchunks; base += CMP_THREADS) {
+        const int i = base + threadIdx.x;
+        const int v = i < nchunks ? cnt[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < CMP_THREADS; d <<= 1) {
+            const int t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nchunks) off[i] = carry + s[threadIdx.x] - v;
+        const int last = s[CMP_THREADS - 1];
+        __syncthreads();
+        carry += last;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// idx[j] = pixel of the j-th known pixel (ascending), pos[i] = j or -1.
+__global__ void __launch_bounds__(CMP_THREADS)
+k_compact_scatter(int N, const uint8_t *__restrict__ m, const int *__restrict__ off, int *__restrict__ idx,
+                  int *__restrict__ pos) {
+    const int i = blockIdx.x * CMP_THREADS + threadIdx.x;
+    const int k = (i < N && m[i]) ? 1 : 0;
+    const unsigned long long b = __ballot(k);
+    const int lane = threadIdx.x & 63;
+    const int before = __popcll(b & ((1ull << lane) - 1ull));
+    __shared__ int s[CMP_THREADS / 64];
+    if (lane == 0) s[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += s[w];
+    if (i < N) {
+        const int j = off[blockIdx.x] + wbase + before;
+        pos[i] = k ? j : -1;
+        if (k) idx[j] = i;
+    }
+}
+
+// ------------------------------------------------------------------ compact <-> image
+
+// img[c][idx[j]] = v[c][j] (only mask pixels are written).
+__global__ void k_scatter_K(int m, int C, int N, const int *__restrict__ idx, const double *__restrict__ v,
+                            double *__restrict__ img) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int i = idx[j];
+    for (int c = 0; c < C; ++c) img[(size_t)c * N + i] = v[(size_t)c * m + j];
+}
+
+// v[c][j] = (double) f[c][idx[j]]
+__global__ void k_gather_f(int m, int C, int N, const int *__restrict__ idx, const float *__restrict__ f,
+                           double *__restrict__ v) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int i = idx[j];
+    for (int c = 0; c < C; ++c) v[(size_t)c * m + j] = (double)f[(size_t)c * N + i];
+}
+
+// B^T gather (Sec. 5.1, symmetrised system): out[c][j] = y[c][k] + sum of w over
+// the unknown 4-neighbours of k = idx[j]. y may be null (then y_k = yK[c][j]).
+__global__ void k_gather_Bt(int W, int H, int m, int C, const int *__restrict__ idx, const uint8_t *__restrict__ mask,
+                            const double *__restrict__ y, const double *__restrict__ yK, const double *__restrict__ w,
+                            double *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int N = W * H;
+    const int k = idx[j];
+    const int x = k % W, yy = k / W;
+    const bool hl = x > 0 && !mask[k - 1], hr = x < W - 1 && !mask[k + 1];
+    const bool hu = yy > 0 && !mask[k - W], hd = yy < H - 1 && !mask[k + W];
+    for (int c = 0; c < C; ++c) {
+        const double *wc = w + (size_t)c * N;
+        double s = y ? y[(size_t)c * N + k] : yK[(size_t)c * m + j];
+        if (hl) s += wc[k - 1];
+        if (hr) s += wc[k + 1];
+        if (hu) s += wc[k - W];
+        if (hd) s += wc[k + W];
+        out[(size_t)c * m + j] = s;
+    }
+}
+
+// rho = f - u over the whole image (FP64), plus partial sums of rho^2 per channel.
+__global__ void __launch_bounds__(256)
+k_image_residual(int N, int C, const float *__restrict__ f, const double *__restrict__ u, double *__restrict__ rho,
+                 double *__restrict__ partials, int nblk) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += nblk * 256)
+        for (int c = 0; c < C; ++c) {
+            const size_t o = (size_t)c * N + i;
+            const double d = (double)f[o] - (u ? u[o] : 0.0);
+            rho[o] = d;
+            acc[c] += d * d;
+        }
+    __shared__ double s[4][3];
+    for (int c = 0; c < C; ++c) {
+        const double a = t_wave_sum_d(acc[c]);
+        if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6][c] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double a = 0.0;
+        for (int w = 0; w < 4; ++w) a += s[w][threadIdx.x];
+        partials[(size_t)threadIdx.x * nblk + blockIdx.x] = a;
+    }
+}
+
+// ------------------------------------------------------------------ compact vector algebra (FP64)
+
+// Partial sums of sum_j a[c][j] * b[c][j] for NP pairs at once: pairs (a_q, b_q),
+// q < np; partials[q][c][blk]. Fixed grid => fixed summation order.
+struct DotArgs { const double *a[4]; const double *b[4]; };
+
+__global__ void __launch_bounds__(256)
+k_dots(int m, int C, int np, DotArgs args, double *__restrict__ partials, int nblk) {
+    double acc[4][3];
+    for (int q = 0; q < 4; ++q)
+        for (int c = 0; c < 3; ++c) acc[q][c] = 0.0;
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < m; j += nblk * 256)
+        for (int q = 0; q < np; ++q)
+            for (int c = 0; c < C; ++c) acc[q][c] += args.a[q][(size_t)c * m + j] * args.b[q][(size_t)c * m + j];
+    __shared__ double s[4][12];
+    for (int q = 0; q < np; ++q)
+        for (int c = 0; c < C; ++c) {
+            const double v = t_wave_sum_d(acc[q][c]);
+            if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6][q * 3 + c] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < np * 3) {
+        const int q = threadIdx.x / 3, c = threadIdx.x % 3;
+        if (c < C) {
+            double v = 0.0;
+            for (int w = 0; w < 4; ++w) v += s[w][threadIdx.x];
+            partials[((size_t)q * 3 + c) * nblk + blockIdx.x] = v;
+        }
+    }
+}
+
+// out[k] = sum_b partials[k][b] for k < nk (one wave per value, fixed order).
+__global__ void k_sum_rows(int nk, int nblk, const double *__restrict__ partials, double *__restrict__ out) {
+    const int k = blockIdx.x;
+    if (k >= nk) return;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 64) a += partials[(size_t)k * nblk + b];
+    a = t_wave_sum_d(a);
+    if (threadIdx.x == 0) out[k] = a;
+}
+
+// y[c] = a[c] * x[c] + b[c] * y[c] (per-channel scalars on the device-visible arg).
+struct Coef3 { double a[3], b[3]; };
+__global__ void k_axpby(int m, int C, Coef3 k, const double *__restrict__ x, double *__restrict__ y) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    for (int c = 0; c < C; ++c) {
+        const size_t o = (size_t)c * m + j;
+        y[o] = k.a[c] * x[o] + k.b[c] * y[o];
+    }
+}
+
+// ------------------------------------------------------------------ RAS local normal equations
+
+// One RAS sweep of Alg. 2 step 2 on 32x32 blocks: each block solves its local
+// normal equations B_i^T B_i v_i = R_i r by `nc` steps of CG on the normal
+// equations (CGNR), where B_i = A_i^{-1} C_i is inpainting on the block's own
+// grid graph (homogeneous Neumann at the block boundary, Sec. 5.2) and each
+// local inpainting is `ni` steps of CG on L_UU of the block. The result is
+// written on the mask pixels the block owns (0/1 partition of unity, the middle
+// of each overlap splitting ownership). FP32 throughout (a preconditioner).
+// Layout as in the Schwarz smoother: one wave per block, 4x4 pixels per lane,
+// neighbour exchange through a zero-ringed LDS tile.
+constexpr int TT = 32;
+constexpr int TLDS_W = 40;
+constexpr int TCOL0 = 4;
+
+struct LocalTile {
+    float (*s_x)[TLDS_W];
+    int bx, by;
+    __device__ void publish(const float *v) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<float4 *>(&s_x[4 * by + j + 1][TCOL0 + 4 * bx]) =
+                make_float4(v[j * 4 + 0], v[j * 4 + 1], v[j * 4 + 2], v[j * 4 + 3]);
+        __syncthreads();
+    }
+    // n[k] = sum of the 4 neighbours of pixel k of v (zero outside the block)
+    __device__ void nbsum(const float *v, float *n) {
+        publish(v);
+        const float4 up = *reinterpret_cast<const float4 *>(&s_x[4 * by][TCOL0 + 4 * bx]);
+        const float4 dn = *reinterpret_cast<const float4 *>(&s_x[4 * by + 5][TCOL0 + 4 * bx]);
+        const float upv[4] = {up.x, up.y, up.z, up.w};
+        const float dnv[4] = {dn.x, dn.y, dn.z, dn.w};
+        float lf[4], rt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            lf[j] = s_x[4 * by + j + 1][TCOL0 + 4 * bx - 1];
+            rt[j] = s_x[4 * by + j + 1][TCOL0 + 4 * bx + 4];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = j * 4 + i;
+                n[k] = (j > 0 ? v[k - 4] : upv[i]) + (j < 3 ? v[k + 4] : dnv[i]) + (i > 0 ? v[k - 1] : lf[j]) +
+                       (i < 3 ? v[k + 1] : rt[j]);
+            }
+        __syncthreads();
+    }
+};
+
+// x = (L_UU of the block)^{-1} b by `iters` CG steps from 0; b and x are zero
+// off U. dg[k] = block-graph degree on U pixels, 0 elsewhere.
+__device__ __forceinline__ void local_cg(LocalTile &T, const float *dg, const float *b, float *x, int iters) {
+    float r[16], p[16], q[16];
+    float rr = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        x[k] = 0.f;
+        r[k] = b[k];
+        p[k] = b[k];
+        rr += b[k] * b[k];
+    }
+    rr = t_wave_sum(rr);
+    const float floor_rr = rr * 1e-14f;
+    for (int it = 0; it < iters && rr > floor_rr && rr >= FLT_MIN; ++it) {
+        T.nbsum(p, q);
+        float pq = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            q[k] = dg[k] > 0.f ? dg[k] * p[k] - q[k] : 0.f;
+            pq += p[k] * q[k];
+        }
+        pq = t_wave_sum(pq);
+        if (!(pq >= FLT_MIN)) break;
+        const float alpha = rr * __builtin_amdgcn_rcpf(pq);
+        float rr2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            x[k] += alpha * p[k];
+            r[k] -= alpha * q[k];
+            rr2 += r[k] * r[k];
+        }
+        rr2 = t_wave_sum(rr2);
+        const float beta = rr2 * __builtin_amdgcn_rcpf(rr);
+        rr = rr2;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) p[k] = r[k] + beta * p[k];
+    }
+}
+
+__global__ void __launch_bounds__(64)
+k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int ni, const uint8_t *__restrict__ mask,
+            const int *__restrict__ pos, const double *__restrict__ r, double *__restrict__ z) {
+    __shared__ __attribute__((aligned(16))) float s_x[TT + 2][TLDS_W];
+    const int ntiles = ntx * nty;
+    const int t = t_xcd_remap(blockIdx.x, ntiles);
+    const int c = blockIdx.y;
+    const int tx = t % ntx, ty = t / ntx;
+    const int Tx = min(TT, W), Ty = min(TT, H);
+    const int x0 = min(tx * sx, W - Tx), y0 = min(ty * sy, H - Ty);
+    const int lane = threadIdx.x;
+    for (int k = lane; k < (TT + 2) * TLDS_W; k += 64) (&s_x[0][0])[k] = 0.f;
+    __syncthreads();
+    LocalTile T{s_x, lane & 7, lane >> 3};
+    const int bx = lane & 7, by = lane >> 3;
+
+    // pixel classes and right-hand side (all loads first, clamped addresses)
+    int pk[16];
+    uint8_t mk[16];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int xx = min(x0 + 4 * bx + i, W - 1), yy = min(y0 + 4 * by + j, H - 1);
+            pk[j * 4 + i] = pos[yy * W + xx];
+            mk[j * 4 + i] = mask[yy * W + xx];
+        }
+    float dgU[16], isK[16], s[16];
+    float ss = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = j * 4 + i;
+            const int lx = 4 * bx + i, ly = 4 * by + j;
+            const bool act = lx < Tx && ly < Ty;
+            const bool known = act && mk[k];
+            const float d = (float)((lx > 0) + (lx < Tx - 1) + (ly > 0) + (ly < Ty - 1));
+            dgU[k] = (act && !known) ? d : 0.f;
+            isK[k] = known ? 1.f : 0.f;
+            s[k] = known ? (float)r[(size_t)c * m + pk[k]] : 0.f;
+            ss += s[k] * s[k];
+        }
+    ss = t_wave_sum(ss);
+
+    // local CGNR on the mask pixels of the block
+    float v[16], p[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { v[k] = 0.f; p[k] = s[k]; }
+    const float floor_ss = ss * 1e-14f;
+    for (int it = 0; it < nc && ss > floor_ss && ss >= FLT_MIN; ++it) {
+        float tvec[16], tmp[16], u[16];
+        // t = B_i p: p on K, inpainted values on U
+        T.nbsum(p, tmp);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tmp[k] : 0.f;
+        local_cg(T, dgU, tmp, u, ni);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tvec[k] = isK[k] > 0.f ? p[k] : u[k];
+        // q = B_i^T t = t_K + sum over unknown neighbours of (L_UU^{-1} t_U)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tvec[k] : 0.f;
+        local_cg(T, dgU, tmp, u, ni);
+        T.nbsum(u, tmp);
+        float pq = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            tmp[k] = isK[k] > 0.f ? tvec[k] + tmp[k] : 0.f;   // q
+            pq += p[k] * tmp[k];
+        }
+        pq = t_wave_sum(pq);
+        if (!(pq >= FLT_MIN)) break;
+        const float alpha = ss * __builtin_amdgcn_rcpf(pq);
+        float ss2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            v[k] += alpha * p[k];
+            s[k] -= alpha * tmp[k];
+            ss2 += s[k] * s[k];
+        }
+        ss2 = t_wave_sum(ss2);
+        const float beta = ss2 * __builtin_amdgcn_rcpf(ss);
+        ss = ss2;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) p[k] = s[k] + beta * p[k];
+    }
+
+    // restricted write-back on owned mask pixels
+    const int xlo = tx == 0 ? 0 : (min((tx - 1) * sx, W - Tx) + Tx + x0) / 2;
+    const int xhi = tx == ntx - 1 ? W : (x0 + Tx + min((tx + 1) * sx, W - Tx)) / 2;
+    const int ylo = ty == 0 ? 0 : (min((ty - 1) * sy, H - Ty) + Ty + y0) / 2;
+    const int yhi = ty == nty - 1 ? H : (y0 + Ty + min((ty + 1) * sy, H - Ty)) / 2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = j * 4 + i;
+            const int x = x0 + 4 * bx + i, y = y0 + 4 * by + j;
+            if (isK[k] > 0.f && x >= xlo && x < xhi && y >= ylo && y < yhi) z[(size_t)c * m + pk[k]] = (double)v[k];
+        }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline dim3 g1(long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+void launch_compact(int N, const uint8_t *mask, int *chunk_cnt, int *chunk_off, int *total, int *idx, int *pos,
+                    hipStream_t s) {
+    const int nch = (N + CMP_THREADS - 1) / CMP_THREADS;
+    hipLaunchKernelGGL(k_compact_count, dim3(nch), dim3(CMP_THREADS), 0, s, N, mask, chunk_cnt);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(CMP_THREADS), 0, s, nch, chunk_cnt, chunk_off, total);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nch), dim3(CMP_THREADS), 0, s, N, mask, chunk_off, idx, pos);
+}
+
+void launch_scatter_K(int m, int C, int N, const int *idx, const double *v, double *img, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_K, g1(m, 256), dim3(256), 0, s, m, C, N, idx, v, img);
+}
+
+void launch_gather_f(int m, int C, int N, const int *idx, const float *f, double *v, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_f, g1(m, 256), dim3(256), 0, s, m, C, N, idx, f, v);
+}
+
+void launch_gather_Bt(int W, int H, int m, int C, const int *idx, const uint8_t *mask, const double *y,
+                      const double *yK, const double *w, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_Bt, g1(m, 256), dim3(256), 0, s, W, H, m, C, idx, mask, y, yK, w, out);
+}
+
+constexpr int RED_BLOCKS = 512;
+
+void launch_image_residual(int N, int C, const float *f, const double *u, double *rho, double *partials,
+                           double *sums, hipStream_t s) {
+    hipLaunchKernelGGL(k_image_residual, dim3(RED_BLOCKS), dim3(256), 0, s, N, C, f, u, rho, partials, RED_BLOCKS);
+    hipLaunchKernelGGL(k_sum_rows, dim3(C), dim3(64), 0, s, C, RED_BLOCKS, partials, sums);
+}
+
+void launch_dots(int m, int C, int np, const double *const *a, const double *const *b, double *partials,
+                 double *sums, hipStream_t s) {
+    DotArgs args;
+    for (int q = 0; q < 4; ++q) {
+        args.a[q] = q < np ? a[q] : nullptr;
+        args.b[q] = q < np ? b[q] : nullptr;
+    }
+    hipLaunchKernelGGL(k_dots, dim3(RED_BLOCKS), dim3(256), 0, s, m, C, np, args, partials, RED_BLOCKS);
+    // sums laid out [q][3]
+    hipLaunchKernelGGL(k_sum_rows, dim3(np * 3), dim3(64), 0, s, np * 3, RED_BLOCKS, partials, sums);
+}
+
+void launch_axpby(int m, int C, const double *a, const double *b, const double *x, double *y, hipStream_t s) {
+    Coef3 k;
+    for (int c = 0; c < 3; ++c) {
+        k.a[c] = c < C ? a[c] : 0.0;
+        k.b[c] = c < C ? b[c] : 0.0;
+    }
+    hipLaunchKernelGGL(k_axpby, g1(m, 256), dim3(256), 0, s, m, C, k, x, y);
+}
+
+void launch_ras_local(int W, int H, int C, int m, int overlap, int nc, int ni, const uint8_t *mask, const int *pos,
+                      const double *r, double *z, hipStream_t s) {
+    const Blocks1D bx = make_blocks(W, overlap), by = make_blocks(H, overlap);
+    dim3 g(bx.count * by.count, C);
+    hipLaunchKernelGGL(k_ras_local, g, dim3(64), 0, s, W, H, m, bx.count, by.count, bx.stride, by.stride, nc, ni,
+                       mask, pos, r, z);
+}
+
+}  // namespace hdi

@@ -1,0 +1,109 @@
+"""GPU parity of tonal_optimize (through the C ABI) against the FP64 oracle
+(Sec. 5, eqs. tonal-opt-minimisation and tonal-normal-equations).
+
+Bar: relative L2 error of g on the mask <= 1e-5 against the oracle's optimum,
+final MSE within 1e-4 (relative) of the oracle's, and the normal residual of the
+GPU's g, recomputed by the oracle with exact solves, at the requested tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2401_06747_amd as hdi
+from oracle import inpaint as oi
+from oracle import tonal as ot
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _run(f, m, **kw):
+    ft = torch.tensor(f, dtype=torch.float32, device=DEV).contiguous()
+    mt = torch.tensor(m, dtype=torch.uint8, device=DEV).contiguous()
+    g, rep, u = hdi.tonal_optimize(ft, mt, params=hdi.TonalParams(**kw), want_u=True)
+    torch.cuda.synchronize()
+    return g.cpu().numpy(), rep, u.cpu().numpy()
+
+
+def _check(f, m, g, rep, u, tol=1e-6, err_tol=1e-5):
+    f = np.asarray(f, np.float64)
+    assert rep["status"] == 0, rep
+    K = m != 0
+    assert np.all(g[:, ~K] == 0)
+    gref = ot.tonal_optimize(f, m)
+    err = np.array([np.linalg.norm(g[c][K] - gref[c][K]) / np.linalg.norm(gref[c][K]) for c in range(f.shape[0])])
+    mse_ref = ot.mse(gref, f, m)
+    mse_gpu = ot.mse(g, f, m)
+    nres = ot.normal_residual(g, f, m)
+    assert err.max() <= err_tol, (err, nres, rep)
+    assert abs(rep["mse_final"] - mse_ref) <= 1e-4 * mse_ref, (rep, mse_ref)
+    assert abs(mse_gpu - mse_ref) <= 1e-4 * mse_ref
+    assert nres.max() <= 2 * tol, (nres, rep)
+    assert rep["mse_final"] <= rep["mse_initial"]
+    # u = B g as returned
+    np.testing.assert_allclose(u, ot.reconstruct(g, m), rtol=0, atol=1e-6 * 255)
+    return err, nres
+
+
+def test_config1_gray_256_default_mode():
+    inst = synth.config1()
+    g, rep, u = _run(inst.f, inst.mask, rel_tol=1e-7)
+    err, nres = _check(inst.f, inst.mask, g, rep, u, tol=1e-7)
+    print("config1 tonal", err, nres, rep)
+
+
+@pytest.mark.parametrize("mode", [hdi.PCG_RAS, hdi.RAS, hdi.CGNR])
+def test_all_outer_methods_reach_the_same_optimum(mode):
+    """Sec. 6.3: the problem is convex, every method converges to the same values."""
+    inst = synth.config2(90, 150, 1, 0.04, item=21)
+    g, rep, u = _run(inst.f, inst.mask, mode=mode, rel_tol=1e-7)
+    err, nres = _check(inst.f, inst.mask, g, rep, u, tol=1e-7)
+    print("mode", mode, err, nres, rep)
+
+
+def test_rgb_textured_ragged_blocks():
+    inst = synth.config2(97, 161, 3, 0.03, item=22)
+    g, rep, u = _run(inst.f, inst.mask, rel_tol=1e-7)
+    err, nres = _check(inst.f, inst.mask, g, rep, u, tol=1e-7)
+    print("rgb", err, nres, rep)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 40), (1, 33, 1), (1, 5, 7), (3, 31, 40)])
+def test_small_shapes(shape):
+    C, H, W = shape
+    rng = np.random.default_rng(sum(shape))
+    f = rng.uniform(0, 255, (C, H, W)).astype(np.float32).astype(np.float64)
+    m = (rng.random((H, W)) < 0.15).astype(np.uint8)
+    m[0, 0] = 1
+    g, rep, u = _run(f, m, rel_tol=1e-7)
+    _check(f, m, g, rep, u, tol=1e-7)
+
+
+def test_full_and_single_pixel_masks():
+    rng = np.random.default_rng(3)
+    f = rng.uniform(0, 255, (1, 20, 30)).astype(np.float32).astype(np.float64)
+    g, rep, _ = _run(f, np.ones((20, 30), np.uint8))
+    assert rep["status"] == 0 and np.allclose(g, f, atol=1e-9)
+    m = np.zeros((20, 30), np.uint8)
+    m[4, 9] = 1
+    g, rep, _ = _run(f, m)
+    assert rep["status"] == 0
+    assert abs(g[0, 4, 9] - f.mean()) < 1e-5 * f.mean()
+    assert abs(rep["mse_final"] - f.var()) < 1e-4 * f.var()
+
+
+def test_empty_mask_is_an_error():
+    f = np.zeros((1, 8, 8))
+    with pytest.raises(hdi.HdiError) as ei:
+        _run(f, np.zeros((8, 8), np.uint8))
+    assert ei.value.status == 2
+
+
+def test_warm_start_from_optimum_returns_immediately():
+    inst = synth.config2(60, 90, 1, 0.05, item=23)
+    ft = torch.tensor(inst.f, dtype=torch.float32, device=DEV)
+    mt = torch.tensor(inst.mask, device=DEV)
+    g1, r1 = hdi.tonal_optimize(ft, mt, params=hdi.TonalParams(rel_tol=1e-8))
+    g2, r2 = hdi.tonal_optimize(ft, mt, g0=g1, params=hdi.TonalParams(rel_tol=1e-6))
+    assert r2["status"] == 0 and r2["outer_iters"] == 0
+    assert torch.equal(g1, g2)
