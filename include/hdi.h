@@ -166,13 +166,18 @@ int64_t hdi_block_count(int32_t width, int32_t height, int32_t overlap);
  *   0 FP64 residual (finest level)     1 Schwarz pre-smoothing (finest level)
  *   2 Schwarz post-smoothing (finest)  3 residual restriction (finest level)
  *   4 FP64 refinement update           5 all coarser levels and the FMG start
+ *   6 tonal RAS sweep (local normal equations)
+ *   7 tonal vector kernels (gathers, scatters, dot products, updates)
  * For each id the library accumulates the number of launches, their summed
- * device time in ms and the algorithmic bytes those launches must move (every
- * input element read once, every output element written once). */
-#define HDI_NUM_KERNEL_IDS 6
+ * device time in ms, the algorithmic bytes those launches must move (every
+ * input element read once, every output element written once) and the
+ * algorithmic floating-point operations of the block solvers (15 per pixel and
+ * local CG step: stencil 5, two dot products 4, three vector updates 6). */
+#define HDI_NUM_KERNEL_IDS 8
 void hdi_stats_enable(int32_t on);
 void hdi_stats_reset(void);
-int32_t hdi_stats_get(int32_t kernel_id, int64_t *launches, double *total_ms, double *alg_bytes);
+int32_t hdi_stats_get(int32_t kernel_id, int64_t *launches, double *total_ms, double *alg_bytes,
+                      double *alg_flops);
 
 const char *hdi_status_string(int32_t status);
 const char *hdi_last_error(void);   /* thread-local message of the last failure */

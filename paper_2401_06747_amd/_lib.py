@@ -51,7 +51,7 @@ _SIGS = {
     "hdi_stats_enable": (None, [ctypes.c_int32]),
     "hdi_stats_reset": (None, []),
     "hdi_stats_get": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
-                                       ctypes.POINTER(ctypes.c_double)]),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "hdi_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "hdi_last_error": (ctypes.c_char_p, []),
 }

@@ -83,10 +83,10 @@ struct SolveCfg {
 // are resolved after the call's final synchronisation.
 struct Prof {
     bool on = false;
-    struct Rec { int id; double bytes; hipEvent_t a, b; };
+    struct Rec { int id; double bytes, flops; hipEvent_t a, b; };
     Rec recs[4096];
     int n = 0;
-    void begin(int id, double bytes, hipStream_t s);
+    void begin(int id, double bytes, hipStream_t s, double flops = 0.0);
     void end(hipStream_t s);
     void flush();   // accumulate into the global counters and free the events
 };

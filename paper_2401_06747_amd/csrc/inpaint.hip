@@ -21,16 +21,17 @@ namespace hdi {
 
 // ------------------------------------------------------------------ kernel timing
 
-struct KStats { int64_t launches; double ms, bytes; };
+struct KStats { int64_t launches; double ms, bytes, flops; };
 static std::mutex g_stats_mu;
 static KStats g_stats[HDI_NUM_KERNEL_IDS];
 static std::atomic<int> g_stats_on{0};
 
-void Prof::begin(int id, double bytes, hipStream_t s) {
+void Prof::begin(int id, double bytes, hipStream_t s, double flops) {
     if (!on || n >= (int)(sizeof recs / sizeof recs[0])) return;
     Rec &r = recs[n];
     r.id = id;
     r.bytes = bytes;
+    r.flops = flops;
     if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
     (void)hipEventRecord(r.a, s);
 }
@@ -47,6 +48,7 @@ void Prof::flush() {
             g_stats[recs[i].id].launches += 1;
             g_stats[recs[i].id].ms += ms;
             g_stats[recs[i].id].bytes += recs[i].bytes;
+            g_stats[recs[i].id].flops += recs[i].flops;
         }
         (void)hipEventDestroy(recs[i].a);
         (void)hipEventDestroy(recs[i].b);
@@ -123,13 +125,15 @@ static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Pr
     }
     Level &Lc = h.lev[l + 1];
     const double N = (double)L.W * L.H, Nc = (double)Lc.W * Lc.H;
-    if (prof) prof->begin(1, N * (1 + 8.0 * C), s);
+    const double blk_px = (double)L.bx.count * L.by.count * std::min(TILE, L.W) * std::min(TILE, L.H) * C;
+    const double cg_flops = 15.0 * blk_px * cfg.local_iters;
+    if (prof) prof->begin(1, N * (1 + 8.0 * C), s, cg_flops);
     launch_smooth_pre(L, C, cfg.local_iters, L.ea, s);
     if (prof) { prof->end(s); prof->begin(3, N * (1 + 8.0 * C) + Nc * (1 + 4.0 * C), s); }
     launch_restrict_residual(L, Lc, C, L.ea, s);
     if (prof) { prof->end(s); prof->begin(5, 0.0, s); }
     const float *ec = vcycle(h, l + 1, cfg, s);
-    if (prof) { prof->end(s); prof->begin(2, N * (1 + 12.0 * C) + 4.0 * C * Nc, s); }
+    if (prof) { prof->end(s); prof->begin(2, N * (1 + 12.0 * C) + 4.0 * C * Nc, s, cg_flops); }
     launch_smooth_post(L, Lc, C, cfg.local_iters, L.ea, ec, L.eb, s);
     if (prof) prof->end(s);
     return L.eb;
@@ -354,10 +358,10 @@ void hdi_stats_enable(int32_t on) { g_stats_on.store(on ? 1 : 0); }
 
 void hdi_stats_reset(void) {
     std::lock_guard<std::mutex> lk(g_stats_mu);
-    for (auto &k : g_stats) k = KStats{0, 0.0, 0.0};
+    for (auto &k : g_stats) k = KStats{0, 0.0, 0.0, 0.0};
 }
 
-int32_t hdi_stats_get(int32_t id, int64_t *launches, double *total_ms, double *alg_bytes) {
+int32_t hdi_stats_get(int32_t id, int64_t *launches, double *total_ms, double *alg_bytes, double *alg_flops) {
     if (id < 0 || id >= HDI_NUM_KERNEL_IDS) {
         set_error("kernel id %d outside 0..%d", id, HDI_NUM_KERNEL_IDS - 1);
         return HDI_ERR_ARG;
@@ -366,6 +370,7 @@ int32_t hdi_stats_get(int32_t id, int64_t *launches, double *total_ms, double *a
     if (launches) *launches = g_stats[id].launches;
     if (total_ms) *total_ms = g_stats[id].ms;
     if (alg_bytes) *alg_bytes = g_stats[id].bytes;
+    if (alg_flops) *alg_flops = g_stats[id].flops;
     return HDI_OK;
 }
 

@@ -93,6 +93,7 @@ struct TonalCtx {
     const float *f;
     SolveCfg inner;
     hipStream_t s;
+    Prof *prof;
     int solves = 0, vcycles = 0;
 
     // u = B x for x given on K (compact); cold start with FMG unless warm.
@@ -101,7 +102,7 @@ struct TonalCtx {
         SolveCfg c = inner;
         c.rel_tol = tol;
         hdi_solve_report rep;
-        int32_t st = solve_system<double>(t.h, W, H, C, mask, t.img_d, nullptr, u, warm, c, &rep, s);
+        int32_t st = solve_system<double>(t.h, W, H, C, mask, t.img_d, nullptr, u, warm, c, &rep, s, prof);
         if (st) set_error("inner B solve (tol %.1e, warm %d): %s", tol, (int)warm, hdi_last_error());
         ++solves;
         vcycles += rep.vcycles;
@@ -113,7 +114,8 @@ struct TonalCtx {
         SolveCfg c = inner;
         c.rel_tol = tol;
         hdi_solve_report rep;
-        int32_t st = solve_system<double>(t.h, W, H, C, mask, (const double *)nullptr, ysrc, t.wA, warm, c, &rep, s);
+        int32_t st =
+            solve_system<double>(t.h, W, H, C, mask, (const double *)nullptr, ysrc, t.wA, warm, c, &rep, s, prof);
         if (st) set_error("inner B^T solve (tol %.1e, warm %d): %s", tol, (int)warm, hdi_last_error());
         ++solves;
         vcycles += rep.vcycles;
@@ -225,9 +227,19 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
                 ? std::min(1e-4, std::max(tight, 1e-3 * rmin))
                 : std::min(1e-3, std::max(tight, 1e-3 * tc.rel_tol / std::max(rmin, 1e-300)));
 
+        const Blocks1D tbx = make_blocks(X.W, tc.overlap), tby = make_blocks(X.H, tc.overlap);
+        const double ras_px = (double)tbx.count * tby.count * std::min(32, X.W) * std::min(32, X.H) * C;
+        // per local CGNR step: two local inpaintings of local_inner CG steps
+        const double ras_flops = ras_px * tc.local_outer * (2.0 * tc.local_inner * 15.0 + 20.0);
+        const double ras_bytes = (double)X.N * 5.0 + 16.0 * C * m;   // mask + pos, r in, z out
+        auto ras_sweep = [&]() {
+            if (X.prof) X.prof->begin(6, ras_bytes, s, ras_flops);
+            launch_ras_local(X.W, X.H, C, m, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK, t.zK, s);
+            if (X.prof) X.prof->end(s);
+        };
         if (tc.mode == HDI_TONAL_RAS) {
             // Alg. 2: local corrections, then the global residual with warm starts
-            launch_ras_local(X.W, X.H, C, m, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK, t.zK, s);
+            ras_sweep();
             const double one[3] = {1, 1, 1};
             launch_axpby(m, C, one, one, t.zK, t.gK, s);
             ++it;
@@ -238,8 +250,7 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             // flexible CG (Notay's FCG with one stored direction)
             const double *z = t.rK;
             if (tc.mode == HDI_TONAL_PCG_RAS) {
-                launch_ras_local(X.W, X.H, C, m, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK,
-                                 t.zK, s);
+                ras_sweep();
                 z = t.zK;
             }
             double beta[3] = {0, 0, 0};
@@ -387,8 +398,13 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
     hipLaunchKernelGGL(k_image_from_K, dim3((N + 255) / 256), dim3(256), 0, s, N, C, m, t.pos, t.gK, t.img_d);
     T_TRY(hipGetLastError());
     inner.known = t.h.known[0];
-    TonalCtx X{t, img.width, img.height, C, N, m, mask, f, inner, s};
+    Prof *prof = prof_for_call();
+    TonalCtx X{t, img.width, img.height, C, N, m, mask, f, inner, s, prof};
     st = run_tonal(X, tc, g, u, report);
+    if (prof) {
+        prof->flush();
+        delete prof;
+    }
     T_TRY(hipEventRecord(e1, s));
     T_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
