@@ -156,6 +156,35 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
                        void *ws, size_t ws_bytes, const hdi_tonal_params *params,
                        hdi_tonal_report *report, void *stream);
 
+/* ------------------------------------------------------------------ densification */
+
+#define HDI_PART_DELAUNAY 0   /* triangles of mask pixels (Sec. 4.1) */
+#define HDI_PART_VORONOI 1    /* Voronoi cells of mask pixels (the ablation of Sec. 6.2) */
+
+/* Bytes of workspace densify_step needs for a width x height mask. 0 on bad sizes. */
+size_t hdi_densify_workspace_bytes(int32_t width, int32_t height);
+
+/* One step of Delaunay densification, Sec. 4.1 Alg. 1: partition the image by
+ * the triangulation of the current mask pixels (built from their Voronoi
+ * diagram, Sec. 4.2), sum the error map per cell, and in the cells with the
+ * largest sums add the pixel of largest error, at most one per cell.
+ * Exact discrete reading (every step integer, so results are reproducible):
+ * nearest mask pixel by (squared distance, linear index); a 2x2 pixel quad with
+ * three or four distinct labels gives one or two triangles (the sorted index
+ * triple is the key; duplicates merged, collinear triples dropped); a pixel
+ * belongs to the covering closed triangle of smallest key, else to its Voronoi
+ * cell; cells rank by (sum of round(e * 2^20) descending, key ascending); the
+ * chosen pixel maximises e, ties to the smaller index.
+ *   mask     H x W uint8, in/out (device); at least one pixel set
+ *   err      H x W float32 error map, e >= 0 (device)
+ *   n_add    pixels to add (>= 0)
+ *   added    nullable int32 output (device), capacity n_add: the added
+ *            linear indices in ascending order
+ *   n_added  host output: min(n_add, number of cells with a free pixel)     */
+int32_t densify_step(int32_t width, int32_t height, uint8_t *mask, const float *err, int64_t n_add,
+                     int32_t partition, int32_t *added, int64_t *n_added, void *ws, size_t ws_bytes,
+                     void *stream);
+
 /* Number of 32x32 Schwarz blocks with the given overlap on one level of one
  * channel: per dimension ceil((n - 32) / (32 - overlap)) + 1 (1 if n <= 32),
  * the last block shifted to end at the border (Sec. 3.3). Host-only. */

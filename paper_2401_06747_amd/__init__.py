@@ -15,10 +15,11 @@ import torch
 from . import _lib
 from ._lib import HdiError, check
 
-__all__ = ["inpaint_solve", "tonal_optimize", "hdi_block_count", "SolveParams", "TonalParams", "HdiError",
+__all__ = ["inpaint_solve", "tonal_optimize", "densify_step", "DELAUNAY", "VORONOI", "hdi_block_count", "SolveParams", "TonalParams", "HdiError",
            "PCG_RAS", "RAS", "CGNR"]
 
 PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
+DELAUNAY, VORONOI = _lib.HDI_PART_DELAUNAY, _lib.HDI_PART_VORONOI
 
 
 @dataclass
@@ -140,3 +141,23 @@ def tonal_optimize(f: torch.Tensor, mask: torch.Tensor, g0: torch.Tensor | None 
     if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
         check(st)
     return (g, report, u) if want_u else (g, report)
+
+
+def densify_step(mask: torch.Tensor, err: torch.Tensor, n_add: int, partition: int = DELAUNAY,
+                 ws: torch.Tensor | None = None):
+    """One densification step (Alg. 1). Updates `mask` in place and returns the
+    added linear indices (int32, ascending)."""
+    if mask.dim() != 2 or err.shape != mask.shape or mask.dtype != torch.uint8 or err.dtype != torch.float32:
+        raise ValueError("need mask (H,W) uint8 and err (H,W) float32")
+    if not (mask.is_cuda and err.is_cuda and mask.is_contiguous() and err.is_contiguous()):
+        raise ValueError("mask and err must be contiguous GPU tensors")
+    L = _lib.lib()
+    H, W = mask.shape
+    if ws is None:
+        ws = workspace(L.hdi_densify_workspace_bytes(W, H), mask.device)
+    added = torch.empty(max(int(n_add), 1), dtype=torch.int32, device=mask.device)
+    n = ctypes.c_int64(0)
+    st = L.densify_step(W, H, _ptr(mask), _ptr(err), int(n_add), int(partition), _ptr(added), ctypes.byref(n),
+                        _ptr(ws), ws.numel(), _stream_ptr(mask.device))
+    check(st)
+    return added[:n.value]

@@ -38,6 +38,7 @@ class hdi_tonal_report(ctypes.Structure):
 HDI_TONAL_PCG_RAS, HDI_TONAL_RAS, HDI_TONAL_CGNR = 0, 1, 2
 HDI_TONAL_INIT_FROM_F = 1
 HDI_TONAL_TRACE = 2
+HDI_PART_DELAUNAY, HDI_PART_VORONOI = 0, 1
 
 _P = ctypes.c_void_p
 _SIGS = {
@@ -47,6 +48,9 @@ _SIGS = {
     "hdi_tonal_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
     "tonal_optimize": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                         ctypes.POINTER(hdi_tonal_params), ctypes.POINTER(hdi_tonal_report), _P]),
+    "hdi_densify_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "densify_step": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32, _P,
+                                      ctypes.POINTER(ctypes.c_int64), _P, ctypes.c_size_t, _P]),
     "hdi_block_count": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hdi_stats_enable": (None, [ctypes.c_int32]),
     "hdi_stats_reset": (None, []),

@@ -1,0 +1,475 @@
+// One Delaunay (or Voronoi) densification step (paper Sec. 4.1, Alg. 1) on the
+// GPU, and its C-ABI entry point.
+//
+// Exact discrete reading of the step, all in integer arithmetic so that the
+// result is reproducible bit for bit:
+//   1 labels     nearest mask pixel of every pixel, by (squared distance,
+//                linear index); the paper builds this Voronoi diagram to get
+//                the Delaunay triangulation (Sec. 4.2)
+//   2 triangles  every 2x2 pixel quad whose corners carry three or four
+//                different labels gives one or two triangles of mask pixels;
+//                the sorted index triple is the key, duplicates are merged and
+//                collinear triples dropped
+//   3 ownership  a pixel belongs to the covering closed triangle with the
+//                smallest key, or, if none covers it, to its Voronoi cell
+//   4 errors     cell sums of round(e * 2^20) (64-bit integers)
+//   5 ranking    cells by (sum descending, key ascending)
+//   6 selection  in ranked order, each cell with a free pixel adds its free
+//                pixel of largest error (ties to the smaller index), until
+//                n_add pixels are added (Alg. 1: at most one per triangle)
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <climits>
+
+#include "hdi_internal.h"
+
+namespace hdi {
+
+void launch_compact(int N, const uint8_t *mask, int *chunk_cnt, int *chunk_off, int *total, int *idx, int *pos,
+                    hipStream_t s);
+bool check_image(const hdi_image &img);
+
+constexpr int SEG = 64;   // rows per column segment of the column pass
+
+// ------------------------------------------------------------------ 1 labels
+
+// Nearest mask pixel in the same column, inside one segment of SEG rows;
+// seg_first/seg_last record the first and last mask rows of the segment.
+__global__ void k_col_seg(int W, int H, int nseg, const uint8_t *__restrict__ mask, int *__restrict__ colnear,
+                          int *__restrict__ seg_first, int *__restrict__ seg_last) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= W * nseg) return;
+    const int x = t % W, sg = t / W;
+    const int y0 = sg * SEG, y1 = min(y0 + SEG, H);
+    int last = -1, first = -1;
+    for (int y = y0; y < y1; ++y) {           // downward: nearest at or above
+        if (mask[(size_t)y * W + x]) { last = y; if (first < 0) first = y; }
+        colnear[(size_t)y * W + x] = last;
+    }
+    seg_first[sg * W + x] = first;
+    seg_last[sg * W + x] = last;
+    int below = -1;
+    for (int y = y1 - 1; y >= y0; --y) {       // upward: nearest at or below
+        if (mask[(size_t)y * W + x]) below = y;
+        const int above = colnear[(size_t)y * W + x];
+        int best = above;
+        // (|dy|, row) order: the upper one wins a tie (smaller index)
+        if (below >= 0 && (best < 0 || below - y < y - best)) best = below;
+        colnear[(size_t)y * W + x] = best;
+    }
+}
+
+// Combine with the nearest mask rows outside the segment.
+__global__ void k_col_fix(int W, int H, int nseg, const int *__restrict__ seg_first, const int *__restrict__ seg_last,
+                          int *__restrict__ colnear) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= W * nseg) return;
+    const int x = t % W, sg = t / W;
+    int above = -1, below = -1;
+    for (int k = sg - 1; k >= 0 && above < 0; --k) above = seg_last[k * W + x];
+    for (int k = sg + 1; k < nseg && below < 0; ++k) below = seg_first[k * W + x];
+    if (above < 0 && below < 0) return;
+    const int y0 = sg * SEG, y1 = min(y0 + SEG, H);
+    for (int y = y0; y < y1; ++y) {
+        int best = colnear[(size_t)y * W + x];
+        const int db = best < 0 ? INT_MAX : abs(best - y);
+        int cand = best, dc = db;
+        if (above >= 0 && (y - above < dc || (y - above == dc && above < cand))) { cand = above; dc = y - above; }
+        if (below >= 0 && (below - y < dc || (below - y == dc && below < cand))) { cand = below; dc = below - y; }
+        colnear[(size_t)y * W + x] = cand;
+    }
+}
+
+// label(p) = argmin over columns x' of (dx^2 + dy^2, index) using each column's
+// nearest mask row; scanning outwards from x until dx^2 exceeds the best.
+__global__ void k_labels(int W, int H, const int *__restrict__ colnear, int *__restrict__ labels) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W * H) return;
+    const int x = i % W, y = i / W;
+    long long bd = LLONG_MAX;
+    int bi = INT_MAX;
+    const int *row = colnear + (size_t)y * W;
+    for (int dx = 0; dx < W; ++dx) {
+        const long long dx2 = (long long)dx * dx;
+        if (dx2 > bd) break;
+        const int xs[2] = {x - dx, x + dx};
+        for (int k = 0; k < (dx ? 2 : 1); ++k) {
+            const int xx = xs[k];
+            if (xx < 0 || xx >= W) continue;
+            const int ys = row[xx];
+            if (ys < 0) continue;
+            const long long d = dx2 + (long long)(ys - y) * (ys - y);
+            const int idx = ys * W + xx;
+            if (d < bd || (d == bd && idx < bi)) { bd = d; bi = idx; }
+        }
+    }
+    labels[i] = bi;
+}
+
+// ------------------------------------------------------------------ 2 triangles
+
+__device__ __forceinline__ long long orient(int W, int a, int b, int c) {
+    const long long ax = a % W, ay = a / W, bx = b % W, by = b / W, cx = c % W, cy = c / W;
+    return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+}
+
+__device__ __forceinline__ void emit(int W, int a, int b, int c, unsigned int *count, int *ta, int *tb, int *tc) {
+    // sort the triple
+    if (a > b) { const int t = a; a = b; b = t; }
+    if (b > c) { const int t = b; b = c; c = t; }
+    if (a > b) { const int t = a; a = b; b = t; }
+    if (orient(W, a, b, c) == 0) return;
+    const unsigned int k = atomicAdd(count, 1u);
+    ta[k] = a;
+    tb[k] = b;
+    tc[k] = c;
+}
+
+__global__ void k_quads(int W, int H, const int *__restrict__ labels, unsigned int *__restrict__ count,
+                        int *__restrict__ ta, int *__restrict__ tb, int *__restrict__ tc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (W - 1) * (H - 1)) return;
+    const int x = i % (W - 1), y = i / (W - 1);
+    const int l0 = labels[y * W + x], l1 = labels[y * W + x + 1];
+    const int l2 = labels[(y + 1) * W + x + 1], l3 = labels[(y + 1) * W + x];
+    const int nd = 1 + (l1 != l0) + (l2 != l0 && l2 != l1) + (l3 != l0 && l3 != l1 && l3 != l2);
+    if (nd == 4) {
+        emit(W, l0, l1, l2, count, ta, tb, tc);
+        emit(W, l0, l2, l3, count, ta, tb, tc);
+    } else if (nd == 3) {
+        // the three distinct labels
+        int a = l0, b, c;
+        b = (l1 != a) ? l1 : l2;
+        const int cands[3] = {l1, l2, l3};
+        c = a;
+        for (int k = 0; k < 3; ++k)
+            if (cands[k] != a && cands[k] != b) c = cands[k];
+        emit(W, a, b, c, count, ta, tb, tc);
+    }
+}
+
+__global__ void k_iota(int n, int *__restrict__ v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = i;
+}
+
+__global__ void k_key_c(int n, const int *__restrict__ tc, unsigned int *__restrict__ key) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) key[i] = (unsigned int)tc[i];
+}
+
+__global__ void k_key_ab(int n, const int *__restrict__ order, const int *__restrict__ ta, const int *__restrict__ tb,
+                         unsigned long long *__restrict__ key) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int j = order[i];
+        key[i] = ((unsigned long long)(unsigned int)ta[j] << 32) | (unsigned int)tb[j];
+    }
+}
+
+// flag[i] = 1 if the i-th triangle in sorted order differs from the previous
+__global__ void k_uniq_flags(int n, const int *__restrict__ order, const int *__restrict__ ta,
+                             const int *__restrict__ tb, const int *__restrict__ tc, int *__restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = order[i];
+    int f = 1;
+    if (i > 0) {
+        const int k = order[i - 1];
+        f = (ta[j] != ta[k]) || (tb[j] != tb[k]) || (tc[j] != tc[k]);
+    }
+    flag[i] = f;
+}
+
+__global__ void k_uniq_scatter(int n, const int *__restrict__ order, const int *__restrict__ flag,
+                               const int *__restrict__ off, const int *__restrict__ ta, const int *__restrict__ tb,
+                               const int *__restrict__ tc, int *__restrict__ ua, int *__restrict__ ub,
+                               int *__restrict__ uc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const int j = order[i], r = off[i];
+    ua[r] = ta[j];
+    ub[r] = tb[j];
+    uc[r] = tc[j];
+}
+
+// ------------------------------------------------------------------ 3 ownership
+
+__global__ void k_fill_i32(int n, int v, int *__restrict__ p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(int n, unsigned long long *__restrict__ p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Closed-triangle coverage with the smallest rank winning (ranks follow the
+// key order). One thread per triangle walks its bounding box.
+__global__ void k_raster(int W, int T, const int *__restrict__ ua, const int *__restrict__ ub,
+                         const int *__restrict__ uc, int *__restrict__ owner) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= T) return;
+    long long ax = ua[r] % W, ay = ua[r] / W, bx = ub[r] % W, by = ub[r] / W, cx = uc[r] % W, cy = uc[r] / W;
+    if ((bx - ax) * (cy - ay) - (by - ay) * (cx - ax) < 0) {
+        long long t = bx; bx = cx; cx = t;
+        t = by; by = cy; cy = t;
+    }
+    const long long x0 = min(ax, min(bx, cx)), x1 = max(ax, max(bx, cx));
+    const long long y0 = min(ay, min(by, cy)), y1 = max(ay, max(by, cy));
+    for (long long y = y0; y <= y1; ++y)
+        for (long long x = x0; x <= x1; ++x) {
+            const long long e0 = (bx - ax) * (y - ay) - (by - ay) * (x - ax);
+            const long long e1 = (cx - bx) * (y - by) - (cy - by) * (x - bx);
+            const long long e2 = (ax - cx) * (y - cy) - (ay - cy) * (x - cx);
+            if (e0 >= 0 && e1 >= 0 && e2 >= 0) atomicMin(&owner[y * W + x], r);
+        }
+}
+
+// ------------------------------------------------------------------ 4 cell errors and argmax
+
+__global__ void k_cells(int N, int T, const int *__restrict__ owner, const int *__restrict__ labels,
+                        const int *__restrict__ seed_pos, const uint8_t *__restrict__ mask, const float *__restrict__ err,
+                        unsigned long long *__restrict__ E, unsigned long long *__restrict__ best) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int o = owner ? owner[i] : INT_MAX;
+    const int cell = o < T ? o : T + seed_pos[labels[i]];
+    const float e = err[i];
+    const unsigned long long q = (unsigned long long)rint(ldexp((double)e, 20));
+    if (q) atomicAdd(&E[cell], q);
+    if (!mask[i]) {
+        // larger error first, then smaller index; e >= 0 so its bits order like its value
+        const unsigned long long key = ((unsigned long long)__float_as_uint(e) << 32) | (0xFFFFFFFFu - (unsigned)i);
+        atomicMax(&best[cell], key);
+    }
+}
+
+__global__ void k_rank_keys(int n, const unsigned long long *__restrict__ E, unsigned long long *__restrict__ key) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) key[i] = ~E[i];
+}
+
+// ------------------------------------------------------------------ 6 selection
+
+__global__ void k_nonempty(int n, const int *__restrict__ order, const unsigned long long *__restrict__ best,
+                           int *__restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = best[order[i]] != 0ull;
+}
+
+__global__ void k_select(int n, long long n_add, const int *__restrict__ order, const unsigned long long *__restrict__ best,
+                         const int *__restrict__ flag, const int *__restrict__ off, uint8_t *__restrict__ newpix) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i] || off[i] >= n_add) return;
+    const unsigned int p = 0xFFFFFFFFu - (unsigned int)(best[order[i]] & 0xFFFFFFFFull);
+    newpix[p] = 1;
+}
+
+__global__ void k_apply(int N, const uint8_t *__restrict__ newpix, uint8_t *__restrict__ mask) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && newpix[i]) mask[i] = 1;
+}
+
+__global__ void k_copy_i32(int n, const int *__restrict__ a, int *__restrict__ b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// ------------------------------------------------------------------ host
+
+struct DensWs {
+    int *colnear, *seg_first, *seg_last, *labels, *owner;
+    int *seed_idx, *seed_pos, *chunk_cnt, *chunk_off, *total;
+    int *ta, *tb, *tc, *ua, *ub, *uc;
+    int *ord0, *ord1, *flag, *off;
+    unsigned int *keyc0, *keyc1, *count;
+    unsigned long long *keyab0, *keyab1, *E, *best, *rk0, *rk1;
+    uint8_t *newpix;
+    void *tmp;
+    size_t tmp_bytes;
+};
+
+static size_t cub_tmp_bytes(int maxn) {
+    size_t a = 0, b = 0, c = 0, d = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, a, (unsigned int *)nullptr, (unsigned int *)nullptr,
+                                             (int *)nullptr, (int *)nullptr, maxn);
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
+                                             (int *)nullptr, (int *)nullptr, maxn);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, c, (int *)nullptr, (int *)nullptr, maxn);
+    d = std::max(std::max(a, b), c);
+    return d;
+}
+
+static bool plan_densify(DensWs &d, Arena &a, int W, int H) {
+    const size_t N = (size_t)W * H;
+    const int nseg = (H + SEG - 1) / SEG;
+    const size_t maxT = 2 * (size_t)std::max(W - 1, 1) * std::max(H - 1, 1);
+    const size_t maxC = maxT + N;   // triangles + Voronoi cells
+    d.colnear = (int *)a.take(N * 4);
+    d.seg_first = (int *)a.take((size_t)nseg * W * 4);
+    d.seg_last = (int *)a.take((size_t)nseg * W * 4);
+    d.labels = (int *)a.take(N * 4);
+    d.owner = (int *)a.take(N * 4);
+    d.seed_idx = (int *)a.take(N * 4);
+    d.seed_pos = (int *)a.take(N * 4);
+    d.chunk_cnt = (int *)a.take(((N + 1023) / 1024) * 4);
+    d.chunk_off = (int *)a.take(((N + 1023) / 1024) * 4);
+    d.total = (int *)a.take(16);
+    int **t3[] = {&d.ta, &d.tb, &d.tc, &d.ua, &d.ub, &d.uc};
+    for (int **p : t3) *p = (int *)a.take(maxT * 4);
+    d.ord0 = (int *)a.take(maxC * 4);
+    d.ord1 = (int *)a.take(maxC * 4);
+    d.flag = (int *)a.take(maxC * 4);
+    d.off = (int *)a.take(maxC * 4);
+    d.keyc0 = (unsigned int *)a.take(maxT * 4);
+    d.keyc1 = (unsigned int *)a.take(maxT * 4);
+    d.count = (unsigned int *)a.take(16);
+    d.keyab0 = (unsigned long long *)a.take(maxT * 8);
+    d.keyab1 = (unsigned long long *)a.take(maxT * 8);
+    d.E = (unsigned long long *)a.take(maxC * 8);
+    d.best = (unsigned long long *)a.take(maxC * 8);
+    d.rk0 = (unsigned long long *)a.take(maxC * 8);
+    d.rk1 = (unsigned long long *)a.take(maxC * 8);
+    d.newpix = (uint8_t *)a.take((N + 3) & ~(size_t)3);   // zeroed in 4-byte words
+    d.tmp_bytes = cub_tmp_bytes((int)maxC);
+    d.tmp = a.take(d.tmp_bytes);
+    return a.base == nullptr || a.used <= a.size;
+}
+
+static size_t densify_ws_bytes(int W, int H) {
+    DensWs d;
+    Arena a{nullptr, 0, 0};
+    plan_densify(d, a, W, H);
+    return a.used + 256;
+}
+
+#define D_TRY(expr)                                                                                  \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) {                                                                      \
+            set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__);   \
+            return HDI_ERR_HIP;                                                                      \
+        }                                                                                            \
+    } while (0)
+
+static inline dim3 gd(long n) { return dim3((unsigned)std::max<long>(1, (n + 255) / 256)); }
+
+static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *err, long long n_add, int partition,
+                           int32_t *added, int64_t *n_added, hipStream_t s) {
+    const int N = W * H;
+    const int nseg = (H + SEG - 1) / SEG;
+    // seeds in ascending order (the Voronoi cell order) and their ranks
+    launch_compact(N, mask, d.chunk_cnt, d.chunk_off, d.total, d.seed_idx, d.seed_pos, s);
+    int m = 0;
+    D_TRY(hipMemcpyAsync(&m, d.total, sizeof(int), hipMemcpyDeviceToHost, s));
+    D_TRY(hipStreamSynchronize(s));
+    if (m == 0) {
+        set_error("empty mask: densification needs at least one mask pixel");
+        return HDI_ERR_EMPTY_MASK;
+    }
+    // 1 labels
+    hipLaunchKernelGGL(k_col_seg, gd((long)W * nseg), dim3(256), 0, s, W, H, nseg, mask, d.colnear, d.seg_first,
+                       d.seg_last);
+    hipLaunchKernelGGL(k_col_fix, gd((long)W * nseg), dim3(256), 0, s, W, H, nseg, d.seg_first, d.seg_last,
+                       d.colnear);
+    hipLaunchKernelGGL(k_labels, gd(N), dim3(256), 0, s, W, H, d.colnear, d.labels);
+    int T = 0;
+    if (partition == HDI_PART_DELAUNAY && W > 1 && H > 1) {
+        // 2 triangles: emit, sort by (a, b, c) with two stable radix passes, merge duplicates
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, 1, 0, (int *)d.count);
+        hipLaunchKernelGGL(k_quads, gd((long)(W - 1) * (H - 1)), dim3(256), 0, s, W, H, d.labels, d.count, d.ta, d.tb,
+                           d.tc);
+        unsigned int nt = 0;
+        D_TRY(hipMemcpyAsync(&nt, d.count, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        D_TRY(hipStreamSynchronize(s));
+        if (nt > 0) {
+            const int n = (int)nt;
+            hipLaunchKernelGGL(k_iota, gd(n), dim3(256), 0, s, n, d.ord0);
+            hipLaunchKernelGGL(k_key_c, gd(n), dim3(256), 0, s, n, d.tc, d.keyc0);
+            size_t tb = d.tmp_bytes;
+            D_TRY(hipcub::DeviceRadixSort::SortPairs(d.tmp, tb, d.keyc0, d.keyc1, d.ord0, d.ord1, n, 0, 32, s));
+            hipLaunchKernelGGL(k_key_ab, gd(n), dim3(256), 0, s, n, d.ord1, d.ta, d.tb, d.keyab0);
+            tb = d.tmp_bytes;
+            D_TRY(hipcub::DeviceRadixSort::SortPairs(d.tmp, tb, d.keyab0, d.keyab1, d.ord1, d.ord0, n, 0, 64, s));
+            hipLaunchKernelGGL(k_uniq_flags, gd(n), dim3(256), 0, s, n, d.ord0, d.ta, d.tb, d.tc, d.flag);
+            tb = d.tmp_bytes;
+            D_TRY(hipcub::DeviceScan::ExclusiveSum(d.tmp, tb, d.flag, d.off, n, s));
+            hipLaunchKernelGGL(k_uniq_scatter, gd(n), dim3(256), 0, s, n, d.ord0, d.flag, d.off, d.ta, d.tb, d.tc,
+                               d.ua, d.ub, d.uc);
+            int last_off = 0, last_flag = 0;
+            D_TRY(hipMemcpyAsync(&last_off, d.off + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+            D_TRY(hipMemcpyAsync(&last_flag, d.flag + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+            D_TRY(hipStreamSynchronize(s));
+            T = last_off + last_flag;
+        }
+        // 3 ownership
+        hipLaunchKernelGGL(k_fill_i32, gd(N), dim3(256), 0, s, N, INT_MAX, d.owner);
+        if (T > 0) hipLaunchKernelGGL(k_raster, gd(T), dim3(256), 0, s, W, T, d.ua, d.ub, d.uc, d.owner);
+    }
+    // 4 cell sums and argmax
+    const int ncell = T + m;
+    hipLaunchKernelGGL(k_fill_u64, gd(ncell), dim3(256), 0, s, ncell, d.E);
+    hipLaunchKernelGGL(k_fill_u64, gd(ncell), dim3(256), 0, s, ncell, d.best);
+    hipLaunchKernelGGL(k_cells, gd(N), dim3(256), 0, s, N, T, T > 0 ? d.owner : (const int *)nullptr, d.labels,
+                       d.seed_pos, mask, err, d.E, d.best);
+    // 5 ranking: E descending, cell order ascending (stable radix sort of ~E)
+    hipLaunchKernelGGL(k_rank_keys, gd(ncell), dim3(256), 0, s, ncell, d.E, d.rk0);
+    hipLaunchKernelGGL(k_iota, gd(ncell), dim3(256), 0, s, ncell, d.ord0);
+    size_t tb = d.tmp_bytes;
+    D_TRY(hipcub::DeviceRadixSort::SortPairs(d.tmp, tb, d.rk0, d.rk1, d.ord0, d.ord1, ncell, 0, 64, s));
+    // 6 selection
+    hipLaunchKernelGGL(k_nonempty, gd(ncell), dim3(256), 0, s, ncell, d.ord1, d.best, d.flag);
+    tb = d.tmp_bytes;
+    D_TRY(hipcub::DeviceScan::ExclusiveSum(d.tmp, tb, d.flag, d.off, ncell, s));
+    hipLaunchKernelGGL(k_fill_i32, gd((N + 3) / 4), dim3(256), 0, s, (N + 3) / 4, 0, (int *)d.newpix);
+    hipLaunchKernelGGL(k_select, gd(ncell), dim3(256), 0, s, ncell, n_add, d.ord1, d.best, d.flag, d.off, d.newpix);
+    hipLaunchKernelGGL(k_apply, gd(N), dim3(256), 0, s, N, d.newpix, mask);
+    // added pixels in ascending order: compaction of the new-pixel flags
+    launch_compact(N, d.newpix, d.chunk_cnt, d.chunk_off, d.total, d.seed_idx, d.seed_pos, s);
+    int na = 0;
+    D_TRY(hipMemcpyAsync(&na, d.total, sizeof(int), hipMemcpyDeviceToHost, s));
+    D_TRY(hipStreamSynchronize(s));
+    if (added && na > 0) hipLaunchKernelGGL(k_copy_i32, gd(na), dim3(256), 0, s, na, d.seed_idx, added);
+    D_TRY(hipGetLastError());
+    D_TRY(hipStreamSynchronize(s));
+    *n_added = na;
+    return HDI_OK;
+}
+
+}  // namespace hdi
+
+using namespace hdi;
+
+extern "C" {
+
+size_t hdi_densify_workspace_bytes(int32_t width, int32_t height) {
+    if (width < 1 || height < 1 || (int64_t)width * height > (int64_t)1 << 30) return 0;
+    return densify_ws_bytes(width, height);
+}
+
+int32_t densify_step(int32_t width, int32_t height, uint8_t *mask, const float *err, int64_t n_add,
+                     int32_t partition, int32_t *added, int64_t *n_added, void *ws, size_t ws_bytes, void *stream) {
+    hdi_image img{width, height, 1};
+    if (!check_image(img)) return HDI_ERR_ARG;
+    if (!mask || !err || !n_added) {
+        set_error("mask, err and n_added must be non-null");
+        return HDI_ERR_ARG;
+    }
+    if (n_add < 0 || (partition != HDI_PART_DELAUNAY && partition != HDI_PART_VORONOI)) {
+        set_error("n_add must be >= 0 and partition HDI_PART_DELAUNAY or HDI_PART_VORONOI");
+        return HDI_ERR_ARG;
+    }
+    const size_t need = densify_ws_bytes(width, height);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
+        return HDI_ERR_WORKSPACE;
+    }
+    Arena a{(char *)ws, ws_bytes, 0};
+    DensWs d;
+    plan_densify(d, a, width, height);
+    return run_densify(d, width, height, mask, err, n_add, partition, added, n_added, (hipStream_t)stream);
+}
+
+}  // extern "C"
