@@ -24,6 +24,26 @@ KERNEL_NAMES = ["fp64_residual", "schwarz_pre", "schwarz_post", "restrict_residu
                 "tonal_ras_sweep", "tonal_vector_ops"]
 ALU_BOUND = {"schwarz_pre", "schwarz_post", "tonal_ras_sweep"}
 
+# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# summarised in profiles/bench_4k_rgb_inpaint_tonal_hbm_counters.md (read =
+# 2 x FETCH_SIZE, written = WRITE_SIZE, by the 1 GiB copy calibration). Valid
+# only while the kernel's source file is unchanged, checked by its SHA-256.
+TRAFFIC = {
+    "tonal_ras_sweep": {"read": 2 * 65115.68 * 1024, "written": 5834.72 * 1024,
+                        "source": "paper_2401_06747_amd/csrc/tonal_kernels.hip", "sha256": "3f4ec511d953106c"},
+    "schwarz_post": {"read": 2 * 124794.56 * 1024, "written": 97261.85 * 1024,
+                     "source": "paper_2401_06747_amd/csrc/solver_kernels.hip", "sha256": "bb576be601c9a812"},
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    h = hashlib.sha256(open(os.path.join(ROOT, t["source"]), "rb").read()).hexdigest()[:16]
+    return round(t["read"] + t["written"]) if h == t["sha256"] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -86,13 +106,13 @@ def roofline_of(ks):
     if dom in ALU_BOUND:
         achieved = fl / (ms * 1e-3) / 1e12
         r = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-             "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": dom,
+             "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dom), "kernel": dom,
              "avg_us": round(ms / n * 1e3, 2), "alg_flops_per_launch": round(fl / n),
              "alg_bytes_per_launch": round(by / n)}
     else:
         achieved = by / (ms * 1e-3) / 1e9
         r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom,
+             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
              "avg_us": round(ms / n * 1e3, 2), "alg_bytes_per_launch": round(by / n)}
     r["share_of_kernel_time"] = round(ms / sum(v[1] for v in ks.values()), 3)
     return r
