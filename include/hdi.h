@@ -102,6 +102,32 @@ int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double
                       const double *u0, void *ws, size_t ws_bytes,
                       const hdi_solve_params *params, hdi_solve_report *report, void *stream);
 
+/* ------------------------------------------------------------------ batches */
+
+/* One inpainting job of a batch: image shape and device pointers as for
+ * inpaint_solve (mask H x W uint8, f C x H x W float32, u C x H x W float64). */
+typedef struct {
+    hdi_image img;
+    const uint8_t *mask;
+    const float *f;
+    double *u;
+} hdi_job;
+
+/* Bytes of workspace hdi_solve_batch needs for these jobs. 0 on bad input. */
+size_t hdi_batch_workspace_bytes(int32_t n, const hdi_job *jobs);
+
+/* Inpainting (eq. inp-discrete-lsi) of n images of any sizes in shared
+ * launches: every phase of the solve is one kernel launch over the work items
+ * (image, level, block) of all images taking part, and each image refines
+ * until its own tolerance. An image's result is bit-for-bit what inpaint_solve
+ * returns for it with the same parameters, whatever else is in the batch.
+ *   params   nullable array of n per-job parameter sets (all with one overlap)
+ *   reports  nullable host array of n reports
+ * Returns the first failing job's status (HDI_ERR_EMPTY_MASK for an empty
+ * mask, before any solve; HDI_ERR_NO_CONVERGENCE with the last iterates). */
+int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_bytes,
+                        const hdi_solve_params *params, hdi_solve_report *reports, void *stream);
+
 /* ------------------------------------------------------------------ tonal */
 
 #define HDI_TONAL_PCG_RAS 0   /* flexible CG, one RAS sweep as preconditioner (default) */

@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import HdiError, check
 
-__all__ = ["inpaint_solve", "tonal_optimize", "densify_step", "DELAUNAY", "VORONOI", "hdi_block_count", "SolveParams", "TonalParams", "HdiError",
+__all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "DELAUNAY", "VORONOI", "hdi_block_count", "SolveParams", "TonalParams", "HdiError",
            "PCG_RAS", "RAS", "CGNR"]
 
 PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
@@ -161,3 +161,32 @@ def densify_step(mask: torch.Tensor, err: torch.Tensor, n_add: int, partition: i
                         _ptr(ws), ws.numel(), _stream_ptr(mask.device))
     check(st)
     return added[:n.value]
+
+
+def solve_batch(fs, masks, params=None, ws: torch.Tensor | None = None, outs=None):
+    """Inpaint a list of images in shared launches (hdi_solve_batch). Returns
+    (list of u float64, list of report dicts)."""
+    n = len(fs)
+    if n == 0 or len(masks) != n:
+        raise ValueError("need equally many images and masks")
+    for f, m in zip(fs, masks):
+        _check_inputs(f, m)
+    L = _lib.lib()
+    us = outs if outs is not None else [torch.empty(f.shape, dtype=torch.float64, device=f.device) for f in fs]
+    jobs = (_lib.hdi_job * n)(*[_lib.hdi_job(_img(f.shape), m.data_ptr(), f.data_ptr(), u.data_ptr())
+                                for f, m, u in zip(fs, masks, us)])
+    need = L.hdi_batch_workspace_bytes(n, jobs)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, fs[0].device)
+    if params is None:
+        pc = None
+    else:
+        plist = params if isinstance(params, (list, tuple)) else [params] * n
+        pc = (_lib.hdi_solve_params * n)(*[p.c() for p in plist])
+    reps = (_lib.hdi_solve_report * n)()
+    st = L.hdi_solve_batch(n, jobs, _ptr(ws), ws.numel(), pc, reps, _stream_ptr(fs[0].device))
+    reports = [{"status": st, "rel_residual": list(r.rel_residual)[:f.shape[0]], "outer_iters": r.outer_iters,
+                "vcycles": r.vcycles, "ms": r.ms} for r, f in zip(reps, fs)]
+    if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
+        check(st)
+    return us, reports

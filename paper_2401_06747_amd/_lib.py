@@ -23,6 +23,10 @@ class hdi_solve_report(ctypes.Structure):
                 ("vcycles", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
+class hdi_job(ctypes.Structure):
+    _fields_ = [("img", hdi_image), ("mask", ctypes.c_void_p), ("f", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
 class hdi_tonal_params(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("local_outer", ctypes.c_int32), ("local_inner", ctypes.c_int32),
@@ -45,6 +49,9 @@ _SIGS = {
     "hdi_inpaint_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
     "inpaint_solve": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                        ctypes.POINTER(hdi_solve_params), ctypes.POINTER(hdi_solve_report), _P]),
+    "hdi_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(hdi_job)]),
+    "hdi_solve_batch": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(hdi_job), _P, ctypes.c_size_t,
+                                         ctypes.POINTER(hdi_solve_params), ctypes.POINTER(hdi_solve_report), _P]),
     "hdi_tonal_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
     "tonal_optimize": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                         ctypes.POINTER(hdi_tonal_params), ctypes.POINTER(hdi_tonal_report), _P]),

@@ -117,6 +117,41 @@ void launch_smooth_fmg(const Level &L, int C, int iters, const float *e_in, floa
 // into counts[0..nlev) (counts must hold MAX_LEVELS entries).
 void launch_mask_pyramid(const Hierarchy &h, int nlev, unsigned int *counts, hipStream_t s);
 
+// ------------------------------------------------------------------ batched solves
+// Descriptor of one level of one image in a batch (device table [img][MAX_LEVELS]).
+struct BLev {
+    int W, H, ntx, nty, sx, sy;
+    int Wc, Hc;                 // next coarser level (0 x 0 on the last level)
+    const uint8_t *mask;
+    uint8_t *mask_c;            // next level's mask
+    float *r, *ea, *eb, *aux;   // this level's buffers
+    float *r_c, *aux_c;         // next level's right-hand side and FMG data
+    const float *ec;            // next level's final correction (post-smoothing input)
+};
+// Descriptor of one image in a batch.
+struct BImg {
+    int W, H, C, nlev, local_iters, coarse_iters, gx, nblk;
+    const uint8_t *mask;
+    const float *f;
+    double *u, *u_alt, *partials, *norms;
+    unsigned int *counts;
+};
+// Work items are int4: tile kernels {img, level, block, channel}; point
+// kernels {img, level, chunk of 256, 0}; residual {img, bx, by, 0};
+// counting {img, level, block, nblocks}; reduction {img, channel, 0, 0}.
+void launch_b_count(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s);
+void launch_b_init_u(const int4 *items, int n, const BImg *I, const uint8_t *active, hipStream_t s);
+void launch_b_residual(const int4 *items, int n, int C, const BImg *I, const uint8_t *active, int use_e,
+                       int parity, const BLev *L, hipStream_t s);
+void launch_b_reduce(const int4 *items, int n, const BImg *I, const uint8_t *active, hipStream_t s);
+// MODE 0 pre-smoothing (coarsest: uses coarse_iters), 1 post, 2 FMG (coarsest: e_in = aux)
+void launch_b_schwarz(int mode, bool coarsest, const int4 *items, int n, const BLev *L, const BImg *I,
+                      const uint8_t *active, hipStream_t s);
+void launch_b_restrict(const int4 *items, int n, const BLev *L, const BImg *I, const uint8_t *active, hipStream_t s);
+void launch_b_data_restrict(bool from_f, const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s);
+void launch_b_fmg_prolong(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s);
+void launch_b_fmg_prolong0(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s);
+
 // Coarse masks, known counts and the number of levels for a new mask.
 int32_t prepare_mask(Hierarchy &h, hipStream_t s);
 

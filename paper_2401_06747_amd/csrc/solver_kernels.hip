@@ -71,15 +71,21 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 
 // u = u0 (or 0) on unknown pixels, u = data exactly on known pixels.
 template <typename TD>
-__global__ void k_init_u(int N, int C, const uint8_t *__restrict__ mask, const TD *__restrict__ data,
-                         const double *__restrict__ u0, double *__restrict__ u) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void init_u_at(int i, int N, int C, const uint8_t *__restrict__ mask,
+                                          const TD *__restrict__ data, const double *__restrict__ u0,
+                                          double *__restrict__ u) {
     if (i >= N) return;
     const bool known = mask[i] != 0;
     for (int c = 0; c < C; ++c) {
         const size_t j = (size_t)c * N + i;
         u[j] = known ? (data ? (double)data[j] : 0.0) : (u0 ? u0[j] : 0.0);
     }
+}
+
+template <typename TD>
+__global__ void k_init_u(int N, int C, const uint8_t *__restrict__ mask, const TD *__restrict__ data,
+                         const double *__restrict__ u0, double *__restrict__ u) {
+    init_u_at<TD>(blockIdx.x * blockDim.x + threadIdx.x, N, C, mask, data, u0, u);
 }
 
 // Fused refinement step and FP64 residual. With e != nullptr the iterate is
@@ -111,18 +117,19 @@ __device__ __forceinline__ double wave_from_right(double v) {  // value of lane 
 }
 
 template <typename TD, int C>
-__global__ void __launch_bounds__(RED_THREADS)
-k_residual(int W, int H, const uint8_t *__restrict__ mask, const double *__restrict__ u_in,
-           const float *__restrict__ e, double *__restrict__ u_out, const TD *__restrict__ data,
-           const double *__restrict__ src, float *__restrict__ r, double *__restrict__ partials, int nblk) {
+__device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__restrict__ mask,
+                                               const double *__restrict__ u_in, const float *__restrict__ e,
+                                               double *__restrict__ u_out, const TD *__restrict__ data,
+                                               const double *__restrict__ src, float *__restrict__ r,
+                                               double *__restrict__ partials, int nblk, int bx, int by, int gx) {
     const int N = W * H;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int x = (blockIdx.x * (RED_THREADS / 64) + wid) * RES_COLS + lane - 1;
+    const int x = (bx * (RED_THREADS / 64) + wid) * RES_COLS + lane - 1;
     const int xs = min(max(x, 0), W - 1);
     const bool owner = lane >= 1 && lane <= RES_COLS && x < W;
     const double wl = x > 0, wr = x < W - 1;
-    const int y0 = blockIdx.y * RES_BAND, y1 = min(y0 + RES_BAND, H);
-    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    const int y0 = by * RES_BAND, y1 = min(y0 + RES_BAND, H);
+    const int bid = by * gx + bx;
 
     // Rows of u (+ e) at column xs: prev (y-1), cur (y), next (y+1), and the
     // prefetched y+2; mask rows y and y+1; data/src of row y. Loads are issued
@@ -213,12 +220,20 @@ k_residual(int W, int H, const uint8_t *__restrict__ mask, const double *__restr
     }
 }
 
+template <typename TD, int C>
+__global__ void __launch_bounds__(RED_THREADS)
+k_residual(int W, int H, const uint8_t *__restrict__ mask, const double *__restrict__ u_in,
+           const float *__restrict__ e, double *__restrict__ u_out, const TD *__restrict__ data,
+           const double *__restrict__ src, float *__restrict__ r, double *__restrict__ partials, int nblk) {
+    residual_block<TD, C>(W, H, mask, u_in, e, u_out, data, src, r, partials, nblk, blockIdx.x, blockIdx.y,
+                          gridDim.x);
+}
+
 // Second stage of the fixed-order reduction: one workgroup of 1024 threads per
 // channel; thread t sums partials t, t+1024, ... in order, then waves and the
 // 16 wave sums are combined in a fixed order.
-__global__ void __launch_bounds__(1024)
-k_reduce_partials(int nblk, const double *__restrict__ partials, double *__restrict__ norms) {
-    const int c = blockIdx.x;
+__device__ __forceinline__ void reduce_partials_block(int nblk, const double *__restrict__ partials,
+                                                      double *__restrict__ norms, int c) {
     double a = 0.0, b = 0.0;
     const double2 *pp = reinterpret_cast<const double2 *>(partials) + (size_t)c * nblk;
 #pragma unroll 4
@@ -238,6 +253,11 @@ k_reduce_partials(int nblk, const double *__restrict__ partials, double *__restr
         norms[c * 2 + 0] = x;
         norms[c * 2 + 1] = y;
     }
+}
+
+__global__ void __launch_bounds__(1024)
+k_reduce_partials(int nblk, const double *__restrict__ partials, double *__restrict__ norms) {
+    reduce_partials_block(nblk, partials, norms, blockIdx.x);
 }
 
 // u += e on unknown pixels (iterative refinement step, FP64).
@@ -266,11 +286,11 @@ __device__ __forceinline__ void block_count_add(unsigned int local, unsigned int
 // Coarse mask: a coarse pixel is known if any of its (up to) four fine pixels
 // is known (Sec. 3.3). Also counts the known coarse pixels. Grid-stride loop
 // over coarse pixels, 256 threads per workgroup.
-__global__ void __launch_bounds__(256)
-k_mask_restrict(int W, int H, const uint8_t *__restrict__ m, int Wc, int Hc, uint8_t *__restrict__ mc,
-                unsigned int *__restrict__ count) {
+__device__ __forceinline__ void mask_restrict_block(int W, int H, const uint8_t *__restrict__ m, int Wc, int Hc,
+                                                    uint8_t *__restrict__ mc, unsigned int *__restrict__ count,
+                                                    int blk, int nblks) {
     unsigned int local = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Wc * Hc; i += gridDim.x * blockDim.x) {
+    for (int i = blk * 256 + threadIdx.x; i < Wc * Hc; i += nblks * 256) {
         const int X = i % Wc, Y = i / Wc;
         uint8_t k = 0;
         for (int j = 0; j < 2; ++j)
@@ -284,12 +304,23 @@ k_mask_restrict(int W, int H, const uint8_t *__restrict__ m, int Wc, int Hc, uin
     block_count_add(local, count);
 }
 
+__global__ void __launch_bounds__(256)
+k_mask_restrict(int W, int H, const uint8_t *__restrict__ m, int Wc, int Hc, uint8_t *__restrict__ mc,
+                unsigned int *__restrict__ count) {
+    mask_restrict_block(W, H, m, Wc, Hc, mc, count, blockIdx.x, gridDim.x);
+}
+
 // Known pixels of the finest mask.
+__device__ __forceinline__ void count_known_block(int N, const uint8_t *__restrict__ m, unsigned int *__restrict__ count,
+                                                  int blk, int nblks) {
+    unsigned int local = 0;
+    for (int i = blk * 256 + threadIdx.x; i < N; i += nblks * 256) local += m[i] != 0;
+    block_count_add(local, count);
+}
+
 __global__ void __launch_bounds__(256)
 k_count_known(int N, const uint8_t *__restrict__ m, unsigned int *__restrict__ count) {
-    unsigned int local = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) local += m[i] != 0;
-    block_count_add(local, count);
+    count_known_block(N, m, count, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_zero_u32(int n, unsigned int *p) {
@@ -301,10 +332,9 @@ __global__ void k_zero_u32(int n, unsigned int *p) {
 // residual r - A e (the coarse operator is the same stencil on the coarse grid,
 // so summing four children scales the averaged residual by H^2/h^2 = 4).
 // Zero on coarse known pixels, where the coarse correction is pinned.
-__global__ void k_restrict_residual(int W, int H, int C, const uint8_t *__restrict__ m,
-                                    const float *__restrict__ r, const float *__restrict__ e,
-                                    int Wc, int Hc, const uint8_t *__restrict__ mc, float *__restrict__ rc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void restrict_residual_at(int i, int W, int H, int C, const uint8_t *__restrict__ m,
+                                                     const float *__restrict__ r, const float *__restrict__ e, int Wc,
+                                                     int Hc, const uint8_t *__restrict__ mc, float *__restrict__ rc) {
     if (i >= Wc * Hc) return;
     const int X = i % Wc, Y = i / Wc;
     const int N = W * H, Nc = Wc * Hc;
@@ -331,6 +361,12 @@ __global__ void k_restrict_residual(int W, int H, int C, const uint8_t *__restri
         }
         rc[(size_t)c * Nc + i] = acc;
     }
+}
+
+__global__ void k_restrict_residual(int W, int H, int C, const uint8_t *__restrict__ m,
+                                    const float *__restrict__ r, const float *__restrict__ e,
+                                    int Wc, int Hc, const uint8_t *__restrict__ mc, float *__restrict__ rc) {
+    restrict_residual_at(blockIdx.x * blockDim.x + threadIdx.x, W, H, C, m, r, e, Wc, Hc, mc, rc);
 }
 
 // Cell-centred bilinear prolongation weights: fine x maps to coarse position
@@ -368,18 +404,15 @@ constexpr int LDS_W = 40;   // row pitch of the LDS tiles (floats), 16-byte alig
 constexpr int COL0 = 4;     // LDS column of block column 0 (col 3 and 36 are the halo)
 
 template <int MODE>
-__global__ void __launch_bounds__(64)
-k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
-          const uint8_t *__restrict__ mask, const float *__restrict__ r, const float *__restrict__ e_in,
-          const float *__restrict__ ec, int Wc, int Hc, float *__restrict__ e_out) {
+__device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, int sx, int sy, int iters,
+                                              const uint8_t *__restrict__ mask, const float *__restrict__ r,
+                                              const float *__restrict__ e_in, const float *__restrict__ ec, int Wc,
+                                              int Hc, float *__restrict__ e_out, const int t, const int c) {
     __shared__ __attribute__((aligned(16))) float s_p[TILE + 2][LDS_W];
     __shared__ __attribute__((aligned(16))) float s_e[TILE + 2][LDS_W];
     __shared__ uint8_t s_m[TILE + 2][TILE + 2];
     __shared__ float s_c[20][20];   // coarse correction around the block (MODE 1)
 
-    const int ntiles = ntx * nty;
-    const int t = xcd_remap(blockIdx.x, ntiles);
-    const int c = blockIdx.y;
     const int tx = t % ntx, ty = t / ntx;
     const int Tx = min(TILE, W), Ty = min(TILE, H);
     const int x0 = min(tx * sx, W - Tx), y0 = min(ty * sy, H - Ty);
@@ -557,14 +590,23 @@ k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
         }
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(64)
+k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
+          const uint8_t *__restrict__ mask, const float *__restrict__ r, const float *__restrict__ e_in,
+          const float *__restrict__ ec, int Wc, int Hc, float *__restrict__ e_out) {
+    schwarz_block<MODE>(W, H, ntx, nty, sx, sy, iters, mask, r, e_in, ec, Wc, Hc, e_out,
+                        xcd_remap(blockIdx.x, ntx * nty), blockIdx.y);
+}
+
 // ------------------------------------------------------------------ reduced FMG (Sec. 3.2)
 
 // Data on the first coarse level: a coarse known pixel takes the mean of its
 // known fine children's values (Sec. 3.3).
 template <typename TD>
-__global__ void k_data_restrict0(int W, int H, int C, const uint8_t *__restrict__ m, const TD *__restrict__ d,
-                                 int Wc, int Hc, const uint8_t *__restrict__ mc, float *__restrict__ dc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void data_restrict_at(int i, int W, int H, int C, const uint8_t *__restrict__ m,
+                                                 const TD *__restrict__ d, int Wc, int Hc,
+                                                 const uint8_t *__restrict__ mc, float *__restrict__ dc) {
     if (i >= Wc * Hc) return;
     const int X = i % Wc, Y = i / Wc;
     for (int c = 0; c < C; ++c) {
@@ -580,10 +622,16 @@ __global__ void k_data_restrict0(int W, int H, int C, const uint8_t *__restrict_
     }
 }
 
+template <typename TD>
+__global__ void k_data_restrict0(int W, int H, int C, const uint8_t *__restrict__ m, const TD *__restrict__ d,
+                                 int Wc, int Hc, const uint8_t *__restrict__ mc, float *__restrict__ dc) {
+    data_restrict_at<TD>(blockIdx.x * blockDim.x + threadIdx.x, W, H, C, m, d, Wc, Hc, mc, dc);
+}
+
 // FMG prolongation: out = P ec on unknown pixels, the level's data on known ones.
-__global__ void k_fmg_prolong(int W, int H, int C, const uint8_t *__restrict__ m, const float *__restrict__ data,
-                              const float *__restrict__ ec, int Wc, int Hc, float *__restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fmg_prolong_at(int i, int W, int H, int C, const uint8_t *__restrict__ m,
+                                               const float *__restrict__ data, const float *__restrict__ ec, int Wc,
+                                               int Hc, float *__restrict__ out) {
     if (i >= W * H) return;
     const int x = i % W, y = i / W;
     for (int c = 0; c < C; ++c) {
@@ -592,13 +640,22 @@ __global__ void k_fmg_prolong(int W, int H, int C, const uint8_t *__restrict__ m
     }
 }
 
+__global__ void k_fmg_prolong(int W, int H, int C, const uint8_t *__restrict__ m, const float *__restrict__ data,
+                              const float *__restrict__ ec, int Wc, int Hc, float *__restrict__ out) {
+    fmg_prolong_at(blockIdx.x * blockDim.x + threadIdx.x, W, H, C, m, data, ec, Wc, Hc, out);
+}
+
 // Level-0 FMG prolongation into the FP64 iterate (known pixels keep the data).
-__global__ void k_fmg_prolong0(int W, int H, int C, const uint8_t *__restrict__ m, const float *__restrict__ ec,
-                               int Wc, int Hc, double *__restrict__ u) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fmg_prolong0_at(int i, int W, int H, int C, const uint8_t *__restrict__ m,
+                                                const float *__restrict__ ec, int Wc, int Hc, double *__restrict__ u) {
     if (i >= W * H || m[i]) return;
     const int x = i % W, y = i / W;
     for (int c = 0; c < C; ++c) u[(size_t)c * W * H + i] = (double)prolong_at(ec + (size_t)c * Wc * Hc, Wc, Hc, x, y);
+}
+
+__global__ void k_fmg_prolong0(int W, int H, int C, const uint8_t *__restrict__ m, const float *__restrict__ ec,
+                               int Wc, int Hc, double *__restrict__ u) {
+    fmg_prolong0_at(blockIdx.x * blockDim.x + threadIdx.x, W, H, C, m, ec, Wc, Hc, u);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -699,5 +756,153 @@ template void launch_residual<double>(int, int, int, const uint8_t *, const doub
                                       const double *, const double *, float *, double *, double *, hipStream_t);
 template void launch_data_restrict0<float>(int, int, int, const uint8_t *, const float *, const Level &, hipStream_t);
 template void launch_data_restrict0<double>(int, int, int, const uint8_t *, const double *, const Level &, hipStream_t);
+
+// ------------------------------------------------------------------ batched kernels
+// One launch serves every image of a batch: each workgroup reads its work item,
+// looks up the image and level descriptors and runs the same block function as
+// the single-image kernel, so an image's result does not depend on the batch.
+
+__global__ void __launch_bounds__(256)
+kb_count(const int4 *__restrict__ items, const BLev *__restrict__ L, const BImg *__restrict__ I) {
+    const int4 it = items[blockIdx.x];
+    const BImg &im = I[it.x];
+    if (it.y == 0) {
+        count_known_block(im.W * im.H, im.mask, im.counts, it.z, it.w);
+    } else {
+        const BLev &f = L[it.x * MAX_LEVELS + it.y - 1];
+        mask_restrict_block(f.W, f.H, f.mask, f.Wc, f.Hc, f.mask_c, im.counts + it.y, it.z, it.w);
+    }
+}
+
+__global__ void kb_init_u(const int4 *__restrict__ items, const BImg *__restrict__ I, const uint8_t *__restrict__ active) {
+    const int4 it = items[blockIdx.x];
+    if (!active[it.x]) return;
+    const BImg &im = I[it.x];
+    init_u_at<float>(it.z * 256 + threadIdx.x, im.W * im.H, im.C, im.mask, im.f, nullptr, im.u);
+}
+
+template <int C>
+__global__ void __launch_bounds__(RED_THREADS)
+kb_residual(const int4 *__restrict__ items, const BImg *__restrict__ I, const uint8_t *__restrict__ active,
+            int use_e, int parity, const BLev *__restrict__ L) {
+    const int4 it = items[blockIdx.x];
+    if (!active[it.x]) return;
+    const BImg &im = I[it.x];
+    const double *u_in = parity ? im.u_alt : im.u;
+    double *u_out = parity ? im.u : im.u_alt;
+    const BLev &l0 = L[it.x * MAX_LEVELS];
+    // the last V-cycle's correction is the finest level's post-smoothing
+    // output (or the single level's smoothing output)
+    const float *e = use_e ? (im.nlev > 1 ? l0.eb : l0.ea) : nullptr;
+    residual_block<float, C>(im.W, im.H, im.mask, u_in, e, use_e ? u_out : nullptr, im.f, nullptr, l0.r,
+                             im.partials, im.nblk, it.y, it.z, im.gx);
+}
+
+__global__ void __launch_bounds__(1024)
+kb_reduce(const int4 *__restrict__ items, const BImg *__restrict__ I, const uint8_t *__restrict__ active) {
+    const int4 it = items[blockIdx.x];
+    if (!active[it.x]) return;
+    const BImg &im = I[it.x];
+    reduce_partials_block(im.nblk, im.partials, im.norms, it.y);
+}
+
+template <int MODE, bool COARSEST>
+__global__ void __launch_bounds__(64)
+kb_schwarz(const int4 *__restrict__ items, int n, const BLev *__restrict__ L, const BImg *__restrict__ I,
+           const uint8_t *__restrict__ active) {
+    const int4 it = items[xcd_remap(blockIdx.x, n)];
+    if (active && !active[it.x]) return;
+    const BImg &im = I[it.x];
+    const BLev &l = L[it.x * MAX_LEVELS + it.y];
+    const int iters = COARSEST ? im.coarse_iters : im.local_iters;
+    if (MODE == 0)
+        schwarz_block<0>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, nullptr, nullptr, 1, 1, l.ea, it.z,
+                         it.w);
+    else if (MODE == 1)
+        schwarz_block<1>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, l.ea, l.ec, l.Wc, l.Hc, l.eb, it.z,
+                         it.w);
+    else
+        schwarz_block<2>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, nullptr, COARSEST ? l.aux : l.eb,
+                         nullptr, 1, 1, l.ea, it.z, it.w);
+}
+
+__global__ void kb_restrict(const int4 *__restrict__ items, const BLev *__restrict__ L, const BImg *__restrict__ I,
+                            const uint8_t *__restrict__ active) {
+    const int4 it = items[blockIdx.x];
+    if (!active[it.x]) return;
+    const BImg &im = I[it.x];
+    const BLev &l = L[it.x * MAX_LEVELS + it.y];
+    restrict_residual_at(it.z * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, l.r, l.ea, l.Wc, l.Hc, l.mask_c, l.r_c);
+}
+
+template <bool FROM_F>
+__global__ void kb_data_restrict(const int4 *__restrict__ items, const BLev *__restrict__ L,
+                                 const BImg *__restrict__ I) {
+    const int4 it = items[blockIdx.x];
+    const BImg &im = I[it.x];
+    const BLev &l = L[it.x * MAX_LEVELS + it.y];
+    const float *src = FROM_F ? im.f : l.aux;
+    data_restrict_at<float>(it.z * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, src, l.Wc, l.Hc, l.mask_c, l.aux_c);
+}
+
+__global__ void kb_fmg_prolong(const int4 *__restrict__ items, const BLev *__restrict__ L,
+                               const BImg *__restrict__ I) {
+    const int4 it = items[blockIdx.x];
+    const BImg &im = I[it.x];
+    const BLev &l = L[it.x * MAX_LEVELS + it.y];
+    // the coarser level's FMG result is in its ea
+    const BLev &c = L[it.x * MAX_LEVELS + it.y + 1];
+    fmg_prolong_at(it.z * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, l.aux, c.ea, l.Wc, l.Hc, l.eb);
+}
+
+__global__ void kb_fmg_prolong0(const int4 *__restrict__ items, const BLev *__restrict__ L,
+                                const BImg *__restrict__ I) {
+    const int4 it = items[blockIdx.x];
+    const BImg &im = I[it.x];
+    const BLev &l = L[it.x * MAX_LEVELS];
+    const BLev &c = L[it.x * MAX_LEVELS + 1];
+    fmg_prolong0_at(it.z * 256 + threadIdx.x, im.W, im.H, im.C, im.mask, c.ea, l.Wc, l.Hc, im.u);
+}
+
+void launch_b_count(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(kb_count, dim3(n), dim3(256), 0, s, items, L, I);
+}
+void launch_b_init_u(const int4 *items, int n, const BImg *I, const uint8_t *active, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(kb_init_u, dim3(n), dim3(256), 0, s, items, I, active);
+}
+void launch_b_residual(const int4 *items, int n, int C, const BImg *I, const uint8_t *active, int use_e,
+                       int parity, const BLev *L, hipStream_t s) {
+    if (!n) return;
+    if (C == 3)
+        hipLaunchKernelGGL(kb_residual<3>, dim3(n), dim3(RED_THREADS), 0, s, items, I, active, use_e, parity, L);
+    else
+        hipLaunchKernelGGL(kb_residual<1>, dim3(n), dim3(RED_THREADS), 0, s, items, I, active, use_e, parity, L);
+}
+void launch_b_reduce(const int4 *items, int n, const BImg *I, const uint8_t *active, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(kb_reduce, dim3(n), dim3(1024), 0, s, items, I, active);
+}
+void launch_b_schwarz(int mode, bool coarsest, const int4 *items, int n, const BLev *L, const BImg *I,
+                      const uint8_t *active, hipStream_t s) {
+    if (!n) return;
+    if (mode == 0 && !coarsest) hipLaunchKernelGGL((kb_schwarz<0, false>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
+    if (mode == 0 && coarsest) hipLaunchKernelGGL((kb_schwarz<0, true>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
+    if (mode == 1) hipLaunchKernelGGL((kb_schwarz<1, false>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
+    if (mode == 2 && !coarsest) hipLaunchKernelGGL((kb_schwarz<2, false>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
+    if (mode == 2 && coarsest) hipLaunchKernelGGL((kb_schwarz<2, true>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
+}
+void launch_b_restrict(const int4 *items, int n, const BLev *L, const BImg *I, const uint8_t *active, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(kb_restrict, dim3(n), dim3(256), 0, s, items, L, I, active);
+}
+void launch_b_data_restrict(bool from_f, const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s) {
+    if (!n) return;
+    if (from_f) hipLaunchKernelGGL(kb_data_restrict<true>, dim3(n), dim3(256), 0, s, items, L, I);
+    else hipLaunchKernelGGL(kb_data_restrict<false>, dim3(n), dim3(256), 0, s, items, L, I);
+}
+void launch_b_fmg_prolong(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(kb_fmg_prolong, dim3(n), dim3(256), 0, s, items, L, I);
+}
+void launch_b_fmg_prolong0(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(kb_fmg_prolong0, dim3(n), dim3(256), 0, s, items, L, I);
+}
 
 }  // namespace hdi

@@ -1,0 +1,88 @@
+"""GPU tests of hdi_solve_batch: uneven images in shared launches give, for every
+image, bit-for-bit the result of the single-image solve, whatever else is in the
+batch, and match the FP64 oracle (eq. inp-discrete-lsi)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2401_06747_amd as hdi
+from oracle import inpaint as oi
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _batch_items(k=8, seed=0):
+    specs = synth.config4_specs(64)[:k]
+    out = []
+    for i, (H, W, C, d) in enumerate(specs):
+        # reduced sizes (the full batch runs in the benchmark)
+        H, W = max(33, H // 6), max(33, W // 6)
+        f = synth.textured_image(H, W, C, 4, i)
+        out.append((f, synth.gradient_mask(f, d)))
+    return out
+
+
+def _t(items):
+    fs = [torch.tensor(f, dtype=torch.float32, device=DEV) for f, _ in items]
+    ms = [torch.tensor(m, device=DEV) for _, m in items]
+    return fs, ms
+
+
+def test_batch_equals_single_solves_bitwise():
+    items = _batch_items(8)
+    fs, ms = _t(items)
+    us, reps = hdi.solve_batch(fs, ms)
+    for (f, m), u, rep in zip(zip(fs, ms), us, reps):
+        u1, r1 = hdi.inpaint_solve(f, m)
+        assert rep["status"] == 0 and r1["status"] == 0
+        assert rep["outer_iters"] == r1["outer_iters"]
+        assert torch.equal(u, u1)
+
+
+def test_result_independent_of_batch_mix():
+    items = _batch_items(6, seed=1)
+    fs, ms = _t(items)
+    full, _ = hdi.solve_batch(fs, ms)
+    alone, _ = hdi.solve_batch(fs[2:3], ms[2:3])
+    assert torch.equal(full[2], alone[0])
+    rev, _ = hdi.solve_batch(fs[::-1], ms[::-1])
+    for a, b in zip(full, rev[::-1]):
+        assert torch.equal(a, b)
+
+
+def test_batch_matches_oracle():
+    items = _batch_items(4)
+    fs, ms = _t(items)
+    us, reps = hdi.solve_batch(fs, ms)
+    for (f, m), u, rep in zip(items, us, reps):
+        assert rep["status"] == 0
+        err = oi.rel_l2(u.cpu().numpy(), oi.inpaint(f, m))
+        assert err.max() <= 1e-5, (err, rep)
+        assert oi.relres(u.cpu().numpy(), f, m).max() <= 1e-6 * 1.0001
+
+
+def test_batch_with_per_job_params_and_tiny_images():
+    rng = np.random.default_rng(4)
+    items = []
+    for (C, H, W) in [(1, 1, 40), (3, 17, 9), (1, 64, 64), (3, 45, 130)]:
+        f = rng.uniform(0, 255, (C, H, W)).astype(np.float32).astype(np.float64)
+        m = (rng.random((H, W)) < 0.1).astype(np.uint8)
+        m[0, 0] = 1
+        items.append((f, m))
+    fs, ms = _t(items)
+    params = [hdi.SolveParams(local_iters=6), hdi.SolveParams(), hdi.SolveParams(flags=1), hdi.SolveParams(coarse_iters=32)]
+    us, reps = hdi.solve_batch(fs, ms, params=params)
+    for (f, m), u, p in zip(zip(fs, ms), us, params):
+        u1, _ = hdi.inpaint_solve(f, m, params=p)
+        assert torch.equal(u, u1)
+
+
+def test_empty_mask_in_batch_is_an_error():
+    items = _batch_items(2)
+    fs, ms = _t(items)
+    ms[1] = torch.zeros_like(ms[1])
+    with pytest.raises(hdi.HdiError) as ei:
+        hdi.solve_batch(fs, ms)
+    assert ei.value.status == 2
