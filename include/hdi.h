@@ -121,7 +121,7 @@ size_t hdi_batch_workspace_bytes(int32_t n, const hdi_job *jobs);
  * (image, level, block) of all images taking part, and each image refines
  * until its own tolerance. An image's result is bit-for-bit what inpaint_solve
  * returns for it with the same parameters, whatever else is in the batch.
- *   params   nullable array of n per-job parameter sets (all with one overlap)
+ *   params   nullable array of n per-job parameter sets
  *   reports  nullable host array of n reports
  * Returns the first failing job's status (HDI_ERR_EMPTY_MASK for an empty
  * mask, before any solve; HDI_ERR_NO_CONVERGENCE with the last iterates). */
@@ -210,6 +210,18 @@ size_t hdi_densify_workspace_bytes(int32_t width, int32_t height);
 int32_t densify_step(int32_t width, int32_t height, uint8_t *mask, const float *err, int64_t n_add,
                      int32_t partition, int32_t *added, int64_t *n_added, void *ws, size_t ws_bytes,
                      void *stream);
+
+/* Autotuner of the inpainting solver: runs inpaint_solve on this image once
+ * per candidate parameter set (reps times each, keeping the fastest device
+ * time) and returns the index of the fastest candidate that reached its
+ * tolerance. The tunables are the block overlap, the local CG steps per
+ * smoothing and the coarsest-level CG steps (Sec. 3.3 tuned these for its GPU;
+ * the best values depend on image size and mask density).
+ *   ws  device workspace of at least hdi_inpaint_workspace_bytes(img) plus
+ *       C*H*W doubles plus 512 bytes (it also holds the trial solutions)     */
+int32_t hdi_autotune(hdi_image img, const uint8_t *mask, const float *f, void *ws, size_t ws_bytes,
+                     const hdi_solve_params *candidates, int32_t n_candidates, int32_t reps,
+                     int32_t *best_index, float *best_ms, void *stream);
 
 /* Number of 32x32 Schwarz blocks with the given overlap on one level of one
  * channel: per dimension ceil((n - 32) / (32 - overlap)) + 1 (1 if n <= 32),

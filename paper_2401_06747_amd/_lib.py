@@ -58,6 +58,9 @@ _SIGS = {
     "hdi_densify_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "densify_step": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32, _P,
                                       ctypes.POINTER(ctypes.c_int64), _P, ctypes.c_size_t, _P]),
+    "hdi_autotune": (ctypes.c_int32, [hdi_image, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(hdi_solve_params),
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_float), _P]),
     "hdi_block_count": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hdi_stats_enable": (None, [ctypes.c_int32]),
     "hdi_stats_reset": (None, []),

@@ -59,11 +59,13 @@ static size_t item_bound(const std::vector<Hierarchy> &hs) {
     return n;
 }
 
-static bool plan_batch(BatchPlan &b, Arena &a, int n, const hdi_job *jobs, int overlap) {
+// overlaps: per-job block overlap (nullptr: the largest valid overlap, whose
+// smallest block stride gives the most blocks and so bounds any choice)
+static bool plan_batch(BatchPlan &b, Arena &a, int n, const hdi_job *jobs, const int *overlaps) {
     b.h.assign(n, Hierarchy());
     for (int i = 0; i < n; ++i)
-        if (!plan_hierarchy(b.h[i], a, jobs[i].img.width, jobs[i].img.height, jobs[i].img.channels, overlap,
-                            jobs[i].mask))
+        if (!plan_hierarchy(b.h[i], a, jobs[i].img.width, jobs[i].img.height, jobs[i].img.channels,
+                            overlaps ? overlaps[i] : 16, jobs[i].mask))
             return false;
     b.d_lev = (BLev *)a.take(sizeof(BLev) * n * MAX_LEVELS);
     b.d_img = (BImg *)a.take(sizeof(BImg) * n);
@@ -385,7 +387,7 @@ size_t hdi_batch_workspace_bytes(int32_t n, const hdi_job *jobs) {
             return 0;
     BatchPlan b;
     Arena a{nullptr, 0, 0};
-    plan_batch(b, a, n, jobs, 4);
+    plan_batch(b, a, n, jobs, nullptr);
     return a.used + 256;
 }
 
@@ -396,21 +398,15 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
         return HDI_ERR_ARG;
     }
     std::vector<SolveCfg> cfg(n);
-    int overlap = 4;
+    std::vector<int> overlap(n, 4);
     for (int i = 0; i < n; ++i) {
         if (!check_image(jobs[i].img)) return HDI_ERR_ARG;
         if (!jobs[i].mask || !jobs[i].f || !jobs[i].u) {
             set_error("job %d: mask, f and u must be non-null device pointers", i);
             return HDI_ERR_ARG;
         }
-        int ov;
-        int32_t st = fill_cfg(params ? &params[i] : nullptr, cfg[i], ov);
+        int32_t st = fill_cfg(params ? &params[i] : nullptr, cfg[i], overlap[i]);
         if (st) return st;
-        if (i == 0) overlap = ov;
-        if (ov != overlap) {
-            set_error("all jobs of a batch share one block overlap");
-            return HDI_ERR_ARG;
-        }
     }
     const size_t need = hdi_batch_workspace_bytes(n, jobs);
     if (!ws || ws_bytes < need) {
@@ -419,7 +415,7 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
     }
     Arena a{(char *)ws, ws_bytes, 0};
     BatchPlan b;
-    plan_batch(b, a, n, jobs, overlap);
+    plan_batch(b, a, n, jobs, overlap.data());
     return run_batch(b, n, jobs, cfg, reports, (hipStream_t)stream);
 }
 

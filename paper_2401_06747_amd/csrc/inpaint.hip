@@ -349,6 +349,49 @@ int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double
     return st;
 }
 
+int32_t hdi_autotune(hdi_image img, const uint8_t *mask, const float *f, void *ws, size_t ws_bytes,
+                     const hdi_solve_params *candidates, int32_t n_candidates, int32_t reps,
+                     int32_t *best_index, float *best_ms, void *stream) {
+    if (!check_image(img)) return HDI_ERR_ARG;
+    if (!mask || !f || !candidates || n_candidates < 1 || reps < 1 || !best_index || !best_ms) {
+        set_error("autotune needs mask, f, at least one candidate, reps >= 1 and result pointers");
+        return HDI_ERR_ARG;
+    }
+    const size_t N = (size_t)img.width * img.height * img.channels;
+    const size_t need = inpaint_ws_bytes(img.width, img.height, img.channels) + N * sizeof(double) + 512;
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
+        return HDI_ERR_WORKSPACE;
+    }
+    Arena a{(char *)ws, ws_bytes, 0};
+    double *u = (double *)a.take(N * sizeof(double));
+    const size_t rest = ws_bytes - a.used - 256;
+    void *sub = (char *)ws + ((a.used + 255) & ~(size_t)255);
+    *best_index = -1;
+    *best_ms = 0.f;
+    for (int k = 0; k < n_candidates; ++k) {
+        float tmin = 1e30f;
+        bool ok = true;
+        for (int r = 0; r < reps && ok; ++r) {
+            hdi_solve_report rep;
+            const int32_t st = inpaint_solve(img, mask, f, u, nullptr, sub, rest, &candidates[k], &rep, stream);
+            if (st == HDI_ERR_ARG || st == HDI_ERR_HIP || st == HDI_ERR_WORKSPACE || st == HDI_ERR_EMPTY_MASK)
+                return st;
+            ok = st == HDI_OK;
+            tmin = std::min(tmin, rep.ms);
+        }
+        if (ok && (*best_index < 0 || tmin < *best_ms)) {
+            *best_index = k;
+            *best_ms = tmin;
+        }
+    }
+    if (*best_index < 0) {
+        set_error("no candidate reached its tolerance");
+        return HDI_ERR_NO_CONVERGENCE;
+    }
+    return HDI_OK;
+}
+
 int64_t hdi_block_count(int32_t width, int32_t height, int32_t overlap) {
     if (width < 1 || height < 1 || overlap < 0 || overlap >= TILE) return -1;
     return (int64_t)make_blocks(width, overlap).count * make_blocks(height, overlap).count;
