@@ -121,10 +121,11 @@ size_t hdi_batch_workspace_bytes(int32_t n, const hdi_job *jobs);
  * (image, level, block) of all images taking part, and each image refines
  * until its own tolerance. An image's result is bit-for-bit what inpaint_solve
  * returns for it with the same parameters, whatever else is in the batch.
- *   params   nullable array of n per-job parameter sets
- *   reports  nullable host array of n reports
- * Returns the first failing job's status (HDI_ERR_EMPTY_MASK for an empty
- * mask, before any solve; HDI_ERR_NO_CONVERGENCE with the last iterates). */
+ *   params   nullable array of n per-job parameter sets (each image its own)
+ *   reports  nullable host array of n reports (ms: the whole batch)
+ * Returns the first failing job's status (HDI_ERR_EMPTY_MASK for a job with
+ * an empty mask, which ends at once while the others are solved;
+ * HDI_ERR_NO_CONVERGENCE with the last iterates). */
 int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_bytes,
                         const hdi_solve_params *params, hdi_solve_report *reports, void *stream);
 
@@ -181,6 +182,70 @@ size_t hdi_tonal_workspace_bytes(hdi_image img);
 int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, double *g, double *u,
                        void *ws, size_t ws_bytes, const hdi_tonal_params *params,
                        hdi_tonal_report *report, void *stream);
+
+/* ------------------------------------------------------------------ serving */
+
+/* A request loop over one device: inpainting and tonal requests of any sizes
+ * are submitted as they arrive and run with continuous batching. Inpainting
+ * requests join the shared launches of the batch engine between refinement
+ * rounds (each keeps its own rounds and tolerance, and its result is bit-for-bit
+ * what inpaint_solve gives); tonal requests run on worker threads with streams
+ * of their own, so their kernels overlap the batch on the device. Every request
+ * is admitted when a slot and its memory in the caller's arena are free, in
+ * arrival order per kind, and its state stays in device memory until it ends. */
+#define HDI_REQ_INPAINT 0
+#define HDI_REQ_TONAL 1
+#define HDI_REQ_HOST_IO 1   /* request flags: mask, f and out are pinned host memory
+                               (copied in and out on the server's copy stream) */
+#define HDI_SERVER_PLAIN 1  /* server flags: one request at a time through
+                               inpaint_solve / tonal_optimize (the control) */
+
+/* One request. Without HDI_REQ_HOST_IO the pointers are device memory that
+ * must stay valid and unchanged until the request is done. Tonal requests
+ * start from g = f on the mask.
+ *   out   u (inpaint, C x H x W float64) or g (tonal, 0 off the mask)      */
+typedef struct {
+    int32_t kind, flags;
+    hdi_image img;
+    const uint8_t *mask;
+    const float *f;
+    double *out;
+    hdi_solve_params solve;          /* inpaint parameters, zero fields: defaults */
+    const hdi_tonal_params *tonal;   /* nullable: tonal defaults */
+} hdi_request;
+
+typedef struct {
+    int32_t status, kind;
+    int32_t outer_iters;       /* refinement rounds (inpaint) or outer iterations (tonal) */
+    int32_t inner_solves;      /* tonal: inpainting solves */
+    int32_t max_running;       /* inpaint: most requests sharing one round with it */
+    double rel_residual[3];    /* inpaint: per channel; tonal: [0] relative normal residual */
+    double mse_initial, mse_final;
+    double t_submit_ms, t_start_ms, t_done_ms;   /* host clock, ms since hdi_server_create */
+} hdi_request_report;
+
+typedef struct hdi_server hdi_server;
+
+/* Arena bytes one request takes while it runs. 0 on bad input. */
+size_t hdi_request_bytes(const hdi_request *req);
+
+/* Start a server on the current device. The arena (caller-owned device memory,
+ * not freed by the server) holds the engine tables and every running request's
+ * state; max_slots bounds the inpainting requests in one batch, tonal_workers
+ * the tonal requests running at once. Returns NULL on bad arguments or HIP
+ * failure (hdi_last_error says which). */
+hdi_server *hdi_server_create(void *arena, size_t arena_bytes, int32_t max_slots, int32_t tonal_workers,
+                              int32_t flags);
+/* Queue a request. HDI_ERR_BUDGET if it can never fit the arena. */
+int32_t hdi_server_submit(hdi_server *srv, const hdi_request *req, uint64_t *ticket);
+/* done = 1 and the report once the request has ended (its outputs final);
+ * a ticket is forgotten after the poll that reports it done. */
+int32_t hdi_server_poll(hdi_server *srv, uint64_t ticket, int32_t *done, hdi_request_report *report);
+/* Wait until every submitted request has ended. */
+int32_t hdi_server_drain(hdi_server *srv);
+/* Drain, stop the worker threads and release the server's streams. */
+void hdi_server_destroy(hdi_server *srv);
+
 
 /* ------------------------------------------------------------------ densification */
 

@@ -15,8 +15,8 @@ import torch
 from . import _lib
 from ._lib import HdiError, check
 
-__all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "DELAUNAY", "VORONOI", "hdi_block_count", "SolveParams", "TonalParams", "HdiError",
-           "PCG_RAS", "RAS", "CGNR"]
+__all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "Server", "DELAUNAY", "VORONOI",
+           "INPAINT", "TONAL", "hdi_block_count", "SolveParams", "TonalParams", "HdiError", "PCG_RAS", "RAS", "CGNR"]
 
 PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
 DELAUNAY, VORONOI = _lib.HDI_PART_DELAUNAY, _lib.HDI_PART_VORONOI
@@ -190,3 +190,97 @@ def solve_batch(fs, masks, params=None, ws: torch.Tensor | None = None, outs=Non
     if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
         check(st)
     return us, reports
+
+
+INPAINT, TONAL = _lib.HDI_REQ_INPAINT, _lib.HDI_REQ_TONAL
+
+
+class Server:
+    """Request loop over one GPU (hdi_server_*): continuous batching of
+    inpainting requests, tonal requests on worker streams, admission by the
+    bytes of a caller-owned arena. `plain=True` runs one request at a time
+    through inpaint_solve / tonal_optimize (the control)."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 64, tonal_workers: int = 2, plain: bool = False,
+                 device="cuda:0"):
+        L = _lib.lib()
+        self.device = torch.device(device)
+        self.arena = workspace(arena_bytes, self.device)
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            h = L.hdi_server_create(_ptr(self.arena), self.arena.numel(), int(max_slots), int(tonal_workers),
+                                    _lib.HDI_SERVER_PLAIN if plain else 0)
+        if not h:
+            raise HdiError(_lib.HDI_ERR_ARG, L.hdi_last_error().decode())
+        self._h = ctypes.c_void_p(h)
+        self._live = {}
+
+    @staticmethod
+    def request_bytes(kind: int, shape) -> int:
+        req = _lib.hdi_request(kind, 0, _img(shape))
+        return int(_lib.lib().hdi_request_bytes(ctypes.byref(req)))
+
+    def submit(self, kind: int, f: torch.Tensor, mask: torch.Tensor, params=None,
+               out: torch.Tensor | None = None) -> int:
+        """Queue a request; returns its ticket. The inputs must not change until
+        it is done; the output (u or g, float64) is returned by poll()."""
+        host = not f.is_cuda
+        if host:
+            # pinned host tensors: the server copies them in and the result out
+            if mask.is_cuda or not (f.is_pinned() and mask.is_pinned()):
+                raise ValueError("host requests need pinned f and mask (tensor.pin_memory())")
+            if f.dim() != 3 or tuple(f.shape[1:]) != tuple(mask.shape) or f.dtype != torch.float32 \
+                    or mask.dtype != torch.uint8 or not (f.is_contiguous() and mask.is_contiguous()):
+                raise ValueError("need contiguous f (C,H,W) float32 and mask (H,W) uint8")
+            out = out if out is not None else torch.empty(f.shape, dtype=torch.float64, pin_memory=True)
+        else:
+            _check_inputs(f, mask)
+            out = out if out is not None else torch.empty(f.shape, dtype=torch.float64, device=f.device)
+        L = _lib.lib()
+        solve = (params if isinstance(params, SolveParams) else SolveParams()).c()
+        tp = params.c() if isinstance(params, TonalParams) else None
+        req = _lib.hdi_request(kind, _lib.HDI_REQ_HOST_IO if host else 0, _img(f.shape), mask.data_ptr(),
+                               f.data_ptr(), out.data_ptr(), solve, ctypes.pointer(tp) if tp is not None else None)
+        # the inputs were written on torch's stream; the server's streams do not wait for it
+        if not host:
+            torch.cuda.current_stream(f.device).synchronize()
+        ticket = ctypes.c_uint64(0)
+        check(L.hdi_server_submit(self._h, ctypes.byref(req), ctypes.byref(ticket)))
+        self._live[ticket.value] = (f, mask, out)
+        return ticket.value
+
+    def poll(self, ticket: int):
+        """None while the request runs; then (output, report dict)."""
+        L = _lib.lib()
+        done = ctypes.c_int32(0)
+        rep = _lib.hdi_request_report()
+        check(L.hdi_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(rep)))
+        if not done.value:
+            return None
+        out = self._live.pop(ticket)[2]
+        report = {"status": rep.status, "kind": rep.kind, "outer_iters": rep.outer_iters,
+                  "inner_solves": rep.inner_solves, "max_running": rep.max_running,
+                  "rel_residual": list(rep.rel_residual), "mse_initial": rep.mse_initial,
+                  "mse_final": rep.mse_final, "t_submit_ms": rep.t_submit_ms, "t_start_ms": rep.t_start_ms,
+                  "t_done_ms": rep.t_done_ms}
+        if rep.status != _lib.HDI_OK:
+            report["message"] = L.hdi_last_error().decode()
+        return out, report
+
+    def drain(self):
+        check(_lib.lib().hdi_server_drain(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().hdi_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()

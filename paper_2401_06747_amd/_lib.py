@@ -39,6 +39,23 @@ class hdi_tonal_report(ctypes.Structure):
                 ("inner_solves", ctypes.c_int32), ("inner_vcycles", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
+class hdi_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("flags", ctypes.c_int32), ("img", hdi_image), ("mask", ctypes.c_void_p),
+                ("f", ctypes.c_void_p), ("out", ctypes.c_void_p), ("solve", hdi_solve_params),
+                ("tonal", ctypes.POINTER(hdi_tonal_params))]
+
+
+class hdi_request_report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("inner_solves", ctypes.c_int32), ("max_running", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double * 3), ("mse_initial", ctypes.c_double),
+                ("mse_final", ctypes.c_double), ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double)]
+
+
+HDI_REQ_INPAINT, HDI_REQ_TONAL = 0, 1
+HDI_REQ_HOST_IO = 1
+HDI_SERVER_PLAIN = 1
 HDI_TONAL_PCG_RAS, HDI_TONAL_RAS, HDI_TONAL_CGNR = 0, 1, 2
 HDI_TONAL_INIT_FROM_F = 1
 HDI_TONAL_TRACE = 2
@@ -61,6 +78,13 @@ _SIGS = {
     "hdi_autotune": (ctypes.c_int32, [hdi_image, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(hdi_solve_params),
                                       ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_float), _P]),
+    "hdi_request_bytes": (ctypes.c_size_t, [ctypes.POINTER(hdi_request)]),
+    "hdi_server_create": (_P, [_P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "hdi_server_submit": (ctypes.c_int32, [_P, ctypes.POINTER(hdi_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "hdi_server_poll": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(hdi_request_report)]),
+    "hdi_server_drain": (ctypes.c_int32, [_P]),
+    "hdi_server_destroy": (None, [_P]),
     "hdi_block_count": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hdi_stats_enable": (None, [ctypes.c_int32]),
     "hdi_stats_reset": (None, []),

@@ -1,25 +1,23 @@
-// Batched inpainting solves: many images of uneven size per launch.
+// Batched inpainting solves: many images of uneven size per launch, joining and
+// leaving between refinement rounds.
 //
 // Every image keeps its own multigrid hierarchy, tolerance and refinement
 // rounds; what is shared is the launch. For each phase of the solve (mask
 // pyramid, reduced FMG start, FP64 residual, each level of the V-cycle) one
-// kernel launch covers the work items (image, level, block) of all images that
-// take part, and per-image descriptor tables tell each workgroup which image
-// and level it serves. The block functions are the ones the single-image
-// kernels use and every reduction keeps its per-image order, so an image's
-// result is bit-for-bit the same alone, in any batch, and through
-// inpaint_solve with the same parameters.
+// kernel launch covers the blocks of all images that take part; a small
+// segment table per launch tells each workgroup which image and level it
+// serves. The block functions are the ones the single-image kernels use and
+// every reduction keeps its per-image order, so an image's result is
+// bit-for-bit the same alone, in any batch, and through inpaint_solve with the
+// same parameters.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
 
-#include "hdi_internal.h"
+#include "engine.h"
 
 namespace hdi {
-
-bool check_image(const hdi_image &img);
-int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap);
 
 #define B_TRY(expr)                                                                                  \
     do {                                                                                             \
@@ -30,348 +28,355 @@ int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap);
         }                                                                                            \
     } while (0)
 
-struct BatchPlan {
-    std::vector<Hierarchy> h;
-    BLev *d_lev;
-    BImg *d_img;
-    uint8_t *d_active;
-    unsigned int *d_counts;   // [n][MAX_LEVELS]
-    double *d_norms;          // [n][6]
-    int4 *d_items;
-    size_t max_items;
-};
-
-static size_t tiles_of(const Level &L) { return (size_t)L.bx.count * L.by.count; }
-
-// Upper bound of the work items one call can create (full hierarchies).
-static size_t item_bound(const std::vector<Hierarchy> &hs) {
-    size_t n = 0;
-    for (const Hierarchy &h : hs) {
-        const size_t N = (size_t)h.lev[0].W * h.lev[0].H;
-        n += 2 * ((N + 255) / 256) + 1024 * MAX_LEVELS;     // init_u, prolong0, counts
-        n += (size_t)h.nblk + h.C;                           // residual, reduce
-        for (int l = 0; l < h.nlev_full; ++l) {
-            const size_t Nl = (size_t)h.lev[l].W * h.lev[l].H;
-            n += 4 * tiles_of(h.lev[l]) * h.C;               // pre, post, coarsest, FMG smoothing
-            n += 3 * ((Nl + 255) / 256);                     // restrict, data restrict, FMG prolong
-        }
-    }
-    return n;
-}
-
-// overlaps: per-job block overlap (nullptr: the largest valid overlap, whose
-// smallest block stride gives the most blocks and so bounds any choice)
-static bool plan_batch(BatchPlan &b, Arena &a, int n, const hdi_job *jobs, const int *overlaps) {
-    b.h.assign(n, Hierarchy());
-    for (int i = 0; i < n; ++i)
-        if (!plan_hierarchy(b.h[i], a, jobs[i].img.width, jobs[i].img.height, jobs[i].img.channels,
-                            overlaps ? overlaps[i] : 16, jobs[i].mask))
-            return false;
-    b.d_lev = (BLev *)a.take(sizeof(BLev) * n * MAX_LEVELS);
-    b.d_img = (BImg *)a.take(sizeof(BImg) * n);
-    b.d_active = (uint8_t *)a.take(n);
-    b.d_counts = (unsigned int *)a.take(sizeof(unsigned int) * n * MAX_LEVELS);
-    b.d_norms = (double *)a.take(sizeof(double) * n * 6);
-    b.max_items = item_bound(b.h);
-    b.d_items = (int4 *)a.take(sizeof(int4) * b.max_items);
-    return a.base == nullptr || a.used <= a.size;
-}
+static constexpr int POINTS = 1 << 30;          // segment unit of point (256-pixel chunk) phases
+static constexpr int ADMIT_PHASES = 5 * MAX_LEVELS + 2;
+static constexpr int RES_PHASES = 3;
+static constexpr int VC_PHASES = 4 * MAX_LEVELS;
 
 __global__ void kb_zero_counts(int n, unsigned int *c) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) c[i] = 0u;
 }
 
-// A list of work items inside the uploaded item buffer.
-struct Span { size_t off = 0; int n = 0; };
+BPhase Engine::SegList::begin(const int4 *dev_base) const { return BPhase{dev_base + v.size(), 0, 0}; }
 
-struct ItemBuilder {
-    std::vector<int4> v;
-    Span begin() { Span s; s.off = v.size(); return s; }
-    void end(Span &s) { s.n = (int)(v.size() - s.off); }
-    void points(int img, int lev, size_t count) {
-        for (size_t k = 0; k < (count + 255) / 256; ++k) v.push_back(make_int4(img, lev, (int)k, 0));
-    }
-    void tiles(int img, int lev, const Level &L, int C) {
-        for (int c = 0; c < C; ++c)
-            for (int t = 0; t < L.bx.count * L.by.count; ++t) v.push_back(make_int4(img, lev, t, c));
-    }
-};
-
-static void fill_tables(const BatchPlan &b, int n, const hdi_job *jobs, const std::vector<SolveCfg> &cfg,
-                        std::vector<BLev> &lev, std::vector<BImg> &img) {
-    lev.assign((size_t)n * MAX_LEVELS, BLev{});
-    img.assign(n, BImg{});
-    for (int i = 0; i < n; ++i) {
-        const Hierarchy &h = b.h[i];
-        for (int l = 0; l < h.nlev; ++l) {
-            const Level &L = h.lev[l];
-            BLev &d = lev[(size_t)i * MAX_LEVELS + l];
-            d.W = L.W;
-            d.H = L.H;
-            d.ntx = L.bx.count;
-            d.nty = L.by.count;
-            d.sx = L.bx.stride;
-            d.sy = L.by.stride;
-            d.mask = L.mask;
-            d.r = L.r;
-            d.ea = L.ea;
-            d.eb = L.eb;
-            d.aux = L.aux;
-            if (l + 1 < h.nlev_full) {
-                const Level &Lc = h.lev[l + 1];
-                d.Wc = Lc.W;
-                d.Hc = Lc.H;
-                d.mask_c = Lc.mask;
-                d.r_c = Lc.r;
-                d.aux_c = Lc.aux;
-                // the coarser level's final correction: its smoothing output if it
-                // is the coarsest level in use, its post-smoothing output otherwise
-                d.ec = (l + 1 == h.nlev - 1) ? Lc.ea : Lc.eb;
-            }
-        }
-        BImg &m = img[i];
-        m.W = jobs[i].img.width;
-        m.H = jobs[i].img.height;
-        m.C = jobs[i].img.channels;
-        m.nlev = h.nlev;
-        m.local_iters = cfg[i].local_iters;
-        m.coarse_iters = cfg[i].coarse_iters;
-        const dim3 g = residual_grid(m.W, m.H);
-        m.gx = (int)g.x;
-        m.nblk = h.nblk;
-        m.mask = jobs[i].mask;
-        m.f = jobs[i].f;
-        m.u = jobs[i].u;
-        m.u_alt = h.u_alt;
-        m.partials = h.partials;
-        m.norms = b.d_norms + (size_t)i * 6;
-        m.counts = b.d_counts + (size_t)i * MAX_LEVELS;
-    }
+void Engine::SegList::add(BPhase &ph, int img, int lev, long count, int unit) {
+    if (count <= 0) return;
+    v.push_back(make_int4(img, lev, ph.n, unit));
+    ph.nseg += 1;
+    ph.n += (int)count;
 }
 
-static int32_t run_batch(BatchPlan &b, int n, const hdi_job *jobs, const std::vector<SolveCfg> &cfg,
-                         hdi_solve_report *reports, hipStream_t s) {
-    std::vector<BLev> lev;
-    std::vector<BImg> img;
-    int maxL = 0;
-    for (int i = 0; i < n; ++i) maxL = std::max(maxL, b.h[i].nlev_full);
-    // 1. mask pyramids and per-level counts, level by level across the batch
-    fill_tables(b, n, jobs, cfg, lev, img);
-    B_TRY(hipMemcpyAsync(b.d_lev, lev.data(), sizeof(BLev) * lev.size(), hipMemcpyHostToDevice, s));
-    B_TRY(hipMemcpyAsync(b.d_img, img.data(), sizeof(BImg) * n, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(kb_zero_counts, dim3((n * MAX_LEVELS + 255) / 256), dim3(256), 0, s, n * MAX_LEVELS,
-                       b.d_counts);
-    {
-        ItemBuilder ib;
-        std::vector<Span> per_level(maxL);
-        for (int l = 0; l < maxL; ++l) {
-            per_level[l] = ib.begin();
-            for (int i = 0; i < n; ++i) {
-                const Hierarchy &h = b.h[i];
-                if (l >= h.nlev_full) continue;
-                const long cnt = (long)h.lev[l].W * h.lev[l].H;
-                const int nb = (int)std::min<long>((cnt + 255) / 256, 1024);
-                for (int k = 0; k < nb; ++k) ib.v.push_back(make_int4(i, l, k, nb));
-            }
-            ib.end(per_level[l]);
-        }
-        B_TRY(hipMemcpyAsync(b.d_items, ib.v.data(), sizeof(int4) * ib.v.size(), hipMemcpyHostToDevice, s));
-        for (int l = 0; l < maxL; ++l)
-            launch_b_count(b.d_items + per_level[l].off, per_level[l].n, b.d_lev, b.d_img, s);
-        std::vector<unsigned int> counts((size_t)n * MAX_LEVELS);
-        B_TRY(hipMemcpyAsync(counts.data(), b.d_counts, sizeof(unsigned int) * counts.size(),
-                             hipMemcpyDeviceToHost, s));
-        B_TRY(hipStreamSynchronize(s));
-        for (int i = 0; i < n; ++i) {
-            Hierarchy &h = b.h[i];
-            for (int l = 0; l < MAX_LEVELS; ++l) h.known[l] = counts[(size_t)i * MAX_LEVELS + l];
-            if (h.known[0] == 0) {
-                set_error("job %d: empty mask (the inpainting matrix is singular)", i);
-                return HDI_ERR_EMPTY_MASK;
-            }
-            // same level rule as the single-image solve
-            h.nlev = h.nlev_full;
-            for (int l = 1; l < h.nlev_full; ++l) {
-                const double N = (double)h.lev[l].W * h.lev[l].H;
-                if (N - (double)h.known[l] <= 0.01 * N) {
-                    h.nlev = l + 1;
-                    break;
-                }
-            }
-        }
-    }
-    fill_tables(b, n, jobs, cfg, lev, img);
-    B_TRY(hipMemcpyAsync(b.d_lev, lev.data(), sizeof(BLev) * lev.size(), hipMemcpyHostToDevice, s));
-    B_TRY(hipMemcpyAsync(b.d_img, img.data(), sizeof(BImg) * n, hipMemcpyHostToDevice, s));
+bool Engine::plan(Arena &a, int max_slots) {
+    nslots_ = max_slots;
+    d_lev_ = (BLev *)a.take(sizeof(BLev) * max_slots * MAX_LEVELS);
+    d_img_ = (BImg *)a.take(sizeof(BImg) * max_slots);
+    d_flags_ = (uint8_t *)a.take(max_slots);
+    d_counts_ = (unsigned int *)a.take(sizeof(unsigned int) * max_slots * MAX_LEVELS);
+    d_norms_ = (double *)a.take(sizeof(double) * max_slots * 6);
+    seg_cap_admit_ = (size_t)ADMIT_PHASES * max_slots;
+    seg_cap_res_ = (size_t)RES_PHASES * max_slots;
+    seg_cap_vc_ = (size_t)VC_PHASES * max_slots;
+    d_seg_admit_ = (int4 *)a.take(sizeof(int4) * seg_cap_admit_);
+    d_seg_res_ = (int4 *)a.take(sizeof(int4) * seg_cap_res_);
+    d_seg_vc_ = (int4 *)a.take(sizeof(int4) * seg_cap_vc_);
+    slot_.assign(max_slots, nullptr);
+    h_lev_.assign((size_t)max_slots * MAX_LEVELS, BLev{});
+    h_img_.assign(max_slots, BImg{});
+    h_flags_.assign(max_slots, 0);
+    h_counts_.assign((size_t)max_slots * MAX_LEVELS, 0);
+    h_norms_.assign((size_t)max_slots * 6, 0.0);
+    return a.base == nullptr || a.used <= a.size;
+}
 
-    // 2. work lists of every phase
-    ItemBuilder ib;
-    Span init_u = ib.begin();
-    for (int i = 0; i < n; ++i) ib.points(i, 0, (size_t)img[i].W * img[i].H);
-    ib.end(init_u);
-    std::vector<Span> drestrict(maxL), fmg_coarse(maxL), fmg_prolong(maxL), fmg_smooth(maxL);
-    for (int l = 0; l + 1 < maxL; ++l) {   // data restriction l -> l+1
-        drestrict[l] = ib.begin();
-        for (int i = 0; i < n; ++i)
-            if (!(cfg[i].flags & HDI_FLAG_NO_FMG) && l + 1 < b.h[i].nlev)
-                ib.points(i, l, (size_t)b.h[i].lev[l + 1].W * b.h[i].lev[l + 1].H);
-        ib.end(drestrict[l]);
-    }
-    for (int l = 1; l < maxL; ++l) {
-        fmg_coarse[l] = ib.begin();
-        for (int i = 0; i < n; ++i)
-            if (!(cfg[i].flags & HDI_FLAG_NO_FMG) && b.h[i].nlev > 1 && l == b.h[i].nlev - 1)
-                ib.tiles(i, l, b.h[i].lev[l], img[i].C);
-        ib.end(fmg_coarse[l]);
-        fmg_prolong[l] = ib.begin();
-        for (int i = 0; i < n; ++i)
-            if (!(cfg[i].flags & HDI_FLAG_NO_FMG) && l < b.h[i].nlev - 1)
-                ib.points(i, l, (size_t)b.h[i].lev[l].W * b.h[i].lev[l].H);
-        ib.end(fmg_prolong[l]);
-        fmg_smooth[l] = ib.begin();
-        for (int i = 0; i < n; ++i)
-            if (!(cfg[i].flags & HDI_FLAG_NO_FMG) && l < b.h[i].nlev - 1) ib.tiles(i, l, b.h[i].lev[l], img[i].C);
-        ib.end(fmg_smooth[l]);
-    }
-    Span prolong0 = ib.begin();
-    for (int i = 0; i < n; ++i)
-        if (!(cfg[i].flags & HDI_FLAG_NO_FMG) && b.h[i].nlev > 1) ib.points(i, 0, (size_t)img[i].W * img[i].H);
-    ib.end(prolong0);
-    Span resid[2], reduce = ib.begin();
-    for (int i = 0; i < n; ++i)
-        for (int c = 0; c < img[i].C; ++c) ib.v.push_back(make_int4(i, c, 0, 0));
-    ib.end(reduce);
-    for (int k = 0; k < 2; ++k) {
-        const int C = k == 0 ? 1 : 3;
-        resid[k] = ib.begin();
-        for (int i = 0; i < n; ++i) {
-            if (img[i].C != C) continue;
-            const dim3 g = residual_grid(img[i].W, img[i].H);
-            for (unsigned by = 0; by < g.y; ++by)
-                for (unsigned bx = 0; bx < g.x; ++bx) ib.v.push_back(make_int4(i, (int)bx, (int)by, 0));
+std::vector<int> Engine::free_slots() const {
+    std::vector<int> out;
+    for (int i = 0; i < nslots_; ++i)
+        if (!slot_[i]) out.push_back(i);
+    return out;
+}
+
+void Engine::abort_all(std::vector<EJob *> &ended) {
+    for (EJob *&j : slot_)
+        if (j) {
+            ended.push_back(j);
+            j = nullptr;
         }
-        ib.end(resid[k]);
+}
+
+int Engine::running() const {
+    int n = 0;
+    for (EJob *j : slot_) n += j != nullptr;
+    return n;
+}
+
+// Host copy of the descriptors of one job's slot.
+void Engine::describe(const EJob &j) {
+    const Hierarchy &h = j.h;
+    const int i = j.slot;
+    for (int l = 0; l < MAX_LEVELS; ++l) h_lev_[(size_t)i * MAX_LEVELS + l] = BLev{};
+    for (int l = 0; l < h.nlev_full; ++l) {
+        const Level &L = h.lev[l];
+        BLev &d = h_lev_[(size_t)i * MAX_LEVELS + l];
+        d.W = L.W;
+        d.H = L.H;
+        d.ntx = L.bx.count;
+        d.nty = L.by.count;
+        d.sx = L.bx.stride;
+        d.sy = L.by.stride;
+        d.mask = L.mask;
+        d.r = L.r;
+        d.ea = L.ea;
+        d.eb = L.eb;
+        d.aux = L.aux;
+        if (l + 1 < h.nlev_full) {
+            const Level &Lc = h.lev[l + 1];
+            d.Wc = Lc.W;
+            d.Hc = Lc.H;
+            d.mask_c = Lc.mask;
+            d.r_c = Lc.r;
+            d.aux_c = Lc.aux;
+            // the coarser level's final correction: its smoothing output if it
+            // is the coarsest level in use, its post-smoothing output otherwise
+            d.ec = (l + 1 == h.nlev - 1) ? Lc.ea : Lc.eb;
+        }
     }
-    std::vector<Span> pre(maxL), coarsest(maxL), restr(maxL), post(maxL);
+    BImg &m = h_img_[i];
+    m = BImg{};
+    m.W = j.job.img.width;
+    m.H = j.job.img.height;
+    m.C = j.job.img.channels;
+    m.nlev = h.nlev;
+    m.local_iters = j.cfg.local_iters;
+    m.coarse_iters = j.cfg.coarse_iters;
+    const dim3 g = residual_grid(m.W, m.H);
+    m.gx = (int)g.x;
+    m.nblk = h.nblk;
+    m.mask = j.job.mask;
+    m.f = j.job.f;
+    m.u = j.job.u;
+    m.u_alt = h.u_alt;
+    m.partials = h.partials;
+    m.norms = d_norms_ + (size_t)i * 6;
+    m.counts = d_counts_ + (size_t)i * MAX_LEVELS;
+}
+
+int32_t Engine::upload_desc(const EJob &j, hipStream_t s) {
+    const int i = j.slot;
+    B_TRY(hipMemcpyAsync(d_lev_ + (size_t)i * MAX_LEVELS, &h_lev_[(size_t)i * MAX_LEVELS], sizeof(BLev) * MAX_LEVELS,
+                         hipMemcpyHostToDevice, s));
+    B_TRY(hipMemcpyAsync(d_img_ + i, &h_img_[i], sizeof(BImg), hipMemcpyHostToDevice, s));
+    return HDI_OK;
+}
+
+int32_t Engine::admit(const std::vector<EJob *> &news, std::vector<EJob *> &ended, hipStream_t s) {
+    if (news.empty()) return HDI_OK;
+    int maxL = 0;
+    for (EJob *j : news) {
+        if (j->slot < 0 || j->slot >= nslots_ || slot_[j->slot]) {
+            set_error("internal: bad engine slot %d", j->slot);
+            return HDI_ERR_ARG;
+        }
+        slot_[j->slot] = j;
+        j->h.nlev = j->h.nlev_full;
+        j->rounds = 0;
+        j->status = HDI_OK;
+        j->where = 0;
+        maxL = std::max(maxL, j->h.nlev_full);
+        describe(*j);
+        int32_t st = upload_desc(*j, s);
+        if (st) return st;
+    }
+    hipLaunchKernelGGL(kb_zero_counts, dim3((nslots_ * MAX_LEVELS + 255) / 256), dim3(256), 0, s,
+                       nslots_ * MAX_LEVELS, d_counts_);
+
+    // 1. coarse masks and known counts, level by level
+    seg_admit_.v.clear();
+    std::vector<BPhase> cnt(maxL);
     for (int l = 0; l < maxL; ++l) {
-        pre[l] = ib.begin();
-        for (int i = 0; i < n; ++i)
-            if (l < b.h[i].nlev - 1) ib.tiles(i, l, b.h[i].lev[l], img[i].C);
-        ib.end(pre[l]);
-        coarsest[l] = ib.begin();
-        for (int i = 0; i < n; ++i)
-            if (l == b.h[i].nlev - 1) ib.tiles(i, l, b.h[i].lev[l], img[i].C);
-        ib.end(coarsest[l]);
-        restr[l] = ib.begin();
-        for (int i = 0; i < n; ++i)
-            if (l < b.h[i].nlev - 1) ib.points(i, l, (size_t)b.h[i].lev[l + 1].W * b.h[i].lev[l + 1].H);
-        ib.end(restr[l]);
-        post[l] = ib.begin();
-        for (int i = 0; i < n; ++i)
-            if (l < b.h[i].nlev - 1) ib.tiles(i, l, b.h[i].lev[l], img[i].C);
-        ib.end(post[l]);
+        cnt[l] = seg_admit_.begin(d_seg_admit_);
+        for (EJob *j : news) {
+            if (l >= j->h.nlev_full) continue;
+            const long N = (long)j->h.lev[l].W * j->h.lev[l].H;
+            seg_admit_.add(cnt[l], j->slot, l, std::min<long>((N + 255) / 256, 1024), POINTS);
+        }
     }
-    if (ib.v.size() > b.max_items) {
-        set_error("internal: %zu work items exceed the planned %zu", ib.v.size(), b.max_items);
-        return HDI_ERR_WORKSPACE;
+    B_TRY(hipMemcpyAsync(d_seg_admit_, seg_admit_.v.data(), sizeof(int4) * seg_admit_.v.size(),
+                         hipMemcpyHostToDevice, s));
+    for (int l = 0; l < maxL; ++l) launch_b_count(cnt[l], d_lev_, d_img_, s);
+    B_TRY(hipGetLastError());
+    B_TRY(hipMemcpyAsync(h_counts_.data(), d_counts_, sizeof(unsigned int) * h_counts_.size(), hipMemcpyDeviceToHost,
+                         s));
+    B_TRY(hipStreamSynchronize(s));
+
+    // 2. levels in use: the same rule as the single-image solve
+    std::vector<EJob *> go;
+    for (EJob *j : news) {
+        Hierarchy &h = j->h;
+        for (int l = 0; l < MAX_LEVELS; ++l) h.known[l] = h_counts_[(size_t)j->slot * MAX_LEVELS + l];
+        if (h.known[0] == 0) {
+            j->status = HDI_ERR_EMPTY_MASK;
+            slot_[j->slot] = nullptr;
+            ended.push_back(j);
+            continue;
+        }
+        h.nlev = h.nlev_full;
+        for (int l = 1; l < h.nlev_full; ++l) {
+            const double N = (double)h.lev[l].W * h.lev[l].H;
+            if (N - (double)h.known[l] <= 0.01 * N) {
+                h.nlev = l + 1;
+                break;
+            }
+        }
+        describe(*j);
+        int32_t st = upload_desc(*j, s);
+        if (st) return st;
+        go.push_back(j);
     }
-    B_TRY(hipMemcpyAsync(b.d_items, ib.v.data(), sizeof(int4) * ib.v.size(), hipMemcpyHostToDevice, s));
-    auto at = [&](const Span &sp) { return b.d_items + sp.off; };
+    if (go.empty()) return HDI_OK;
 
     // 3. starting iterate: u = f on the mask, reduced FMG elsewhere (Sec. 3.2)
-    std::vector<uint8_t> active(n, 1);
-    B_TRY(hipMemcpyAsync(b.d_active, active.data(), n, hipMemcpyHostToDevice, s));
-    hipEvent_t e0, e1;
-    B_TRY(hipEventCreate(&e0));
-    B_TRY(hipEventCreate(&e1));
-    B_TRY(hipEventRecord(e0, s));
-    launch_b_init_u(at(init_u), init_u.n, b.d_img, b.d_active, s);
-    for (int l = 0; l + 1 < maxL; ++l)
-        launch_b_data_restrict(l == 0, at(drestrict[l]), drestrict[l].n, b.d_lev, b.d_img, s);
+    seg_admit_.v.clear();
+    auto fmg = [](const EJob *j) { return !(j->cfg.flags & HDI_FLAG_NO_FMG); };
+    auto chunks = [](const Level &L) { return ((long)L.W * L.H + 255) / 256; };
+    auto tiles = [](const Level &L) { return (long)L.bx.count * L.by.count; };
+    BPhase init_u = seg_admit_.begin(d_seg_admit_);
+    for (EJob *j : go) seg_admit_.add(init_u, j->slot, 0, chunks(j->h.lev[0]), POINTS);
+    std::vector<BPhase> drestrict(maxL), fmg_coarse(maxL), fmg_prolong(maxL), fmg_smooth(maxL);
+    for (int l = 0; l + 1 < maxL; ++l) {   // data restriction l -> l+1
+        drestrict[l] = seg_admit_.begin(d_seg_admit_);
+        for (EJob *j : go)
+            if (fmg(j) && l + 1 < j->h.nlev) seg_admit_.add(drestrict[l], j->slot, l, chunks(j->h.lev[l + 1]), POINTS);
+    }
+    for (int l = 1; l < maxL; ++l) {
+        fmg_coarse[l] = seg_admit_.begin(d_seg_admit_);
+        for (EJob *j : go)
+            if (fmg(j) && j->h.nlev > 1 && l == j->h.nlev - 1)
+                seg_admit_.add(fmg_coarse[l], j->slot, l, tiles(j->h.lev[l]) * j->h.C, (int)tiles(j->h.lev[l]));
+        fmg_prolong[l] = seg_admit_.begin(d_seg_admit_);
+        for (EJob *j : go)
+            if (fmg(j) && l < j->h.nlev - 1) seg_admit_.add(fmg_prolong[l], j->slot, l, chunks(j->h.lev[l]), POINTS);
+        fmg_smooth[l] = seg_admit_.begin(d_seg_admit_);
+        for (EJob *j : go)
+            if (fmg(j) && l < j->h.nlev - 1)
+                seg_admit_.add(fmg_smooth[l], j->slot, l, tiles(j->h.lev[l]) * j->h.C, (int)tiles(j->h.lev[l]));
+    }
+    BPhase prolong0 = seg_admit_.begin(d_seg_admit_);
+    for (EJob *j : go)
+        if (fmg(j) && j->h.nlev > 1) seg_admit_.add(prolong0, j->slot, 0, chunks(j->h.lev[0]), POINTS);
+    if (seg_admit_.v.size() > seg_cap_admit_) {
+        set_error("internal: %zu segments exceed the planned %zu", seg_admit_.v.size(), seg_cap_admit_);
+        return HDI_ERR_WORKSPACE;
+    }
+    B_TRY(hipMemcpyAsync(d_seg_admit_, seg_admit_.v.data(), sizeof(int4) * seg_admit_.v.size(),
+                         hipMemcpyHostToDevice, s));
+    launch_b_init_u(init_u, d_img_, s);
+    for (int l = 0; l + 1 < maxL; ++l) launch_b_data_restrict(l == 0, drestrict[l], d_lev_, d_img_, s);
     for (int l = maxL - 1; l >= 1; --l) {
-        launch_b_schwarz(2, true, at(fmg_coarse[l]), fmg_coarse[l].n, b.d_lev, b.d_img, nullptr, s);
-        launch_b_fmg_prolong(at(fmg_prolong[l]), fmg_prolong[l].n, b.d_lev, b.d_img, s);
-        launch_b_schwarz(2, false, at(fmg_smooth[l]), fmg_smooth[l].n, b.d_lev, b.d_img, nullptr, s);
+        launch_b_schwarz(2, true, fmg_coarse[l], d_lev_, d_img_, s);
+        launch_b_fmg_prolong(fmg_prolong[l], d_lev_, d_img_, s);
+        launch_b_schwarz(2, false, fmg_smooth[l], d_lev_, d_img_, s);
     }
-    launch_b_fmg_prolong0(at(prolong0), prolong0.n, b.d_lev, b.d_img, s);
+    launch_b_fmg_prolong0(prolong0, d_lev_, d_img_, s);
     B_TRY(hipGetLastError());
+    return HDI_OK;
+}
 
-    // 4. refinement rounds, each image until its own tolerance
-    std::vector<int> rounds(n, 0), status(n, HDI_OK), final_parity(n, 0);
-    std::vector<double> rel((size_t)n * 3, 0.0), norms((size_t)n * 6);
-    int round = 0;
-    int nactive = n;
-    for (;;) {
-        const int parity = (round > 0 && round % 2 == 0) ? 1 : 0;
-        for (int k = 0; k < 2; ++k)
-            launch_b_residual(at(resid[k]), resid[k].n, k == 0 ? 1 : 3, b.d_img, b.d_active, round > 0, parity,
-                              b.d_lev, s);
-        launch_b_reduce(at(reduce), reduce.n, b.d_img, b.d_active, s);
-        B_TRY(hipMemcpyAsync(norms.data(), b.d_norms, sizeof(double) * norms.size(), hipMemcpyDeviceToHost, s));
-        B_TRY(hipStreamSynchronize(s));
-        // where this round's iterate lives: u for round 0, else the residual's output
-        const int where = round == 0 ? 0 : (parity ? 0 : 1);
-        for (int i = 0; i < n; ++i) {
-            if (!active[i]) continue;
-            final_parity[i] = where;
-            double worst = 0.0;
-            bool finite = true;
-            for (int c = 0; c < img[i].C; ++c) {
-                const double rr = norms[(size_t)i * 6 + 2 * c], bb = norms[(size_t)i * 6 + 2 * c + 1];
-                finite = finite && std::isfinite(rr) && std::isfinite(bb);
-                rel[(size_t)i * 3 + c] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
-                worst = std::fmax(worst, rel[(size_t)i * 3 + c]);
-            }
-            if (!finite) {
-                status[i] = HDI_ERR_ARG;
-                active[i] = 0;
-            } else if (worst <= cfg[i].rel_tol) {
-                active[i] = 0;
-            } else if (rounds[i] >= cfg[i].max_outer) {
-                status[i] = HDI_ERR_NO_CONVERGENCE;
-                active[i] = 0;
-            }
+int32_t Engine::round(std::vector<EJob *> &ended, hipStream_t s) {
+    std::vector<EJob *> run;
+    for (EJob *j : slot_)
+        if (j) run.push_back(j);
+    if (run.empty()) return HDI_OK;
+
+    // 1. FP64 residual (and, after a V-cycle, the fused update) of every job
+    seg_res_.v.clear();
+    BPhase res[2];
+    for (int k = 0; k < 2; ++k) {
+        const int C = k == 0 ? 1 : 3;
+        res[k] = seg_res_.begin(d_seg_res_);
+        for (EJob *j : run) {
+            if (j->h.C != C) continue;
+            const dim3 g = residual_grid(j->job.img.width, j->job.img.height);
+            seg_res_.add(res[k], j->slot, 0, (long)g.x * g.y, (int)g.x);
         }
-        nactive = (int)std::count(active.begin(), active.end(), (uint8_t)1);
-        if (nactive == 0) break;
-        B_TRY(hipMemcpyAsync(b.d_active, active.data(), n, hipMemcpyHostToDevice, s));
-        for (int l = 0; l < maxL; ++l) {
-            launch_b_schwarz(0, false, at(pre[l]), pre[l].n, b.d_lev, b.d_img, b.d_active, s);
-            launch_b_schwarz(0, true, at(coarsest[l]), coarsest[l].n, b.d_lev, b.d_img, b.d_active, s);
-            launch_b_restrict(at(restr[l]), restr[l].n, b.d_lev, b.d_img, b.d_active, s);
-        }
-        for (int l = maxL - 2; l >= 0; --l)
-            launch_b_schwarz(1, false, at(post[l]), post[l].n, b.d_lev, b.d_img, b.d_active, s);
-        for (int i = 0; i < n; ++i) rounds[i] += active[i];
-        ++round;
     }
-    // iterates that ended in the workspace copy go back to the caller's u
-    for (int i = 0; i < n; ++i)
-        if (final_parity[i] == 1)
-            B_TRY(hipMemcpyAsync(jobs[i].u, b.h[i].u_alt, sizeof(double) * img[i].C * img[i].W * img[i].H,
-                                 hipMemcpyDeviceToDevice, s));
+    BPhase red = seg_res_.begin(d_seg_res_);
+    for (EJob *j : run) seg_res_.add(red, j->slot, 0, j->h.C, POINTS);
+    for (EJob *j : run) {
+        const int r = j->rounds;
+        h_flags_[j->slot] = (uint8_t)(1 | (r > 0 ? 2 : 0) | ((r > 0 && r % 2 == 0) ? 4 : 0));
+    }
+    B_TRY(hipMemcpyAsync(d_seg_res_, seg_res_.v.data(), sizeof(int4) * seg_res_.v.size(), hipMemcpyHostToDevice, s));
+    B_TRY(hipMemcpyAsync(d_flags_, h_flags_.data(), nslots_, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < 2; ++k) launch_b_residual(res[k], k == 0 ? 1 : 3, d_img_, d_flags_, d_lev_, s);
+    launch_b_reduce(red, d_img_, s);
     B_TRY(hipGetLastError());
-    B_TRY(hipEventRecord(e1, s));
-    B_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    B_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    int32_t worst_status = HDI_OK;
-    for (int i = 0; i < n; ++i) {
-        if (reports) {
-            for (int c = 0; c < 3; ++c) reports[i].rel_residual[c] = c < img[i].C ? rel[(size_t)i * 3 + c] : 0.0;
-            reports[i].outer_iters = rounds[i];
-            reports[i].vcycles = rounds[i];
-            reports[i].ms = ms;
+    B_TRY(hipMemcpyAsync(h_norms_.data(), d_norms_, sizeof(double) * h_norms_.size(), hipMemcpyDeviceToHost, s));
+    B_TRY(hipStreamSynchronize(s));
+
+    // 2. per-job decision
+    std::vector<EJob *> go;
+    for (EJob *j : run) {
+        const int r = j->rounds;
+        // where the residual's iterate lives: u after round 0 and after even
+        // rounds, u_alt after odd ones
+        j->where = (r % 2 == 1) ? 1 : 0;
+        double worst = 0.0;
+        bool finite = true;
+        for (int c = 0; c < j->h.C; ++c) {
+            const double rr = h_norms_[(size_t)j->slot * 6 + 2 * c], bb = h_norms_[(size_t)j->slot * 6 + 2 * c + 1];
+            finite = finite && std::isfinite(rr) && std::isfinite(bb);
+            j->rel[c] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+            worst = std::fmax(worst, j->rel[c]);
         }
-        if (status[i] != HDI_OK && worst_status == HDI_OK) {
-            worst_status = status[i];
-            set_error("job %d: %s", i, status[i] == HDI_ERR_NO_CONVERGENCE ? "no convergence" : "non-finite residual");
+        bool stop = true;
+        if (!finite)
+            j->status = HDI_ERR_ARG;
+        else if (worst <= j->cfg.rel_tol)
+            j->status = HDI_OK;
+        else if (r >= j->cfg.max_outer)
+            j->status = HDI_ERR_NO_CONVERGENCE;
+        else
+            stop = false;
+        if (!stop) {
+            go.push_back(j);
+            continue;
         }
+        // iterates that ended in the workspace copy go back to the caller's u
+        if (j->where == 1)
+            B_TRY(hipMemcpyAsync(j->job.u, j->h.u_alt,
+                                 sizeof(double) * j->h.C * j->job.img.width * j->job.img.height,
+                                 hipMemcpyDeviceToDevice, s));
+        slot_[j->slot] = nullptr;
+        ended.push_back(j);
     }
-    return worst_status;
+    if (go.empty()) return HDI_OK;
+
+    // 3. one V-cycle for the jobs that go on
+    int maxL = 0;
+    for (EJob *j : go) maxL = std::max(maxL, j->h.nlev);
+    seg_vc_.v.clear();
+    std::vector<BPhase> pre(maxL), coarsest(maxL), restr(maxL), post(maxL);
+    for (int l = 0; l < maxL; ++l) {
+        auto tiles = [&](BPhase &ph, bool above_coarsest) {
+            for (EJob *j : go)
+                if (above_coarsest ? l < j->h.nlev - 1 : l == j->h.nlev - 1) {
+                    const Level &L = j->h.lev[l];
+                    const long nt = (long)L.bx.count * L.by.count;
+                    seg_vc_.add(ph, j->slot, l, nt * j->h.C, (int)nt);
+                }
+        };
+        pre[l] = seg_vc_.begin(d_seg_vc_);
+        tiles(pre[l], true);
+        coarsest[l] = seg_vc_.begin(d_seg_vc_);
+        tiles(coarsest[l], false);
+        restr[l] = seg_vc_.begin(d_seg_vc_);
+        for (EJob *j : go)
+            if (l < j->h.nlev - 1)
+                seg_vc_.add(restr[l], j->slot, l, ((long)j->h.lev[l + 1].W * j->h.lev[l + 1].H + 255) / 256, POINTS);
+        post[l] = seg_vc_.begin(d_seg_vc_);
+        tiles(post[l], true);
+    }
+    B_TRY(hipMemcpyAsync(d_seg_vc_, seg_vc_.v.data(), sizeof(int4) * seg_vc_.v.size(), hipMemcpyHostToDevice, s));
+    for (int l = 0; l < maxL; ++l) {
+        launch_b_schwarz(0, false, pre[l], d_lev_, d_img_, s);
+        launch_b_schwarz(0, true, coarsest[l], d_lev_, d_img_, s);
+        launch_b_restrict(restr[l], d_lev_, d_img_, s);
+    }
+    for (int l = maxL - 2; l >= 0; --l) launch_b_schwarz(1, false, post[l], d_lev_, d_img_, s);
+    B_TRY(hipGetLastError());
+    for (EJob *j : go) j->rounds += 1;
+    return HDI_OK;
+}
+
+// Workspace layout of hdi_solve_batch: engine tables for n slots, then the
+// hierarchies of the jobs in order.
+static bool plan_batch(Engine &e, std::vector<EJob> &jobs, Arena &a) {
+    if (!e.plan(a, (int)jobs.size())) return false;
+    for (EJob &j : jobs)
+        if (!plan_hierarchy(j.h, a, j.job.img.width, j.job.img.height, j.job.img.channels, j.overlap, j.job.mask))
+            return false;
+    return true;
 }
 
 }  // namespace hdi
@@ -382,12 +387,15 @@ extern "C" {
 
 size_t hdi_batch_workspace_bytes(int32_t n, const hdi_job *jobs) {
     if (n < 1 || !jobs) return 0;
-    for (int i = 0; i < n; ++i)
+    std::vector<EJob> ej(n);
+    for (int i = 0; i < n; ++i) {
         if (jobs[i].img.width < 1 || jobs[i].img.height < 1 || (jobs[i].img.channels != 1 && jobs[i].img.channels != 3))
             return 0;
-    BatchPlan b;
+        ej[i].job = jobs[i];
+    }
+    Engine e;
     Arena a{nullptr, 0, 0};
-    plan_batch(b, a, n, jobs, nullptr);
+    plan_batch(e, ej, a);
     return a.used + 256;
 }
 
@@ -397,26 +405,60 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
         set_error("need n >= 1 jobs");
         return HDI_ERR_ARG;
     }
-    std::vector<SolveCfg> cfg(n);
-    std::vector<int> overlap(n, 4);
+    std::vector<EJob> ej(n);
     for (int i = 0; i < n; ++i) {
         if (!check_image(jobs[i].img)) return HDI_ERR_ARG;
         if (!jobs[i].mask || !jobs[i].f || !jobs[i].u) {
             set_error("job %d: mask, f and u must be non-null device pointers", i);
             return HDI_ERR_ARG;
         }
-        int32_t st = fill_cfg(params ? &params[i] : nullptr, cfg[i], overlap[i]);
+        int32_t st = fill_cfg(params ? &params[i] : nullptr, ej[i].cfg, ej[i].overlap);
         if (st) return st;
+        ej[i].job = jobs[i];
+        ej[i].slot = i;
     }
     const size_t need = hdi_batch_workspace_bytes(n, jobs);
     if (!ws || ws_bytes < need) {
         set_error("workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
         return HDI_ERR_WORKSPACE;
     }
+    hipStream_t s = (hipStream_t)stream;
     Arena a{(char *)ws, ws_bytes, 0};
-    BatchPlan b;
-    plan_batch(b, a, n, jobs, overlap.data());
-    return run_batch(b, n, jobs, cfg, reports, (hipStream_t)stream);
+    Engine e;
+    plan_batch(e, ej, a);
+    hipEvent_t e0, e1;
+    B_TRY(hipEventCreate(&e0));
+    B_TRY(hipEventCreate(&e1));
+    B_TRY(hipEventRecord(e0, s));
+    std::vector<EJob *> news, ended;
+    for (EJob &j : ej) news.push_back(&j);
+    int32_t st = e.admit(news, ended, s);
+    while (st == HDI_OK && e.running() > 0) st = e.round(ended, s);
+    B_TRY(hipEventRecord(e1, s));
+    B_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    B_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    int32_t worst = HDI_OK;
+    for (int i = 0; i < n; ++i) {
+        const EJob &j = ej[i];
+        if (reports) {
+            for (int c = 0; c < 3; ++c) reports[i].rel_residual[c] = c < j.h.C ? j.rel[c] : 0.0;
+            reports[i].outer_iters = j.rounds;
+            reports[i].vcycles = j.rounds;
+            reports[i].ms = ms;
+        }
+        if (j.status != HDI_OK && worst == HDI_OK) {
+            worst = j.status;
+            set_error("job %d: %s", i,
+                      j.status == HDI_ERR_NO_CONVERGENCE ? "no convergence"
+                      : j.status == HDI_ERR_EMPTY_MASK   ? "empty mask (the inpainting matrix is singular)"
+                                                          : "non-finite residual");
+        }
+    }
+    return worst;
 }
 
 }  // extern "C"

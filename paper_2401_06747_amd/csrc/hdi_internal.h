@@ -136,21 +136,22 @@ struct BImg {
     double *u, *u_alt, *partials, *norms;
     unsigned int *counts;
 };
-// Work items are int4: tile kernels {img, level, block, channel}; point
-// kernels {img, level, chunk of 256, 0}; residual {img, bx, by, 0};
-// counting {img, level, block, nblocks}; reduction {img, channel, 0, 0}.
-void launch_b_count(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s);
-void launch_b_init_u(const int4 *items, int n, const BImg *I, const uint8_t *active, hipStream_t s);
-void launch_b_residual(const int4 *items, int n, int C, const BImg *I, const uint8_t *active, int use_e,
-                       int parity, const BLev *L, hipStream_t s);
-void launch_b_reduce(const int4 *items, int n, const BImg *I, const uint8_t *active, hipStream_t s);
-// MODE 0 pre-smoothing (coarsest: uses coarse_iters), 1 post, 2 FMG (coarsest: e_in = aux)
-void launch_b_schwarz(int mode, bool coarsest, const int4 *items, int n, const BLev *L, const BImg *I,
-                      const uint8_t *active, hipStream_t s);
-void launch_b_restrict(const int4 *items, int n, const BLev *L, const BImg *I, const uint8_t *active, hipStream_t s);
-void launch_b_data_restrict(bool from_f, const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s);
-void launch_b_fmg_prolong(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s);
-void launch_b_fmg_prolong0(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s);
+// One launch's work list: nseg segments {img, level, first workgroup, unit}
+// (device table, starts ascending from 0) covering n workgroups.
+struct BPhase {
+    const int4 *seg;
+    int nseg, n;
+};
+void launch_b_count(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
+void launch_b_init_u(const BPhase &ph, const BImg *I, hipStream_t s);
+void launch_b_residual(const BPhase &ph, int C, const BImg *I, const uint8_t *flags, const BLev *L, hipStream_t s);
+void launch_b_reduce(const BPhase &ph, const BImg *I, hipStream_t s);
+// mode 0 pre-smoothing (coarsest: uses coarse_iters), 1 post, 2 FMG (coarsest: e_in = aux)
+void launch_b_schwarz(int mode, bool coarsest, const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
+void launch_b_restrict(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
+void launch_b_data_restrict(bool from_f, const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
+void launch_b_fmg_prolong(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
+void launch_b_fmg_prolong0(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
 
 // Coarse masks, known counts and the number of levels for a new mask.
 int32_t prepare_mask(Hierarchy &h, hipStream_t s);

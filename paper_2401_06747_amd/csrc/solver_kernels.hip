@@ -758,151 +758,181 @@ template void launch_data_restrict0<float>(int, int, int, const uint8_t *, const
 template void launch_data_restrict0<double>(int, int, int, const uint8_t *, const double *, const Level &, hipStream_t);
 
 // ------------------------------------------------------------------ batched kernels
-// One launch serves every image of a batch: each workgroup reads its work item,
-// looks up the image and level descriptors and runs the same block function as
-// the single-image kernel, so an image's result does not depend on the batch.
+// One launch serves several images: each workgroup finds its segment in the
+// launch's segment table (one entry per image and level taking part), looks up
+// the image and level descriptors and runs the same block function as the
+// single-image kernel, so an image's result does not depend on the batch.
+
+struct SegItem { int img, lev, a, b; };
+
+// Segment k covers workgroups [start_k, start_{k+1}); starts ascend from 0. One
+// lane per segment compares its start with the workgroup index and the ballot
+// count is the segment's position, so a table of up to 64 segments costs one
+// vector load. The local index splits into (local % unit, local / unit).
+__device__ __forceinline__ SegItem seg_item(const int4 *__restrict__ seg, int nseg, int b) {
+    const int lane = threadIdx.x & 63;
+    int4 cur = make_int4(0, 0, 0, 1), prev = cur;
+    int cnt = 0;
+    for (int base = 0; base < nseg; base += 64) {
+        prev = cur;
+        const int k = base + lane;
+        cur = k < nseg ? seg[k] : make_int4(0, 0, 0x7fffffff, 1);
+        cnt = (int)__popcll(__ballot(cur.z <= b));
+        if (cnt < 64) break;
+    }
+    const int4 src = cnt == 0 ? prev : cur;
+    const int at = cnt == 0 ? 63 : cnt - 1;
+    const int img = __builtin_amdgcn_readlane(src.x, at);
+    const int lev = __builtin_amdgcn_readlane(src.y, at);
+    const int start = __builtin_amdgcn_readlane(src.z, at);
+    const int unit = __builtin_amdgcn_readlane(src.w, at);
+    const int local = b - start;
+    return SegItem{img, lev, local % unit, local / unit};
+}
 
 __global__ void __launch_bounds__(256)
-kb_count(const int4 *__restrict__ items, const BLev *__restrict__ L, const BImg *__restrict__ I) {
-    const int4 it = items[blockIdx.x];
-    const BImg &im = I[it.x];
-    if (it.y == 0) {
-        count_known_block(im.W * im.H, im.mask, im.counts, it.z, it.w);
+kb_count(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L, const BImg *__restrict__ I) {
+    const SegItem it = seg_item(seg, nseg, blockIdx.x);
+    const BImg &im = I[it.img];
+    if (it.lev == 0) {
+        const int N = im.W * im.H;
+        count_known_block(N, im.mask, im.counts, it.a, min((N + 255) / 256, 1024));
     } else {
-        const BLev &f = L[it.x * MAX_LEVELS + it.y - 1];
-        mask_restrict_block(f.W, f.H, f.mask, f.Wc, f.Hc, f.mask_c, im.counts + it.y, it.z, it.w);
+        const BLev &f = L[it.img * MAX_LEVELS + it.lev - 1];
+        const int Nc = f.Wc * f.Hc;
+        mask_restrict_block(f.W, f.H, f.mask, f.Wc, f.Hc, f.mask_c, im.counts + it.lev, it.a,
+                            min((Nc + 255) / 256, 1024));
     }
 }
 
-__global__ void kb_init_u(const int4 *__restrict__ items, const BImg *__restrict__ I, const uint8_t *__restrict__ active) {
-    const int4 it = items[blockIdx.x];
-    if (!active[it.x]) return;
-    const BImg &im = I[it.x];
-    init_u_at<float>(it.z * 256 + threadIdx.x, im.W * im.H, im.C, im.mask, im.f, nullptr, im.u);
+__global__ void kb_init_u(const int4 *__restrict__ seg, int nseg, const BImg *__restrict__ I) {
+    const SegItem it = seg_item(seg, nseg, blockIdx.x);
+    const BImg &im = I[it.img];
+    init_u_at<float>(it.a * 256 + threadIdx.x, im.W * im.H, im.C, im.mask, im.f, nullptr, im.u);
 }
 
+// flags[img]: bit 1 = apply the last V-cycle's correction, bit 2 = the current
+// iterate is in u_alt (the refinement ping-pongs between u and u_alt)
 template <int C>
 __global__ void __launch_bounds__(RED_THREADS)
-kb_residual(const int4 *__restrict__ items, const BImg *__restrict__ I, const uint8_t *__restrict__ active,
-            int use_e, int parity, const BLev *__restrict__ L) {
-    const int4 it = items[blockIdx.x];
-    if (!active[it.x]) return;
-    const BImg &im = I[it.x];
+kb_residual(const int4 *__restrict__ seg, int nseg, const BImg *__restrict__ I, const uint8_t *__restrict__ flags,
+            const BLev *__restrict__ L) {
+    const SegItem it = seg_item(seg, nseg, blockIdx.x);
+    const BImg &im = I[it.img];
+    const int fl = flags[it.img];
+    const bool use_e = fl & 2, parity = fl & 4;
     const double *u_in = parity ? im.u_alt : im.u;
     double *u_out = parity ? im.u : im.u_alt;
-    const BLev &l0 = L[it.x * MAX_LEVELS];
+    const BLev &l0 = L[it.img * MAX_LEVELS];
     // the last V-cycle's correction is the finest level's post-smoothing
     // output (or the single level's smoothing output)
     const float *e = use_e ? (im.nlev > 1 ? l0.eb : l0.ea) : nullptr;
     residual_block<float, C>(im.W, im.H, im.mask, u_in, e, use_e ? u_out : nullptr, im.f, nullptr, l0.r,
-                             im.partials, im.nblk, it.y, it.z, im.gx);
+                             im.partials, im.nblk, it.a, it.b, im.gx);
 }
 
 __global__ void __launch_bounds__(1024)
-kb_reduce(const int4 *__restrict__ items, const BImg *__restrict__ I, const uint8_t *__restrict__ active) {
-    const int4 it = items[blockIdx.x];
-    if (!active[it.x]) return;
-    const BImg &im = I[it.x];
-    reduce_partials_block(im.nblk, im.partials, im.norms, it.y);
+kb_reduce(const int4 *__restrict__ seg, int nseg, const BImg *__restrict__ I) {
+    const SegItem it = seg_item(seg, nseg, blockIdx.x);
+    const BImg &im = I[it.img];
+    reduce_partials_block(im.nblk, im.partials, im.norms, it.a);
 }
 
 template <int MODE, bool COARSEST>
 __global__ void __launch_bounds__(64)
-kb_schwarz(const int4 *__restrict__ items, int n, const BLev *__restrict__ L, const BImg *__restrict__ I,
-           const uint8_t *__restrict__ active) {
-    const int4 it = items[xcd_remap(blockIdx.x, n)];
-    if (active && !active[it.x]) return;
-    const BImg &im = I[it.x];
-    const BLev &l = L[it.x * MAX_LEVELS + it.y];
+kb_schwarz(const int4 *__restrict__ seg, int nseg, int n, const BLev *__restrict__ L, const BImg *__restrict__ I) {
+    const SegItem it = seg_item(seg, nseg, xcd_remap(blockIdx.x, n));
+    const BImg &im = I[it.img];
+    const BLev &l = L[it.img * MAX_LEVELS + it.lev];
     const int iters = COARSEST ? im.coarse_iters : im.local_iters;
     if (MODE == 0)
-        schwarz_block<0>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, nullptr, nullptr, 1, 1, l.ea, it.z,
-                         it.w);
+        schwarz_block<0>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, nullptr, nullptr, 1, 1, l.ea, it.a,
+                         it.b);
     else if (MODE == 1)
-        schwarz_block<1>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, l.ea, l.ec, l.Wc, l.Hc, l.eb, it.z,
-                         it.w);
+        schwarz_block<1>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, l.ea, l.ec, l.Wc, l.Hc, l.eb, it.a,
+                         it.b);
     else
         schwarz_block<2>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, nullptr, COARSEST ? l.aux : l.eb,
-                         nullptr, 1, 1, l.ea, it.z, it.w);
+                         nullptr, 1, 1, l.ea, it.a, it.b);
 }
 
-__global__ void kb_restrict(const int4 *__restrict__ items, const BLev *__restrict__ L, const BImg *__restrict__ I,
-                            const uint8_t *__restrict__ active) {
-    const int4 it = items[blockIdx.x];
-    if (!active[it.x]) return;
-    const BImg &im = I[it.x];
-    const BLev &l = L[it.x * MAX_LEVELS + it.y];
-    restrict_residual_at(it.z * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, l.r, l.ea, l.Wc, l.Hc, l.mask_c, l.r_c);
+__global__ void kb_restrict(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L,
+                            const BImg *__restrict__ I) {
+    const SegItem it = seg_item(seg, nseg, blockIdx.x);
+    const BImg &im = I[it.img];
+    const BLev &l = L[it.img * MAX_LEVELS + it.lev];
+    restrict_residual_at(it.a * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, l.r, l.ea, l.Wc, l.Hc, l.mask_c, l.r_c);
 }
 
 template <bool FROM_F>
-__global__ void kb_data_restrict(const int4 *__restrict__ items, const BLev *__restrict__ L,
+__global__ void kb_data_restrict(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L,
                                  const BImg *__restrict__ I) {
-    const int4 it = items[blockIdx.x];
-    const BImg &im = I[it.x];
-    const BLev &l = L[it.x * MAX_LEVELS + it.y];
+    const SegItem it = seg_item(seg, nseg, blockIdx.x);
+    const BImg &im = I[it.img];
+    const BLev &l = L[it.img * MAX_LEVELS + it.lev];
     const float *src = FROM_F ? im.f : l.aux;
-    data_restrict_at<float>(it.z * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, src, l.Wc, l.Hc, l.mask_c, l.aux_c);
+    data_restrict_at<float>(it.a * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, src, l.Wc, l.Hc, l.mask_c, l.aux_c);
 }
 
-__global__ void kb_fmg_prolong(const int4 *__restrict__ items, const BLev *__restrict__ L,
+__global__ void kb_fmg_prolong(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L,
                                const BImg *__restrict__ I) {
-    const int4 it = items[blockIdx.x];
-    const BImg &im = I[it.x];
-    const BLev &l = L[it.x * MAX_LEVELS + it.y];
+    const SegItem it = seg_item(seg, nseg, blockIdx.x);
+    const BImg &im = I[it.img];
+    const BLev &l = L[it.img * MAX_LEVELS + it.lev];
     // the coarser level's FMG result is in its ea
-    const BLev &c = L[it.x * MAX_LEVELS + it.y + 1];
-    fmg_prolong_at(it.z * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, l.aux, c.ea, l.Wc, l.Hc, l.eb);
+    const BLev &c = L[it.img * MAX_LEVELS + it.lev + 1];
+    fmg_prolong_at(it.a * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, l.aux, c.ea, l.Wc, l.Hc, l.eb);
 }
 
-__global__ void kb_fmg_prolong0(const int4 *__restrict__ items, const BLev *__restrict__ L,
+__global__ void kb_fmg_prolong0(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L,
                                 const BImg *__restrict__ I) {
-    const int4 it = items[blockIdx.x];
-    const BImg &im = I[it.x];
-    const BLev &l = L[it.x * MAX_LEVELS];
-    const BLev &c = L[it.x * MAX_LEVELS + 1];
-    fmg_prolong0_at(it.z * 256 + threadIdx.x, im.W, im.H, im.C, im.mask, c.ea, l.Wc, l.Hc, im.u);
+    const SegItem it = seg_item(seg, nseg, blockIdx.x);
+    const BImg &im = I[it.img];
+    const BLev &l = L[it.img * MAX_LEVELS];
+    const BLev &c = L[it.img * MAX_LEVELS + 1];
+    fmg_prolong0_at(it.a * 256 + threadIdx.x, im.W, im.H, im.C, im.mask, c.ea, l.Wc, l.Hc, im.u);
 }
 
-void launch_b_count(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s) {
-    if (n) hipLaunchKernelGGL(kb_count, dim3(n), dim3(256), 0, s, items, L, I);
+#define SEG_ARGS(ph) (ph).seg, (ph).nseg
+void launch_b_count(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s) {
+    if (ph.n) hipLaunchKernelGGL(kb_count, dim3(ph.n), dim3(256), 0, s, SEG_ARGS(ph), L, I);
 }
-void launch_b_init_u(const int4 *items, int n, const BImg *I, const uint8_t *active, hipStream_t s) {
-    if (n) hipLaunchKernelGGL(kb_init_u, dim3(n), dim3(256), 0, s, items, I, active);
+void launch_b_init_u(const BPhase &ph, const BImg *I, hipStream_t s) {
+    if (ph.n) hipLaunchKernelGGL(kb_init_u, dim3(ph.n), dim3(256), 0, s, SEG_ARGS(ph), I);
 }
-void launch_b_residual(const int4 *items, int n, int C, const BImg *I, const uint8_t *active, int use_e,
-                       int parity, const BLev *L, hipStream_t s) {
-    if (!n) return;
+void launch_b_residual(const BPhase &ph, int C, const BImg *I, const uint8_t *flags, const BLev *L, hipStream_t s) {
+    if (!ph.n) return;
     if (C == 3)
-        hipLaunchKernelGGL(kb_residual<3>, dim3(n), dim3(RED_THREADS), 0, s, items, I, active, use_e, parity, L);
+        hipLaunchKernelGGL(kb_residual<3>, dim3(ph.n), dim3(RED_THREADS), 0, s, SEG_ARGS(ph), I, flags, L);
     else
-        hipLaunchKernelGGL(kb_residual<1>, dim3(n), dim3(RED_THREADS), 0, s, items, I, active, use_e, parity, L);
+        hipLaunchKernelGGL(kb_residual<1>, dim3(ph.n), dim3(RED_THREADS), 0, s, SEG_ARGS(ph), I, flags, L);
 }
-void launch_b_reduce(const int4 *items, int n, const BImg *I, const uint8_t *active, hipStream_t s) {
-    if (n) hipLaunchKernelGGL(kb_reduce, dim3(n), dim3(1024), 0, s, items, I, active);
+void launch_b_reduce(const BPhase &ph, const BImg *I, hipStream_t s) {
+    if (ph.n) hipLaunchKernelGGL(kb_reduce, dim3(ph.n), dim3(1024), 0, s, SEG_ARGS(ph), I);
 }
-void launch_b_schwarz(int mode, bool coarsest, const int4 *items, int n, const BLev *L, const BImg *I,
-                      const uint8_t *active, hipStream_t s) {
-    if (!n) return;
-    if (mode == 0 && !coarsest) hipLaunchKernelGGL((kb_schwarz<0, false>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
-    if (mode == 0 && coarsest) hipLaunchKernelGGL((kb_schwarz<0, true>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
-    if (mode == 1) hipLaunchKernelGGL((kb_schwarz<1, false>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
-    if (mode == 2 && !coarsest) hipLaunchKernelGGL((kb_schwarz<2, false>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
-    if (mode == 2 && coarsest) hipLaunchKernelGGL((kb_schwarz<2, true>), dim3(n), dim3(64), 0, s, items, n, L, I, active);
+void launch_b_schwarz(int mode, bool coarsest, const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s) {
+    if (!ph.n) return;
+    const dim3 g(ph.n), b(64);
+    if (mode == 0 && !coarsest) hipLaunchKernelGGL((kb_schwarz<0, false>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 0 && coarsest) hipLaunchKernelGGL((kb_schwarz<0, true>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 1) hipLaunchKernelGGL((kb_schwarz<1, false>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 2 && !coarsest) hipLaunchKernelGGL((kb_schwarz<2, false>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 2 && coarsest) hipLaunchKernelGGL((kb_schwarz<2, true>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
 }
-void launch_b_restrict(const int4 *items, int n, const BLev *L, const BImg *I, const uint8_t *active, hipStream_t s) {
-    if (n) hipLaunchKernelGGL(kb_restrict, dim3(n), dim3(256), 0, s, items, L, I, active);
+void launch_b_restrict(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s) {
+    if (ph.n) hipLaunchKernelGGL(kb_restrict, dim3(ph.n), dim3(256), 0, s, SEG_ARGS(ph), L, I);
 }
-void launch_b_data_restrict(bool from_f, const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s) {
-    if (!n) return;
-    if (from_f) hipLaunchKernelGGL(kb_data_restrict<true>, dim3(n), dim3(256), 0, s, items, L, I);
-    else hipLaunchKernelGGL(kb_data_restrict<false>, dim3(n), dim3(256), 0, s, items, L, I);
+void launch_b_data_restrict(bool from_f, const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s) {
+    if (!ph.n) return;
+    if (from_f) hipLaunchKernelGGL(kb_data_restrict<true>, dim3(ph.n), dim3(256), 0, s, SEG_ARGS(ph), L, I);
+    else hipLaunchKernelGGL(kb_data_restrict<false>, dim3(ph.n), dim3(256), 0, s, SEG_ARGS(ph), L, I);
 }
-void launch_b_fmg_prolong(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s) {
-    if (n) hipLaunchKernelGGL(kb_fmg_prolong, dim3(n), dim3(256), 0, s, items, L, I);
+void launch_b_fmg_prolong(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s) {
+    if (ph.n) hipLaunchKernelGGL(kb_fmg_prolong, dim3(ph.n), dim3(256), 0, s, SEG_ARGS(ph), L, I);
 }
-void launch_b_fmg_prolong0(const int4 *items, int n, const BLev *L, const BImg *I, hipStream_t s) {
-    if (n) hipLaunchKernelGGL(kb_fmg_prolong0, dim3(n), dim3(256), 0, s, items, L, I);
+void launch_b_fmg_prolong0(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s) {
+    if (ph.n) hipLaunchKernelGGL(kb_fmg_prolong0, dim3(ph.n), dim3(256), 0, s, SEG_ARGS(ph), L, I);
 }
+#undef SEG_ARGS
 
 }  // namespace hdi

@@ -1,0 +1,150 @@
+"""GPU tests of the request loop (hdi_server_*): requests of mixed kinds and
+sizes that run together give, each, bit-for-bit the result of running alone
+(inpainting through the batch engine, tonal through tonal_optimize on a worker
+stream); admission waits for arena memory; bad requests fail alone."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2401_06747_amd as hdi
+from oracle import inpaint as oi
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GiB = 1 << 30
+
+
+def _inst(H, W, C, d, item):
+    f = synth.textured_image(H, W, C, 5, item)
+    return (torch.tensor(f, dtype=torch.float32, device=DEV), torch.tensor(synth.gradient_mask(f, d), device=DEV))
+
+
+def _mix():
+    shapes = [(64, 96, 3, 0.05, hdi.INPAINT), (120, 200, 1, 0.02, hdi.TONAL), (257, 300, 3, 0.04, hdi.INPAINT),
+              (33, 40, 1, 0.08, hdi.INPAINT), (96, 128, 3, 0.03, hdi.TONAL), (300, 180, 1, 0.01, hdi.INPAINT),
+              (200, 256, 1, 0.06, hdi.INPAINT), (48, 64, 3, 0.05, hdi.TONAL)]
+    return [(_inst(H, W, C, d, i), kind) for i, (H, W, C, d, kind) in enumerate(shapes)]
+
+
+def _alone(kind, f, m):
+    if kind == hdi.INPAINT:
+        return hdi.inpaint_solve(f, m)[0]
+    return hdi.tonal_optimize(f, m)[0]
+
+
+def _run(server, reqs, gap_s=0.0):
+    tickets = []
+    for (f, m), kind in reqs:
+        tickets.append(server.submit(kind, f, m))
+        if gap_s:
+            time.sleep(gap_s)
+    server.drain()
+    out = []
+    for t in tickets:
+        r = server.poll(t)
+        assert r is not None
+        out.append(r)
+    return out
+
+
+def test_mixed_requests_equal_their_solo_results():
+    reqs = _mix()
+    with hdi.Server(2 * GiB, max_slots=8, tonal_workers=2) as srv:
+        res = _run(srv, reqs)
+    for ((f, m), kind), (out, rep) in zip(reqs, res):
+        assert rep["status"] == 0, rep
+        assert torch.equal(out, _alone(kind, f, m)), (kind, tuple(f.shape))
+        assert rep["t_submit_ms"] <= rep["t_start_ms"] <= rep["t_done_ms"]
+    # the inpainting requests shared rounds
+    assert max(rep["max_running"] for (_, kind), (_, rep) in zip(reqs, res) if kind == hdi.INPAINT) >= 2
+
+
+def test_requests_join_a_running_batch():
+    """A long solve is running when small requests arrive: they join its rounds
+    and end before it, each with its solo result."""
+    big = _inst(2160, 3840, 1, 0.02, 50)
+    tight = hdi.SolveParams(rel_tol=1e-10)
+    small = [_inst(64 + 8 * i, 80, 1, 0.05, 60 + i) for i in range(4)]
+    with hdi.Server(4 * GiB, max_slots=8, tonal_workers=1) as srv:
+        tb = srv.submit(hdi.INPAINT, *big, params=tight)
+        ts = []
+        for f, m in small:
+            time.sleep(0.0005)
+            ts.append(srv.submit(hdi.INPAINT, f, m))
+        srv.drain()
+        ub, rb = srv.poll(tb)
+        outs = [srv.poll(t) for t in ts]
+    assert rb["status"] == 0 and torch.equal(ub, hdi.inpaint_solve(*big, params=tight)[0])
+    for (f, m), (u, r) in zip(small, outs):
+        assert r["status"] == 0
+        assert torch.equal(u, hdi.inpaint_solve(f, m)[0])
+    assert rb["max_running"] >= 2
+    joined = [r for _, r in outs if r["t_start_ms"] > rb["t_start_ms"] and r["t_done_ms"] < rb["t_done_ms"]]
+    assert joined, (rb, [r for _, r in outs])
+
+
+def test_admission_waits_for_memory_and_budget_error():
+    reqs = [(_inst(300, 400, 3, 0.03, 70 + i), hdi.INPAINT) for i in range(4)]
+    need = hdi.Server.request_bytes(hdi.INPAINT, (3, 300, 400))
+    # room for one request at a time (plus the engine tables, well under 1 MiB)
+    assert need > 4 << 20
+    with hdi.Server(need + need // 2 + (1 << 20), max_slots=4, tonal_workers=1) as srv:
+        res = _run(srv, reqs)
+        for ((f, m), _), (u, rep) in zip(reqs, res):
+            assert rep["status"] == 0 and rep["max_running"] == 1
+            assert torch.equal(u, hdi.inpaint_solve(f, m)[0])
+        # starts are serialised by memory: each after the previous one ended
+        starts = sorted(r["t_start_ms"] for _, r in res)
+        dones = sorted(r["t_done_ms"] for _, r in res)
+        assert all(s >= d - 1e-3 for s, d in zip(starts[1:], dones[:-1]))
+        f, m = _inst(1080, 1920, 3, 0.03, 80)
+        with pytest.raises(hdi.HdiError) as ei:
+            srv.submit(hdi.INPAINT, f, m)
+        assert ei.value.status == 6
+
+
+def test_failed_request_does_not_disturb_the_others():
+    reqs = _mix()[:4]
+    (f1, m1), k1 = reqs[1]
+    reqs[1] = ((f1, torch.zeros_like(m1)), k1)     # empty mask: singular system
+    (f2, m2), _ = reqs[2]
+    reqs[2] = ((f2, torch.zeros_like(m2)), hdi.INPAINT)
+    with hdi.Server(2 * GiB, max_slots=8, tonal_workers=1) as srv:
+        res = _run(srv, reqs)
+    assert res[1][1]["status"] == 2 and res[2][1]["status"] == 2
+    for i in (0, 3):
+        (f, m), kind = reqs[i]
+        assert res[i][1]["status"] == 0
+        assert torch.equal(res[i][0], _alone(kind, f, m))
+
+
+def test_plain_server_and_host_requests():
+    reqs = _mix()[:5]
+    with hdi.Server(2 * GiB, plain=True) as srv:
+        res = _run(srv, reqs, gap_s=0.001)
+    for ((f, m), kind), (out, rep) in zip(reqs, res):
+        assert rep["status"] == 0 and torch.equal(out, _alone(kind, f, m))
+    # pinned host inputs and outputs go through the copy stream
+    (f, m), _ = reqs[2]
+    fh, mh = f.cpu().pin_memory(), m.cpu().pin_memory()
+    with hdi.Server(1 * GiB) as srv:
+        t = srv.submit(hdi.INPAINT, fh, mh)
+        t2 = srv.submit(hdi.TONAL, fh, mh)
+        srv.drain()
+        (u, r), (g, r2) = srv.poll(t), srv.poll(t2)
+    assert not u.is_cuda and r["status"] == 0 and r2["status"] == 0
+    assert torch.equal(u, hdi.inpaint_solve(f, m)[0].cpu())
+    assert torch.equal(g, hdi.tonal_optimize(f, m)[0].cpu())
+
+
+def test_served_result_matches_oracle():
+    (f, m), _ = _mix()[0]
+    with hdi.Server(1 * GiB) as srv:
+        t = srv.submit(hdi.INPAINT, f, m)
+        srv.drain()
+        u, rep = srv.poll(t)
+    ref = oi.inpaint(f.cpu().numpy().astype(np.float64), m.cpu().numpy())
+    assert oi.rel_l2(u.cpu().numpy(), ref).max() <= 1e-5
