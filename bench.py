@@ -118,6 +118,152 @@ def roofline_of(ks):
     return r
 
 
+def _median(xs):
+    return float(np.median(np.asarray(xs, dtype=np.float64)))
+
+
+def batch_bench(torch, hdi, synth, dev, n_images=64, reps=3):
+    """Uneven batch: 64 images (512..2048 x 512..1152, half gray, half RGB,
+    1-10% FS-gradient masks) solved by 64 plain calls and by one batched call,
+    both with default parameters and with per-image autotuned ones."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2401_06747_amd import autotune
+    specs = synth.config4_specs(n_images)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(8) as ex:
+        insts = list(ex.map(lambda a: synth.config4_item(*a), enumerate(specs)))
+    log(f"batch workload generated in {time.perf_counter() - t0:.1f} s")
+    fs = [torch.tensor(i.f, dtype=torch.float32, device=dev) for i in insts]
+    ms = [torch.tensor(i.mask, device=dev) for i in insts]
+    outs_p = [torch.empty(f.shape, dtype=torch.float64, device=dev) for f in fs]
+    outs_b = [torch.empty(f.shape, dtype=torch.float64, device=dev) for f in fs]
+    from paper_2401_06747_amd import _lib
+    L = _lib.lib()
+    ws_single = hdi.workspace(max(L.hdi_inpaint_workspace_bytes(hdi._img(f.shape)) for f in fs), dev)
+    jobs = (_lib.hdi_job * len(fs))(*[_lib.hdi_job(hdi._img(f.shape), m.data_ptr(), f.data_ptr(), u.data_ptr())
+                                      for f, m, u in zip(fs, ms, outs_b)])
+    ws_batch = hdi.workspace(L.hdi_batch_workspace_bytes(len(fs), jobs), dev)
+    mpx = sum(f.numel() for f in fs) / 1e6
+
+    def plain(params):
+        for f, m, u, p in zip(fs, ms, outs_p, params):
+            _, r = hdi.inpaint_solve(f, m, params=p, ws=ws_single, out=u)
+            assert r["status"] == 0, r
+
+    def batched(params):
+        _, reps_ = hdi.solve_batch(fs, ms, params=params, ws=ws_batch, outs=outs_b)
+        assert all(r["status"] == 0 for r in reps_)
+
+    def timed(fn, params):
+        fn(params)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn(params)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return _median(ts)
+
+    default = [hdi.SolveParams()] * len(fs)
+    t_plain = timed(plain, default)
+    t_batch = timed(batched, default)
+    equal = all(torch.equal(a, b) for a, b in zip(outs_p, outs_b))
+    t0 = time.perf_counter()
+    tuner = autotune.Autotuner(None, reps=1)
+    tuned = [tuner.params_for(f, m) for f, m in zip(fs, ms)]
+    t_tune = time.perf_counter() - t0
+    t_plain_tuned = timed(plain, tuned)
+    t_batch_tuned = timed(batched, tuned)
+    equal_tuned = all(torch.equal(a, b) for a, b in zip(outs_p, outs_b))
+    res = {"workload": f"{len(fs)} uneven images 512..2048 x 512..1152, half gray half RGB, 1-10% FS-gradient "
+                       f"masks, inpaint to rel-res 1e-6",
+           "megapixels": round(mpx, 2),
+           "plain_images_per_s": round(len(fs) / t_plain, 2), "batched_images_per_s": round(len(fs) / t_batch, 2),
+           "speedup": round(t_plain / t_batch, 3),
+           "tuned_plain_images_per_s": round(len(fs) / t_plain_tuned, 2),
+           "tuned_batched_images_per_s": round(len(fs) / t_batch_tuned, 2),
+           "tuned_speedup_vs_default_plain": round(t_plain / t_batch_tuned, 3),
+           "autotune_buckets": len(tuner.cache), "autotune_s": round(t_tune, 2),
+           "batched_equals_plain_bitwise": bool(equal and equal_tuned)}
+    return res
+
+
+def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=200, seed=5):
+    """Serving stream: Poisson arrivals of inpaint and tonal requests over sizes
+    {256^2, 1024x768, 1920x1080, 3840x2160}, gray or RGB, 1-8% masks, at 0.8x
+    and 1.5x the plain path's capacity; latency from submission to result."""
+    from concurrent.futures import ThreadPoolExecutor
+    sizes = [(256, 256), (768, 1024), (1080, 1920), (2160, 3840)]
+    rng = np.random.default_rng(seed)
+    classes = [(H, W, C) for (H, W) in sizes for C in (1, 3)]
+    dens = {c: float(rng.uniform(0.01, 0.08)) for c in classes}
+
+    def make(k, c):
+        H, W, C = c
+        if (H, W, C) == (2160, 3840, 3):
+            return inst4k.f, inst4k.mask
+        f = synth.textured_image(H, W, C, 5, 100 + k)
+        return f, synth.gradient_mask(f, dens[c])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(8) as ex:
+        pool = list(ex.map(lambda kc: make(*kc), enumerate(classes)))
+    log(f"serving pool generated in {time.perf_counter() - t0:.1f} s")
+    pool = [(torch.tensor(f, dtype=torch.float32, device=dev), torch.tensor(m, device=dev)) for f, m in pool]
+    kinds = (hdi.INPAINT, hdi.TONAL)
+    # plain service time per (class, kind), after one warm run each
+    svc = {}
+    for ci, (f, m) in enumerate(pool):
+        for kind in kinds:
+            fn = (lambda: hdi.inpaint_solve(f, m)) if kind == hdi.INPAINT else (lambda: hdi.tonal_optimize(f, m))
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            svc[(ci, kind)] = time.perf_counter() - t
+    mu_plain = 1.0 / float(np.mean(list(svc.values())))
+    req_class = rng.integers(0, len(pool), n_requests)
+    req_kind = rng.integers(0, 2, n_requests)
+    gaps = rng.exponential(1.0, n_requests)
+    outs = [torch.empty(pool[c][0].shape, dtype=torch.float64, device=dev) for c in req_class]
+    torch.cuda.synchronize()
+
+    def run(load, plain):
+        lam = load * mu_plain
+        arrive = np.cumsum(gaps) / lam
+        srv = hdi.Server(32 << 30, max_slots=32, tonal_workers=2, plain=plain, device=dev)
+        try:
+            tickets = []
+            t0 = time.perf_counter()
+            for i in range(n_requests):
+                wait = arrive[i] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                f, m = pool[req_class[i]]
+                tickets.append(srv.submit(kinds[req_kind[i]], f, m, out=outs[i]))
+            srv.drain()
+            reps_ = [srv.poll(t)[1] for t in tickets]
+        finally:
+            srv.close()
+        assert all(r["status"] == 0 for r in reps_), [r for r in reps_ if r["status"]][:3]
+        lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in reps_])
+        span = max(r["t_done_ms"] for r in reps_) - min(r["t_submit_ms"] for r in reps_)
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "solves_per_s": round(n_requests / (span * 1e-3), 2),
+                "max_batch": int(max(r["max_running"] for r in reps_))}
+
+    res = {"workload": f"{n_requests} Poisson arrivals, inpaint/tonal 50/50, sizes 256^2..3840x2160, gray/RGB, "
+                       f"1-8% FS-gradient masks (one image per size and channel count)",
+           "mu_plain_per_s": round(mu_plain, 2)}
+    for load in (0.8, 1.5):
+        res[f"load_{load}"] = {"lambda_per_s": round(load * mu_plain, 2), "served": run(load, False),
+                               "plain": run(load, True)}
+        log(f"serving at {load}x plain capacity: {res[f'load_{load}']}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +271,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-calibration", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
@@ -192,6 +341,13 @@ def main():
                 f"{(fl / (ms * 1e-3) / 1e12 if ms > 0 else 0):6.2f} TFLOP/s")
     roofline = roofline_of(ks)
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_bench(torch, hdi, synth, dev)
+        log(f"batch: {batch}")
+    serving = None
+    if not args.no_serve:
+        serving = serve_bench(torch, hdi, synth, dev, inst, n_requests=args.serve_requests)
     copy = None
     if not args.no_copy_calibration:
         copy = copy_calibration(torch, dev)
@@ -212,6 +368,7 @@ def main():
                    "tonal_outer_iters": rt["outer_iters"], "tonal_inner_solves": rt["inner_solves"],
                    "mse_initial": round(rt["mse_initial"], 4), "mse_final": round(rt["mse_final"], 4)},
         "roofline": roofline, "cpu_baseline": cpu, "copy_calibration": copy,
+        "batch": batch, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

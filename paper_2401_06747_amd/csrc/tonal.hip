@@ -205,7 +205,15 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
         return w;
     };
 
-    int it = 0, restarts = 0;
+    int it = 0, restarts = 0, fallbacks = 0, tightenings = 0;
+    // inexact-Krylov factor of the inner tolerances; tightened when the outer
+    // residual stalls (the products' errors then limit what the recurrence
+    // can reach, which happens for sparse masks, where A^{-1} is large)
+    double fac = 1e-3, best = 1e300;
+    int stall = 0;
+    // stationary RAS step length: halved whenever the residual grows (with
+    // 32x32 blocks on sparse masks the undamped iteration can diverge)
+    double omega = 1.0, prev_worst = worst(), best_ever = worst();
     bool done = worst() <= tc.rel_tol;
     int32_t status = HDI_OK;
     double pq_prev[3] = {1, 1, 1};
@@ -224,8 +232,8 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
         // relative to its own size, so its warm-started solves tighten with it.
         const double tol_in =
             tc.mode == HDI_TONAL_RAS
-                ? std::min(1e-4, std::max(tight, 1e-3 * rmin))
-                : std::min(1e-3, std::max(tight, 1e-3 * tc.rel_tol / std::max(rmin, 1e-300)));
+                ? std::min(1e-4, std::max(tight, fac * rmin))
+                : std::min(1e-3, std::max(tight, fac * tc.rel_tol / std::max(rmin, 1e-300)));
 
         const Blocks1D tbx = make_blocks(X.W, tc.overlap), tby = make_blocks(X.H, tc.overlap);
         const double ras_px = (double)tbx.count * tby.count * std::min(32, X.W) * std::min(32, X.H) * C;
@@ -240,12 +248,21 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
         if (tc.mode == HDI_TONAL_RAS) {
             // Alg. 2: local corrections, then the global residual with warm starts
             ras_sweep();
-            const double one[3] = {1, 1, 1};
-            launch_axpby(m, C, one, one, t.zK, t.gK, s);
+            const double one[3] = {1, 1, 1}, om[3] = {omega, omega, omega};
+            launch_axpby(m, C, om, one, t.zK, t.gK, s);
             ++it;
             T_ST(X.normal_residual(true, tol_in, sse));
             T_ST(X.norms(t.rK, rnorm));
             for (int c = 0; c < C; ++c) rel[c] = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : rnorm[c];
+            if (worst() > prev_worst) omega = std::max(omega * 0.5, 1.0 / 64);
+            prev_worst = worst();
+            best_ever = std::min(best_ever, worst());
+            if (worst() > 10.0 * best_ever || (omega <= 1.0 / 64 && worst() > 1.05 * best_ever)) {
+                status = HDI_ERR_NO_CONVERGENCE;
+                set_error("tonal: stationary RAS diverges on this mask (relative normal residual %.3e); "
+                          "the flexible-CG mode converges", worst());
+                break;
+            }
         } else {
             // flexible CG (Notay's FCG with one stored direction)
             const double *z = t.rK;
@@ -254,11 +271,28 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
                 z = t.zK;
             }
             double beta[3] = {0, 0, 0};
-            if (!first) {
-                const double *a[1] = {z}, *b[1] = {t.qprev};
+            {
+                // one reduction: <z, r> and <z, z> for the descent test, and
+                // <z, q_prev> for the FCG coefficient
+                const double *a[3] = {z, z, z}, *b[3] = {t.rK, z, t.qprev};
                 double d[4][3];
-                T_ST(X.dots(1, a, b, d));
-                for (int c = 0; c < C; ++c) beta[c] = d[0][c] / pq_prev[c];
+                T_ST(X.dots(first ? 2 : 3, a, b, d));
+                bool descent = true;
+                for (int c = 0; c < C; ++c)
+                    if (rel[c] > 0.5 * tc.rel_tol && !(d[0][c] > 1e-3 * std::sqrt(d[1][c]) * rnorm[c])) descent = false;
+                if (!descent) {
+                    // the preconditioned direction is (nearly) orthogonal to the
+                    // residual: take the plain normal-equation residual this step
+                    z = t.rK;
+                    ++fallbacks;
+                    if (!first) {
+                        const double *a1[1] = {z}, *b1[1] = {t.qprev};
+                        T_ST(X.dots(1, a1, b1, d));
+                        for (int c = 0; c < C; ++c) d[2][c] = d[0][c];
+                    }
+                }
+                if (!first)
+                    for (int c = 0; c < C; ++c) beta[c] = d[2][c] / pq_prev[c];
             }
             const double one[3] = {1, 1, 1};
             double nb[3];
@@ -291,8 +325,24 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             for (int c = 0; c < C; ++c) rel[c] = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : rnorm[c];
         }
         if (tc.flags & HDI_TONAL_TRACE)
-            fprintf(stderr, "[hdi tonal] it %d mode %d rel %.3e tol_in %.1e solves %d vcycles %d\n", it, tc.mode,
-                    worst(), tol_in, X.solves, X.vcycles);
+            fprintf(stderr, "[hdi tonal] it %d mode %d rel %.3e tol_in %.1e solves %d vcycles %d fallbacks %d\n", it,
+                    tc.mode, worst(), tol_in, X.solves, X.vcycles, fallbacks);
+        if (worst() < 0.95 * best) {
+            best = worst();
+            stall = 0;
+        } else if (tc.mode != HDI_TONAL_RAS && ++stall >= 3 && tightenings < 3 && worst() > tc.rel_tol) {
+            // stalled: tighten the inner solves and restart from the true residual
+            fac *= 1e-2;
+            ++tightenings;
+            stall = 0;
+            T_ST(X.normal_residual(false, tight, sse));
+            T_ST(X.norms(t.rK, rnorm));
+            for (int c = 0; c < C; ++c) rel[c] = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : rnorm[c];
+            best = worst();
+            first = true;
+            done = worst() <= tc.rel_tol;
+            continue;
+        }
         if (worst() <= 0.5 * tc.rel_tol || (tc.mode == HDI_TONAL_RAS && worst() <= tc.rel_tol)) {
             // true normal residual with tight solves
             T_ST(X.normal_residual(false, tight, sse));

@@ -231,7 +231,8 @@ __global__ void k_axpby(int m, int C, Coef3 k, const double *__restrict__ x, dou
     if (j >= m) return;
     for (int c = 0; c < C; ++c) {
         const size_t o = (size_t)c * m + j;
-        y[o] = k.a[c] * x[o] + k.b[c] * y[o];
+        // with b = 0, y is output only: it may hold anything (a fresh direction)
+        y[o] = k.b[c] != 0.0 ? k.a[c] * x[o] + k.b[c] * y[o] : k.a[c] * x[o];
     }
 }
 

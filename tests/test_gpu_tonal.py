@@ -107,3 +107,21 @@ def test_warm_start_from_optimum_returns_immediately():
     g2, r2 = hdi.tonal_optimize(ft, mt, g0=g1, params=hdi.TonalParams(rel_tol=1e-6))
     assert r2["status"] == 0 and r2["outer_iters"] == 0
     assert torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("mode", [hdi.PCG_RAS, hdi.RAS, hdi.CGNR])
+def test_poisoned_workspace_gives_identical_results(mode):
+    """Every workspace byte tonal_optimize reads was written by it first: a
+    workspace full of NaN bit patterns gives the same g (regression test for the
+    first flexible-CG direction, formed as z + 0 * p before p was ever set)."""
+    from paper_2401_06747_amd import _lib
+    f = synth.textured_image(96, 128, 3, 5, 1)
+    m = synth.gradient_mask(f, 0.03)
+    ft = torch.tensor(f, dtype=torch.float32, device=DEV)
+    mt = torch.tensor(m, device=DEV)
+    n = _lib.lib().hdi_tonal_workspace_bytes(_lib.hdi_image(128, 96, 3))
+    p = hdi.TonalParams(mode=mode)
+    g0, r0 = hdi.tonal_optimize(ft, mt, params=p, ws=torch.zeros(n, dtype=torch.uint8, device=DEV))
+    g1, r1 = hdi.tonal_optimize(ft, mt, params=p, ws=torch.full((n,), 0xFF, dtype=torch.uint8, device=DEV))
+    assert r0["status"] == 0 and r1["status"] == 0, (r0, r1)
+    assert torch.equal(g0, g1)
