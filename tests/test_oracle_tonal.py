@@ -136,3 +136,10 @@ def test_cg_path_matches_direct_path():
     a = ot.tonal_optimize(f, m, method="direct")
     b = ot.tonal_optimize(f, m, method="cg")
     np.testing.assert_allclose(a, b, atol=1e-7)
+
+
+def test_psnr_closed_form():
+    """PSNR = 10 log10(255^2 / MSE) (the quality measure reported beside the MSE
+    in Sec. 6.3): an MSE of 255^2 / 100 is 20 dB, each 10x smaller MSE adds 10 dB."""
+    assert abs(ot.psnr(255.0 ** 2 / 100) - 20.0) < 1e-12
+    assert abs(ot.psnr(255.0 ** 2 / 1000) - 30.0) < 1e-12
