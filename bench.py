@@ -122,6 +122,53 @@ def _median(xs):
     return float(np.median(np.asarray(xs, dtype=np.float64)))
 
 
+def densify_bench(torch, hdi, synth, dev, steps=8, target=0.04, reps=3):
+    """Densification loop (Alg. 1) on 1920x1080 gray: 0.5% uniform start, 8
+    steps of equal size up to 4%; each step is error map, densify_step and an
+    inpainting solve warm-started from the previous solution."""
+    inst = synth.config3()
+    f = torch.tensor(inst.f, dtype=torch.float32, device=dev)
+    m0 = torch.tensor(inst.mask, device=dev)
+    H, W = inst.mask.shape
+    n0 = int(inst.mask.sum())
+    delta = int(target * H * W) - n0
+    targets = [n0 + int(np.floor(delta * k / steps + 0.5)) for k in range(1, steps + 1)]
+    ws_d = hdi.workspace(hdi._lib.lib().hdi_densify_workspace_bytes(W, H), dev)
+
+    def loop(times):
+        m = m0.clone()
+        u, r = hdi.inpaint_solve(f, m)
+        prev = n0
+        for t in targets:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            err = hdi.error_map(u, f)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            added = hdi.densify_step(m, err, t - prev, ws=ws_d)
+            t2 = time.perf_counter()
+            u, r = hdi.inpaint_solve(f, m, u0=u)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            assert r["status"] == 0 and added.numel() == t - prev
+            prev = t
+            times.append((t1 - t0, t2 - t1, t3 - t2))
+        return int(m.sum())
+
+    loop([])
+    runs = []
+    for _ in range(reps):
+        times = []
+        known = loop(times)
+        runs.append(np.array(times))
+    tm = np.median(np.stack(runs), axis=0)     # per step, per phase
+    return {"workload": f"{W}x{H} gray, {n0} uniform start pixels, {steps} densification steps to {targets[-1]} "
+                        f"(4%), Delaunay cells, warm-started solves",
+            "loop_ms": round(float(tm.sum()) * 1e3, 2), "error_map_ms": round(float(tm[:, 0].mean()) * 1e3, 3),
+            "densify_step_ms": round(float(tm[:, 1].mean()) * 1e3, 3),
+            "solve_ms": round(float(tm[:, 2].mean()) * 1e3, 3), "final_known": known}
+
+
 def batch_bench(torch, hdi, synth, dev, n_images=64, reps=3):
     """Uneven batch: 64 images (512..2048 x 512..1152, half gray, half RGB,
     1-10% FS-gradient masks) solved by 64 plain calls and by one batched call,
@@ -272,6 +319,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-calibration", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--no-densify", action="store_true", help="skip the densification-loop measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=200)
     args = ap.parse_args()
@@ -341,6 +389,10 @@ def main():
                 f"{(fl / (ms * 1e-3) / 1e12 if ms > 0 else 0):6.2f} TFLOP/s")
     roofline = roofline_of(ks)
 
+    densify = None
+    if not args.no_densify:
+        densify = densify_bench(torch, hdi, synth, dev)
+        log(f"densify: {densify}")
     batch = None
     if not args.no_batch:
         batch = batch_bench(torch, hdi, synth, dev)
@@ -368,7 +420,7 @@ def main():
                    "tonal_outer_iters": rt["outer_iters"], "tonal_inner_solves": rt["inner_solves"],
                    "mse_initial": round(rt["mse_initial"], 4), "mse_final": round(rt["mse_final"], 4)},
         "roofline": roofline, "cpu_baseline": cpu, "copy_calibration": copy,
-        "batch": batch, "serving": serving,
+        "densify": densify, "batch": batch, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

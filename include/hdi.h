@@ -142,11 +142,12 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
  *                recomputed with tight inner solves (default 1e-6)
  *   max_outer    outer iteration cap (default 500)
  *   mode         HDI_TONAL_PCG_RAS / HDI_TONAL_RAS / HDI_TONAL_CGNR
- *   overlap      overlap of the 32x32 blocks of the RAS sweep (default 6,
- *                Sec. 5.2 uses 6)
- *   local_outer  CG steps on each block's local normal equations (default 4)
- *   local_inner  CG steps of each local inpainting inside them (default 32;
- *                fewer steps truncate the local echoes, which makes the
+ *   overlap      overlap of the 32x32 blocks of the RAS sweep (default 14;
+ *                Sec. 5.2 uses 6 with 64x64 blocks: with 32x32 blocks a wider
+ *                overlap buys fewer outer iterations than its sweep costs)
+ *   local_outer  CG steps on each block's local normal equations (default 3)
+ *   local_inner  CG steps of each local inpainting inside them (default 24;
+ *                far fewer steps truncate the local echoes, which makes the
  *                stationary RAS iteration overshoot)
  *   flags        HDI_TONAL_INIT_FROM_F
  *   inner        parameters of the global inpainting solves (rel_tol is set
@@ -251,6 +252,14 @@ void hdi_server_destroy(hdi_server *srv);
 
 #define HDI_PART_DELAUNAY 0   /* triangles of mask pixels (Sec. 4.1) */
 #define HDI_PART_VORONOI 1    /* Voronoi cells of mask pixels (the ablation of Sec. 6.2) */
+
+/* Error map that drives densification (Sec. 4.1: the squared error of the
+ * current reconstruction, summed over the colour channels):
+ * err_i = fp32(sum_c (u_c,i - f_c,i)^2), accumulated in FP64 in channel order
+ * and rounded once to nearest, so equal inputs give equal maps everywhere.
+ *   u    C x H x W float64, f C x H x W float32, err H x W float32 (device)
+ * Enqueued on `stream`; returns without waiting. */
+int32_t hdi_error_map(hdi_image img, const double *u, const float *f, float *err, void *stream);
 
 /* Bytes of workspace densify_step needs for a width x height mask. 0 on bad sizes. */
 size_t hdi_densify_workspace_bytes(int32_t width, int32_t height);

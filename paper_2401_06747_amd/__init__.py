@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import HdiError, check
 
-__all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "Server", "DELAUNAY", "VORONOI",
+__all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "error_map", "Server", "DELAUNAY", "VORONOI",
            "INPAINT", "TONAL", "hdi_block_count", "SolveParams", "TonalParams", "HdiError", "PCG_RAS", "RAS", "CGNR"]
 
 PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
@@ -41,9 +41,9 @@ class TonalParams:
     rel_tol: float = 0.0       # 0 -> 1e-6
     max_outer: int = 0         # 0 -> 500
     mode: int = 0              # PCG_RAS, RAS or CGNR
-    overlap: int = 0           # 0 -> 6
-    local_outer: int = 0       # 0 -> 4
-    local_inner: int = 0       # 0 -> 32
+    overlap: int = 0           # 0 -> 14
+    local_outer: int = 0       # 0 -> 3
+    local_inner: int = 0       # 0 -> 24
     flags: int = 0
     inner: SolveParams | None = None
 
@@ -141,6 +141,17 @@ def tonal_optimize(f: torch.Tensor, mask: torch.Tensor, g0: torch.Tensor | None 
     if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
         check(st)
     return (g, report, u) if want_u else (g, report)
+
+
+def error_map(u: torch.Tensor, f: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """err = fp32(sum_c (u - f)^2) per pixel (FP64 sum, one rounding)."""
+    if u.shape != f.shape or u.dim() != 3 or u.dtype != torch.float64 or f.dtype != torch.float32:
+        raise ValueError("need u (C,H,W) float64 and f (C,H,W) float32")
+    if not (u.is_cuda and f.is_cuda and u.is_contiguous() and f.is_contiguous()):
+        raise ValueError("u and f must be contiguous GPU tensors")
+    err = out if out is not None else torch.empty(u.shape[1:], dtype=torch.float32, device=u.device)
+    check(_lib.lib().hdi_error_map(_img(u.shape), _ptr(u), _ptr(f), _ptr(err), _stream_ptr(u.device)))
+    return err
 
 
 def densify_step(mask: torch.Tensor, err: torch.Tensor, n_add: int, partition: int = DELAUNAY,

@@ -72,6 +72,7 @@ _SIGS = {
     "hdi_tonal_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
     "tonal_optimize": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                         ctypes.POINTER(hdi_tonal_params), ctypes.POINTER(hdi_tonal_report), _P]),
+    "hdi_error_map": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P]),
     "hdi_densify_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "densify_step": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32, _P,
                                       ctypes.POINTER(ctypes.c_int64), _P, ctypes.c_size_t, _P]),

@@ -438,11 +438,43 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
     return HDI_OK;
 }
 
+// Error map of the densification loop: e = fp32(sum_c (u_c - f_c)^2), summed in
+// FP64 in channel order and rounded once to nearest. Explicit _rn operations
+// keep the compiler from contracting the square and the sum into an FMA.
+__global__ void k_error_map(int N, int C, const double *__restrict__ u, const float *__restrict__ f,
+                            float *__restrict__ e) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double acc = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const double d = __dsub_rn(u[(size_t)c * N + i], (double)f[(size_t)c * N + i]);
+        acc = __dadd_rn(acc, __dmul_rn(d, d));
+    }
+    e[i] = __double2float_rn(acc);
+}
+
 }  // namespace hdi
 
 using namespace hdi;
 
 extern "C" {
+
+int32_t hdi_error_map(hdi_image img, const double *u, const float *f, float *err, void *stream) {
+    if (!check_image(img)) return HDI_ERR_ARG;
+    if (!u || !f || !err) {
+        set_error("u, f and err must be non-null device pointers");
+        return HDI_ERR_ARG;
+    }
+    const int N = img.width * img.height;
+    hipLaunchKernelGGL(k_error_map, dim3((N + 255) / 256), dim3(256), 0, (hipStream_t)stream, N, img.channels, u, f,
+                       err);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("error map launch failed: %s", hipGetErrorString(e));
+        return HDI_ERR_HIP;
+    }
+    return HDI_OK;
+}
 
 size_t hdi_densify_workspace_bytes(int32_t width, int32_t height) {
     if (width < 1 || height < 1 || (int64_t)width * height > (int64_t)1 << 30) return 0;

@@ -407,9 +407,9 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
     tc.rel_tol = (params && params->rel_tol > 0) ? params->rel_tol : 1e-6;
     tc.max_outer = (params && params->max_outer > 0) ? params->max_outer : 500;
     tc.mode = params ? params->mode : HDI_TONAL_PCG_RAS;
-    tc.overlap = (params && params->overlap > 0) ? params->overlap : 6;
-    tc.local_outer = (params && params->local_outer > 0) ? params->local_outer : 4;
-    tc.local_inner = (params && params->local_inner > 0) ? params->local_inner : 32;
+    tc.overlap = (params && params->overlap > 0) ? params->overlap : 14;
+    tc.local_outer = (params && params->local_outer > 0) ? params->local_outer : 3;
+    tc.local_inner = (params && params->local_inner > 0) ? params->local_inner : 24;
     tc.flags = params ? params->flags : 0;
     if (tc.mode < 0 || tc.mode > 2 || !(tc.rel_tol < 1.0) || tc.overlap < 2 || tc.overlap > 16 || (tc.overlap & 1) ||
         tc.local_outer > 64 || tc.local_inner > 256) {

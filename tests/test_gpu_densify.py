@@ -70,7 +70,11 @@ def test_densification_loop_matches_oracle_at_every_step():
         mt = torch.tensor(mask, device=DEV)
         u, rep = hdi.inpaint_solve(f, mt)
         assert rep["status"] == 0
-        err = ((u - f.double()) ** 2).sum(0).float().cpu().numpy()
+        err_t = hdi.error_map(u, f)
+        err = err_t.cpu().numpy()
+        # the map itself: FP64 sum over channels, one rounding (numpy adds in channel order)
+        ref = ((u.cpu().numpy() - inst.f.astype(np.float32).astype(np.float64)) ** 2).sum(0).astype(np.float32)
+        assert np.array_equal(err, ref)
         added = _compare(mask, err, target - prev, hdi.DELAUNAY)
         assert len(added) == target - prev
         mask[np.unravel_index(added, mask.shape)] = 1
@@ -87,3 +91,13 @@ def test_errors():
     m[2, 2] = 1
     with pytest.raises(hdi.HdiError):
         hdi.densify_step(m, e, 3, partition=7)
+
+
+def test_error_map_rgb_bit_exact():
+    rng = np.random.default_rng(11)
+    u = rng.normal(100, 40, (3, 37, 91))
+    f = rng.uniform(0, 255, (3, 37, 91)).astype(np.float32)
+    e = hdi.error_map(torch.tensor(u, device=DEV), torch.tensor(f, device=DEV)).cpu().numpy()
+    d = u - f.astype(np.float64)
+    ref = ((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]).astype(np.float32)
+    assert np.array_equal(e, ref)
