@@ -408,10 +408,11 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
                                               const uint8_t *__restrict__ mask, const float *__restrict__ r,
                                               const float *__restrict__ e_in, const float *__restrict__ ec, int Wc,
                                               int Hc, float *__restrict__ e_out, const int t, const int c) {
+    // s_p: the search direction with a zero ring during CG; before that it
+    // holds the starting correction with its 1-pixel halo (MODE 1/2)
     __shared__ __attribute__((aligned(16))) float s_p[TILE + 2][LDS_W];
-    __shared__ __attribute__((aligned(16))) float s_e[TILE + 2][LDS_W];
     __shared__ uint8_t s_m[TILE + 2][TILE + 2];
-    __shared__ float s_c[20][20];   // coarse correction around the block (MODE 1)
+    __shared__ float s_c[MODE == 1 ? 20 : 1][20];   // coarse correction around the block (MODE 1)
 
     const int tx = t % ntx, ty = t / ntx;
     const int Tx = min(TILE, W), Ty = min(TILE, H);
@@ -419,34 +420,44 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     const int N = W * H;
     const float *rc = r + (size_t)c * N;
     const int lane = threadIdx.x;
+    const int bx = lane & 7, by = lane >> 3;
 
-    // MODE 1: stage the coarse correction around the block with clamped
-    // coordinates, so that the clamped bilinear lookup becomes plain indexing.
+    // The lane's own 4x4 right-hand side goes straight to registers (8 lanes
+    // cover a 32-pixel row); addresses are clamped so every load is unconditional.
+    float rown[16];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int xc = min(x0 + 4 * bx + i, W - 1), yc = min(y0 + 4 * by + j, H - 1);
+            rown[j * 4 + i] = r ? rc[yc * W + xc] : 0.f;
+        }
+    // MODE 1: the coarse correction around the block, with clamped coordinates
+    // so that the clamped bilinear lookup becomes plain indexing; its loads are
+    // in flight together with the first staging batch.
     const int X0 = ((x0 - 1) >> 1) - 1, Y0 = ((y0 - 1) >> 1) - 1;
+    constexpr int NCV = (400 + 63) / 64;
+    float cv[MODE == 1 ? NCV : 1];
     if (MODE == 1) {
         const float *ecc = ec + (size_t)c * Wc * Hc;
-        for (int k = lane; k < 400; k += 64) {
-            const int j = k / 20, i = k % 20;
-            const int X = min(max(X0 + i, 0), Wc - 1), Y = min(max(Y0 + j, 0), Hc - 1);
-            s_c[j][i] = ecc[Y * Wc + X];
+#pragma unroll
+        for (int h = 0; h < NCV; ++h) {
+            const int k = min(lane + 64 * h, 399);
+            const int X = min(max(X0 + k % 20, 0), Wc - 1), Y = min(max(Y0 + k / 20, 0), Hc - 1);
+            cv[h] = ecc[Y * Wc + X];
         }
-        __syncthreads();
     }
-    // Stage mask, right-hand side and (MODE 1/2) the current correction for the
-    // block and a 1-pixel halo, in coalesced rows of 34. Addresses are clamped
-    // into the image so that no load sits behind a branch: all loads of a lane
-    // are in flight before the first is used. s_m: 0 unknown, 1 known,
-    // 2 outside the image. The right-hand side goes to the interior of s_p
-    // (free until the CG starts) and the ring of s_p is zeroed (Dirichlet
-    // values outside the block). In MODE 1, e_in is exactly 0 on known pixels;
-    // in MODE 2 it holds the data there.
+    // Stage mask and (MODE 1/2) the starting correction for the block and a
+    // 1-pixel halo, in coalesced rows of 34. s_m: 0 unknown, 1 known, 2 outside
+    // the image. In MODE 1, e_in is exactly 0 on known pixels; in MODE 2 it
+    // holds the data there. MODE 0 starts from zero.
     constexpr int NST = (TILE + 2) * (TILE + 2);
     constexpr int NIT = (NST + 63) / 64;     // 19 rounds of 64 lanes
     constexpr int HALF = (NIT + 1) / 2;      // staged in two batches to bound register use
 #pragma unroll
     for (int batch = 0; batch < 2; ++batch) {
         int mraw[HALF];
-        float ev[HALF], rv[HALF];
+        float ev[HALF];
 #pragma unroll
         for (int h = 0; h < HALF; ++h) {
             const int k = lane + 64 * (batch * HALF + h);
@@ -455,7 +466,14 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
             const int pc = yc * W + xc;
             mraw[h] = mask[pc];
             ev[h] = MODE != 0 ? e_in[(size_t)c * N + pc] : 0.f;
-            rv[h] = r ? rc[pc] : 0.f;
+        }
+        if (MODE == 1 && batch == 0) {
+#pragma unroll
+            for (int h = 0; h < NCV; ++h) {
+                const int k = lane + 64 * h;
+                if (k < 400) s_c[k / 20][k % 20] = cv[h];
+            }
+            __syncthreads();
         }
 #pragma unroll
         for (int h = 0; h < HALF; ++h) {
@@ -466,8 +484,9 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
                 const bool in = x >= 0 && x < W && y >= 0 && y < H;
                 const int mk = in ? (mraw[h] != 0) : 2;
                 s_m[ly][lx] = (uint8_t)mk;
+                float v = 0.f;
                 if (MODE != 0) {
-                    float v = in ? ev[h] : 0.f;
+                    v = in ? ev[h] : 0.f;
                     if (MODE == 1) {
                         if (mk == 0) {
                             // cell-centred bilinear: 3/4 parent, 1/4 next cell on each side of x and y
@@ -478,44 +497,53 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
                             v = 0.f;
                         }
                     }
-                    s_e[ly][COL0 - 1 + lx] = v;
                 }
-                const bool interior = lx >= 1 && lx <= TILE && ly >= 1 && ly <= TILE;
-                s_p[ly][COL0 - 1 + lx] = interior ? rv[h] : 0.f;
+                s_p[ly][COL0 - 1 + lx] = v;
             }
         }
     }
     __syncthreads();
 
-    const int bx = lane & 7, by = lane >> 3;
+    // Local right-hand side r - A e_start on the block's unknown pixels; the
+    // CG iterate v starts at e_start (so it is the final correction), and p
+    // and the local residual at the right-hand side.
     float v[16], rl[16], p[16], dg[16];
     float rr = 0.f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float4 r4 = *reinterpret_cast<const float4 *>(&s_p[4 * by + j + 1][COL0 + 4 * bx]);
-        const float rj[4] = {r4.x, r4.y, r4.z, r4.w};
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int lx = 4 * bx + i, ly = 4 * by + j, k = j * 4 + i;
             const int x = x0 + lx, y = y0 + ly;
-            float res = 0.f, d = 0.f;
-            if (lx < Tx && ly < Ty && s_m[ly + 1][lx + 1] == 0) {
+            float res = 0.f, d = 0.f, e0 = 0.f;
+            const bool inside = lx < Tx && ly < Ty;
+            if (MODE != 0 && inside) e0 = s_p[ly + 1][COL0 + lx];
+            if (inside && s_m[ly + 1][lx + 1] == 0) {
                 d = (float)deg_of(x, y, W, H);
-                res = rj[i];
+                res = rown[k];
                 if (MODE != 0) {
-                    const float sn = s_e[ly][COL0 + lx] + s_e[ly + 2][COL0 + lx] +
-                                     s_e[ly + 1][COL0 + lx - 1] + s_e[ly + 1][COL0 + lx + 1];
-                    res -= d * s_e[ly + 1][COL0 + lx] - sn;
+                    const float sn = s_p[ly][COL0 + lx] + s_p[ly + 2][COL0 + lx] +
+                                     s_p[ly + 1][COL0 + lx - 1] + s_p[ly + 1][COL0 + lx + 1];
+                    res -= d * e0 - sn;
                 }
             }
             dg[k] = d;
-            v[k] = 0.f;
+            v[k] = e0;
             rl[k] = res;
             p[k] = res;
             rr += res * res;
         }
+    __syncthreads();   // every lane has read the starting correction before the ring is cleared
+    if (MODE != 0) {
+        // zero ring (Dirichlet values outside the block): rows 0 and 33, and
+        // the two halo columns of rows 1..32
+        for (int k = lane; k < 2 * (TILE + 2) + 2 * TILE; k += 64) {
+            if (k < 2 * (TILE + 2))
+                s_p[k < TILE + 2 ? 0 : TILE + 1][COL0 - 1 + k % (TILE + 2)] = 0.f;
+            else
+                s_p[1 + (k - 2 * (TILE + 2)) / 2][(k & 1) ? COL0 + TILE : COL0 - 1] = 0.f;
+        }
     }
-    __syncthreads();   // every lane has read its right-hand side before p overwrites s_p
     rr = wave_sum(rr);
     // Local CG stops after `iters` steps or once the block residual has fallen
     // to the FP32 rounding floor (squared norm 1e-14 of the start); the
@@ -575,6 +603,8 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     const int xhi = tx == ntx - 1 ? W : (x0 + Tx + min((tx + 1) * sx, W - Tx)) / 2;
     const int ylo = ty == 0 ? 0 : (min((ty - 1) * sy, H - Ty) + Ty + y0) / 2;
     const int yhi = ty == nty - 1 ? H : (y0 + Ty + min((ty + 1) * sy, H - Ty)) / 2;
+    // v is the starting correction plus the local CG update; on known pixels
+    // it kept its start (0 in MODE 0/1, the data in MODE 2)
     float *eo = e_out + (size_t)c * N;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -582,11 +612,7 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
         for (int i = 0; i < 4; ++i) {
             const int lx = 4 * bx + i, ly = 4 * by + j;
             const int x = x0 + lx, y = y0 + ly;
-            if (lx < Tx && ly < Ty && x >= xlo && x < xhi && y >= ylo && y < yhi) {
-                float base = 0.f;
-                if (MODE != 0) base = s_e[ly + 1][COL0 + lx];
-                eo[y * W + x] = dg[j * 4 + i] > 0.f ? base + v[j * 4 + i] : (MODE == 2 ? base : 0.f);
-            }
+            if (lx < Tx && ly < Ty && x >= xlo && x < xhi && y >= ylo && y < yhi) eo[y * W + x] = v[j * 4 + i];
         }
 }
 
