@@ -330,6 +330,7 @@ __global__ void __launch_bounds__(64)
 k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int ni, const uint8_t *__restrict__ mask,
             const int *__restrict__ pos, const double *__restrict__ r, double *__restrict__ z) {
     __shared__ __attribute__((aligned(16))) float s_x[TT + 2][TLDS_W];
+    __shared__ __attribute__((aligned(16))) float s_t[TT][TT];   // t = B_i p between the two local solves
     const int ntiles = ntx * nty;
     const int t = t_xcd_remap(blockIdx.x, ntiles);
     const int c = blockIdx.y;
@@ -353,7 +354,9 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
             pk[j * 4 + i] = pos[yy * W + xx];
             mk[j * 4 + i] = mask[yy * W + xx];
         }
-    float dgU[16], isK[16], s[16];
+    // pixel class in one value: degree in the block graph on U (> 0), 0 on
+    // the mask, -1 outside the image (tiles narrower than 32)
+    float dgU[16], s[16];
     float ss = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -364,8 +367,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
             const bool act = lx < Tx && ly < Ty;
             const bool known = act && mk[k];
             const float d = (float)((lx > 0) + (lx < Tx - 1) + (ly > 0) + (ly < Ty - 1));
-            dgU[k] = (act && !known) ? d : 0.f;
-            isK[k] = known ? 1.f : 0.f;
+            dgU[k] = !act ? -1.f : (known ? 0.f : d);
             s[k] = known ? (float)r[(size_t)c * m + pk[k]] : 0.f;
             ss += s[k] * s[k];
         }
@@ -377,24 +379,35 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
     for (int k = 0; k < 16; ++k) { v[k] = 0.f; p[k] = s[k]; }
     const float floor_ss = ss * 1e-14f;
     for (int it = 0; it < nc && ss > floor_ss && ss >= FLT_MIN; ++it) {
-        float tvec[16], tmp[16], u[16];
+        float tmp[16], u[16];
         // t = B_i p: p on K, inpainted values on U
         T.nbsum(p, tmp);
 #pragma unroll
         for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tmp[k] : 0.f;
         local_cg(T, dgU, tmp, u, ni);
+        // t is parked in LDS (the lane's own 4x4) while the second solve runs
 #pragma unroll
-        for (int k = 0; k < 16; ++k) tvec[k] = isK[k] > 0.f ? p[k] : u[k];
+        for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] == 0.f ? p[k] : u[k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<float4 *>(&s_t[4 * by + j][4 * bx]) =
+                make_float4(tmp[j * 4 + 0], tmp[j * 4 + 1], tmp[j * 4 + 2], tmp[j * 4 + 3]);
         // q = B_i^T t = t_K + sum over unknown neighbours of (L_UU^{-1} t_U)
 #pragma unroll
-        for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tvec[k] : 0.f;
+        for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tmp[k] : 0.f;
         local_cg(T, dgU, tmp, u, ni);
         T.nbsum(u, tmp);
         float pq = 0.f;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            tmp[k] = isK[k] > 0.f ? tvec[k] + tmp[k] : 0.f;   // q
-            pq += p[k] * tmp[k];
+        for (int j = 0; j < 4; ++j) {
+            const float4 t4 = *reinterpret_cast<const float4 *>(&s_t[4 * by + j][4 * bx]);
+            const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = j * 4 + i;
+                tmp[k] = dgU[k] == 0.f ? tv[i] + tmp[k] : 0.f;   // q
+                pq += p[k] * tmp[k];
+            }
         }
         pq = t_wave_sum(pq);
         if (!(pq >= FLT_MIN)) break;
@@ -418,13 +431,16 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
     const int xhi = tx == ntx - 1 ? W : (x0 + Tx + min((tx + 1) * sx, W - Tx)) / 2;
     const int ylo = ty == 0 ? 0 : (min((ty - 1) * sy, H - Ty) + Ty + y0) / 2;
     const int yhi = ty == nty - 1 ? H : (y0 + Ty + min((ty + 1) * sy, H - Ty)) / 2;
+    // the compact positions are read again rather than kept live through the solve
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int k = j * 4 + i;
             const int x = x0 + 4 * bx + i, y = y0 + 4 * by + j;
-            if (isK[k] > 0.f && x >= xlo && x < xhi && y >= ylo && y < yhi) z[(size_t)c * m + pk[k]] = (double)v[k];
+            if (dgU[k] == 0.f && x >= xlo && x < xhi && y >= ylo && y < yhi)
+                z[(size_t)c * m + pos[y * W + x]] = (double)v[k];
         }
 }
 
