@@ -332,34 +332,62 @@ __global__ void k_zero_u32(int n, unsigned int *p) {
 // residual r - A e (the coarse operator is the same stencil on the coarse grid,
 // so summing four children scales the averaged residual by H^2/h^2 = 4).
 // Zero on coarse known pixels, where the coarse correction is pinned.
+// Branch-free: the thread loads the 4x4 fine neighbourhood of its 2x2 children
+// (corners excluded) from clamped addresses, all loads in flight at once, and
+// validity (inside the image, unknown child) enters through selects.
 __device__ __forceinline__ void restrict_residual_at(int i, int W, int H, int C, const uint8_t *__restrict__ m,
                                                      const float *__restrict__ r, const float *__restrict__ e, int Wc,
                                                      int Hc, const uint8_t *__restrict__ mc, float *__restrict__ rc) {
     if (i >= Wc * Hc) return;
     const int X = i % Wc, Y = i / Wc;
     const int N = W * H, Nc = Wc * Hc;
+    // fine columns 2X-1 .. 2X+2 and rows 2Y-1 .. 2Y+2: clamped index, inside flag
+    int xs[4], ys[4];
+    bool vx[4], vy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = 2 * X - 1 + k, y = 2 * Y - 1 + k;
+        vx[k] = x >= 0 && x < W;
+        vy[k] = y >= 0 && y < H;
+        xs[k] = min(max(x, 0), W - 1);
+        ys[k] = min(max(y, 0), H - 1);
+    }
+    bool unk[2][2];
+#pragma unroll
+    for (int jc = 0; jc < 2; ++jc)
+#pragma unroll
+        for (int qc = 0; qc < 2; ++qc)
+            unk[jc][qc] = vx[1 + qc] && vy[1 + jc] && m[ys[1 + jc] * W + xs[1 + qc]] == 0;
     const bool cknown = mc[i] != 0;
     for (int c = 0; c < C; ++c) {
+        const float *ecn = e + (size_t)c * N;
+        const float *rcn = r + (size_t)c * N;
+        float E[4][4], R[2][2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if ((a == 0 || a == 3) && (b == 0 || b == 3))
+                    E[a][b] = 0.f;   // corners: not a neighbour of any child
+                else
+                    E[a][b] = ecn[ys[a] * W + xs[b]];
+#pragma unroll
+        for (int jc = 0; jc < 2; ++jc)
+#pragma unroll
+            for (int qc = 0; qc < 2; ++qc) R[jc][qc] = rcn[ys[1 + jc] * W + xs[1 + qc]];
         float acc = 0.f;
-        if (!cknown) {
-            const float *ec = e + (size_t)c * N;
-            const float *rcn = r + (size_t)c * N;
-            for (int j = 0; j < 2; ++j)
-                for (int q = 0; q < 2; ++q) {
-                    const int x = 2 * X + q, y = 2 * Y + j;
-                    if (x >= W || y >= H) continue;
-                    const int p = y * W + x;
-                    if (m[p]) continue;
-                    float s = 0.f;
-                    int d = 0;
-                    if (x > 0) { s += ec[p - 1]; ++d; }
-                    if (x < W - 1) { s += ec[p + 1]; ++d; }
-                    if (y > 0) { s += ec[p - W]; ++d; }
-                    if (y < H - 1) { s += ec[p + W]; ++d; }
-                    acc += rcn[p] - ((float)d * ec[p] - s);
-                }
-        }
-        rc[(size_t)c * Nc + i] = acc;
+#pragma unroll
+        for (int jc = 0; jc < 2; ++jc)
+#pragma unroll
+            for (int qc = 0; qc < 2; ++qc) {
+                const int a = 1 + jc, b = 1 + qc;
+                const float s = (vx[b - 1] ? E[a][b - 1] : 0.f) + (vx[b + 1] ? E[a][b + 1] : 0.f) +
+                                (vy[a - 1] ? E[a - 1][b] : 0.f) + (vy[a + 1] ? E[a + 1][b] : 0.f);
+                const float d = (float)((int)vx[b - 1] + (int)vx[b + 1] + (int)vy[a - 1] + (int)vy[a + 1]);
+                const float res = R[jc][qc] - (d * E[a][b] - s);
+                acc += unk[jc][qc] ? res : 0.f;
+            }
+        rc[(size_t)c * Nc + i] = cknown ? 0.f : acc;
     }
 }
 
