@@ -160,6 +160,10 @@ static void fmg_init(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
 template <typename TD>
 int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, const TD *data, const double *src,
                      double *u, bool warm, const SolveCfg &cfg, hdi_solve_report *rep, hipStream_t s, Prof *prof) {
+    if ((data == nullptr) == (src == nullptr)) {
+        set_error("internal: a solve takes either data on the mask or a source off it");
+        return HDI_ERR_ARG;
+    }
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));

@@ -116,7 +116,10 @@ __device__ __forceinline__ double wave_from_right(double v) {  // value of lane 
     return __hiloint2double(hi, lo);
 }
 
-template <typename TD, int C>
+// SRC: the right-hand side off the mask is src (a source problem, data absent);
+// otherwise the problem has data on the mask and zero source. Each variant
+// keeps only the registers its right-hand side needs.
+template <typename TD, int C, bool SRC>
 __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__restrict__ mask,
                                                const double *__restrict__ u_in, const float *__restrict__ e,
                                                double *__restrict__ u_out, const TD *__restrict__ data,
@@ -143,15 +146,20 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
         ev = e ? e[j] : 0.f;
     };
     auto fetch_mask = [&](int y) -> int { return mask[(size_t)min(y, H - 1) * W + xs]; };
-    // right-hand side of row y (data on known pixels, src elsewhere), loaded
-    // without a per-pixel branch and selected at use, so no load of a later
-    // row has to complete before row y is computed
-    auto fetch_b = [&](int y, TD *dk, double *sv) {
+    // right-hand side of row y: data on known pixels only (the mask of row y
+    // is already in a register, loaded an iteration earlier, so waiting for
+    // it never waits for a later row's prefetch), or src elsewhere
+    auto fetch_b = [&](int y, int mk, TD *dk, double *sv) {
         const size_t i = (size_t)min(y, H - 1) * W + xs;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            dk[c] = data ? data[(size_t)c * N + i] : TD(0);
-            sv[c] = src ? src[(size_t)c * N + i] : 0.0;
+            if constexpr (SRC) {
+                dk[c] = TD(0);
+                sv[c] = src[(size_t)c * N + i];
+            } else {
+                dk[c] = mk ? data[(size_t)c * N + i] : TD(0);
+                sv[c] = 0.0;
+            }
         }
     };
     double pu[C], cu[C], nu[C], qu[C];
@@ -165,7 +173,7 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
         fetch(c, y0 + 1, nu[c], ne[c]);
     }
     int mcur = fetch_mask(y0), mnxt = fetch_mask(y0 + 1);
-    fetch_b(y0, dcur, scur);
+    fetch_b(y0, mcur, dcur, scur);
     double rr[C], bb[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) rr[c] = bb[c] = 0.0;
@@ -174,7 +182,7 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
 #pragma unroll
         for (int c = 0; c < C; ++c) fetch(c, y + 2, qu[c], qe[c]);
         const int mq = fetch_mask(y + 2);
-        fetch_b(y + 1, dnxt, snxt);
+        fetch_b(y + 1, mnxt, dnxt, snxt);
         // then compute row y from registers
         const size_t i = (size_t)y * W + xs;
         const bool known = mcur != 0;
@@ -220,13 +228,13 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
     }
 }
 
-template <typename TD, int C>
+template <typename TD, int C, bool SRC>
 __global__ void __launch_bounds__(RED_THREADS)
 k_residual(int W, int H, const uint8_t *__restrict__ mask, const double *__restrict__ u_in,
            const float *__restrict__ e, double *__restrict__ u_out, const TD *__restrict__ data,
            const double *__restrict__ src, float *__restrict__ r, double *__restrict__ partials, int nblk) {
-    residual_block<TD, C>(W, H, mask, u_in, e, u_out, data, src, r, partials, nblk, blockIdx.x, blockIdx.y,
-                          gridDim.x);
+    residual_block<TD, C, SRC>(W, H, mask, u_in, e, u_out, data, src, r, partials, nblk, blockIdx.x, blockIdx.y,
+                               gridDim.x);
 }
 
 // Second stage of the fixed-order reduction: one workgroup of 1024 threads per
@@ -743,12 +751,22 @@ void launch_residual(int W, int H, int C, const uint8_t *mask, const double *u_i
                      const TD *data, const double *src, float *r, double *partials, double *norms, hipStream_t s) {
     const dim3 g = residual_grid(W, H);
     const int nblk = g.x * g.y;
-    if (C == 3)
-        hipLaunchKernelGGL((k_residual<TD, 3>), g, dim3(RED_THREADS), 0, s, W, H, mask, u_in, e, u_out, data, src, r,
-                           partials, nblk);
-    else
-        hipLaunchKernelGGL((k_residual<TD, 1>), g, dim3(RED_THREADS), 0, s, W, H, mask, u_in, e, u_out, data, src, r,
-                           partials, nblk);
+    // a problem has either data on the mask or a source off it
+    if (src) {
+        if (C == 3)
+            hipLaunchKernelGGL((k_residual<TD, 3, true>), g, dim3(RED_THREADS), 0, s, W, H, mask, u_in, e, u_out,
+                               data, src, r, partials, nblk);
+        else
+            hipLaunchKernelGGL((k_residual<TD, 1, true>), g, dim3(RED_THREADS), 0, s, W, H, mask, u_in, e, u_out,
+                               data, src, r, partials, nblk);
+    } else {
+        if (C == 3)
+            hipLaunchKernelGGL((k_residual<TD, 3, false>), g, dim3(RED_THREADS), 0, s, W, H, mask, u_in, e, u_out,
+                               data, src, r, partials, nblk);
+        else
+            hipLaunchKernelGGL((k_residual<TD, 1, false>), g, dim3(RED_THREADS), 0, s, W, H, mask, u_in, e, u_out,
+                               data, src, r, partials, nblk);
+    }
     hipLaunchKernelGGL(k_reduce_partials, dim3(C), dim3(1024), 0, s, nblk, partials, norms);
 }
 
@@ -881,7 +899,7 @@ kb_residual(const int4 *__restrict__ seg, int nseg, const BImg *__restrict__ I, 
     // the last V-cycle's correction is the finest level's post-smoothing
     // output (or the single level's smoothing output)
     const float *e = use_e ? (im.nlev > 1 ? l0.eb : l0.ea) : nullptr;
-    residual_block<float, C>(im.W, im.H, im.mask, u_in, e, use_e ? u_out : nullptr, im.f, nullptr, l0.r,
+    residual_block<float, C, false>(im.W, im.H, im.mask, u_in, e, use_e ? u_out : nullptr, im.f, nullptr, l0.r,
                              im.partials, im.nblk, it.a, it.b, im.gx);
 }
 
