@@ -191,8 +191,9 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
     T_ST(X.norms(t.bK, bnorm));
 
     // initial residual r = B^T (f - B g); errors here are corrected by the
-    // final true-residual check
-    T_ST(X.normal_residual(false, std::max(tight, 1e-2 * tc.rel_tol), sse));
+    // final true-residual check (solving it tighter than rel_tol bought no
+    // iterations in measurements)
+    T_ST(X.normal_residual(false, std::max(tight, tc.rel_tol), sse));
     double mse0 = 0.0;
     for (int c = 0; c < C; ++c) mse0 += sse[c];
     mse0 /= (double)C * X.N;
@@ -211,8 +212,11 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
     int it = 0, restarts = 0, fallbacks = 0, tightenings = 0;
     // inexact-Krylov factor of the inner tolerances; tightened when the outer
     // residual stalls (the products' errors then limit what the recurrence
-    // can reach, which happens for sparse masks, where A^{-1} is large)
-    double fac = 1e-3, best = 1e300;
+    // can reach, which happens for sparse masks, where A^{-1} is large).
+    // Krylov products are relaxed as 3e-2 * rel_tol / ||r||_rel (a sweep over
+    // 1e-3 .. 1e-1 kept the iteration counts and the final true residuals);
+    // the stationary RAS residual evaluation keeps 1e-3.
+    double fac = tc.mode == HDI_TONAL_RAS ? 1e-3 : 3e-2, best = 1e300;
     int stall = 0;
     // stationary RAS step length: halved whenever the residual grows (with
     // 32x32 blocks on sparse masks the undamped iteration can diverge)
