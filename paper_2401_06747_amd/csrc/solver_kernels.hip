@@ -46,6 +46,23 @@ __device__ __forceinline__ float wave_sum(float v) {
     v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
+// Two sums over the wavefront at once (independent DPP chains, interleaved).
+__device__ __forceinline__ void wave_sum2(float &a, float &b) {
+    a += dpp_f<0xB1, 0xF>(a);
+    b += dpp_f<0xB1, 0xF>(b);
+    a += dpp_f<0x4E, 0xF>(a);
+    b += dpp_f<0x4E, 0xF>(b);
+    a += dpp_f<0x114, 0xF>(a);
+    b += dpp_f<0x114, 0xF>(b);
+    a += dpp_f<0x118, 0xF>(a);
+    b += dpp_f<0x118, 0xF>(b);
+    a += dpp_f<0x142, 0xA>(a);
+    b += dpp_f<0x142, 0xA>(b);
+    a += dpp_f<0x143, 0xC>(a);
+    b += dpp_f<0x143, 0xC>(b);
+    a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 63));
+    b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 63));
+}
 __device__ __forceinline__ double wave_sum_d(double v) {
     v += dpp_d<0xB1, 0xF>(v);
     v += dpp_d<0x4E, 0xF>(v);
@@ -541,10 +558,9 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     __syncthreads();
 
     // Local right-hand side r - A e_start on the block's unknown pixels; the
-    // CG iterate v starts at e_start (so it is the final correction), and p
-    // and the local residual at the right-hand side.
-    float v[16], rl[16], p[16], dg[16];
-    float rr = 0.f;
+    // CG iterate v starts at e_start (so it is the final correction), and the
+    // local residual at the right-hand side.
+    float v[16], rl[16], dg[16];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -566,8 +582,6 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
             dg[k] = d;
             v[k] = e0;
             rl[k] = res;
-            p[k] = res;
-            rr += res * res;
         }
     __syncthreads();   // every lane has read the starting correction before the ring is cleared
     if (MODE != 0) {
@@ -580,17 +594,23 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
                 s_p[1 + (k - 2 * (TILE + 2)) / 2][(k & 1) ? COL0 + TILE : COL0 - 1] = 0.f;
         }
     }
-    rr = wave_sum(rr);
-    // Local CG stops after `iters` steps or once the block residual has fallen
-    // to the FP32 rounding floor (squared norm 1e-14 of the start); the
-    // reciprocal below also needs a normal (not denormal) divisor.
-    const float rr_floor = rr * 1e-14f;
 
-    for (int it = 0; it < iters && rr > rr_floor && rr >= FLT_MIN; ++it) {
-        // publish p
+    // Local CG in the Chronopoulos-Gear arrangement: each step applies the
+    // block operator to the residual and takes both inner products, (r, r) and
+    // (A r, r), in one merged wavefront reduction; the directions follow from
+    // the recurrences p = r + beta p, s = A r + beta s (s = A p). It stops after
+    // `iters` steps or once the block residual has fallen to the FP32 rounding
+    // floor (squared norm 1e-14 of the start); the reciprocals also need normal
+    // (not denormal) divisors.
+    float p[16], sv[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) p[k] = sv[k] = 0.f;
+    float gamma_prev = 1.f, alpha_prev = 1.f, rr_floor = 0.f;
+    for (int it = 0; it < iters; ++it) {
+        // publish r
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            float4 w4 = make_float4(p[j * 4 + 0], p[j * 4 + 1], p[j * 4 + 2], p[j * 4 + 3]);
+            float4 w4 = make_float4(rl[j * 4 + 0], rl[j * 4 + 1], rl[j * 4 + 2], rl[j * 4 + 3]);
             *reinterpret_cast<float4 *>(&s_p[4 * by + j + 1][COL0 + 4 * bx]) = w4;
         }
         __syncthreads();
@@ -604,33 +624,35 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
         }
         const float upv[4] = {up.x, up.y, up.z, up.w};
         const float dnv[4] = {dn.x, dn.y, dn.z, dn.w};
-        float q[16];
-        float pq = 0.f;
+        float w[16];
+        float gamma = 0.f, delta = 0.f;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int k = j * 4 + i;
-                const float n = (j > 0 ? p[k - 4] : upv[i]) + (j < 3 ? p[k + 4] : dnv[i]) +
-                                (i > 0 ? p[k - 1] : lf[j]) + (i < 3 ? p[k + 1] : rt[j]);
-                q[k] = dg[k] > 0.f ? dg[k] * p[k] - n : 0.f;
-                pq += p[k] * q[k];
+                const float n = (j > 0 ? rl[k - 4] : upv[i]) + (j < 3 ? rl[k + 4] : dnv[i]) +
+                                (i > 0 ? rl[k - 1] : lf[j]) + (i < 3 ? rl[k + 1] : rt[j]);
+                w[k] = dg[k] > 0.f ? dg[k] * rl[k] - n : 0.f;
+                gamma += rl[k] * rl[k];
+                delta += w[k] * rl[k];
             }
-        pq = wave_sum(pq);
-        if (!(pq >= FLT_MIN)) break;
-        const float alpha = rr * __builtin_amdgcn_rcpf(pq);
-        float rr2 = 0.f;
+        wave_sum2(gamma, delta);
+        if (it == 0) rr_floor = gamma * 1e-14f;
+        if (!(gamma > rr_floor && gamma >= FLT_MIN)) break;
+        const float beta = it == 0 ? 0.f : gamma * __builtin_amdgcn_rcpf(gamma_prev);
+        const float denom = delta - beta * gamma * __builtin_amdgcn_rcpf(alpha_prev);
+        if (!(denom >= FLT_MIN)) break;
+        const float alpha = gamma * __builtin_amdgcn_rcpf(denom);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
+            p[k] = rl[k] + beta * p[k];
+            sv[k] = w[k] + beta * sv[k];
             v[k] += alpha * p[k];
-            rl[k] -= alpha * q[k];
-            rr2 += rl[k] * rl[k];
+            rl[k] -= alpha * sv[k];
         }
-        rr2 = wave_sum(rr2);
-        const float beta = rr2 * __builtin_amdgcn_rcpf(rr);
-        rr = rr2;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) p[k] = rl[k] + beta * p[k];
+        gamma_prev = gamma;
+        alpha_prev = alpha;
         __syncthreads();
     }
 
