@@ -115,3 +115,22 @@ def test_autotune_picks_a_converging_candidate_and_caches(tmp_path):
     # a second tuner reads the cache instead of measuring again
     again = autotune.Autotuner(str(path)).params_for(ft, mt)
     assert (again.overlap, again.local_iters, again.coarse_iters) == (p.overlap, p.local_iters, p.coarse_iters)
+
+
+def test_full_uneven_batch_equals_plain_solves():
+    """The benchmark's 64-image batch at full size (512..2048 x 512..1152, gray and
+    RGB, 1-10% masks): every image bit-for-bit equal to its plain solve, and the
+    smallest one against the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    specs = synth.config4_specs(64)
+    with ThreadPoolExecutor(8) as ex:
+        insts = list(ex.map(lambda a: synth.config4_item(*a), enumerate(specs)))
+    fs = [torch.tensor(i.f, dtype=torch.float32, device=DEV) for i in insts]
+    ms = [torch.tensor(i.mask, device=DEV) for i in insts]
+    us, reps = hdi.solve_batch(fs, ms)
+    assert all(r["status"] == 0 for r in reps)
+    for f, m, u in zip(fs, ms, us):
+        assert torch.equal(u, hdi.inpaint_solve(f, m)[0])
+    k = min(range(64), key=lambda i: insts[i].f.size)
+    err = oi.rel_l2(us[k].cpu().numpy(), oi.inpaint(insts[k].f, insts[k].mask))
+    assert err.max() <= 1e-5, err

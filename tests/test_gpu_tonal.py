@@ -68,6 +68,44 @@ def test_rgb_textured_ragged_blocks():
     print("rgb", err, nres, rep)
 
 
+def test_rgb_270x480_many_blocks():
+    """Several hundred RAS blocks per channel with ragged last rows and columns."""
+    inst = synth.config2(270, 480, 3, 0.03, item=24)
+    g, rep, u = _run(inst.f, inst.mask, rel_tol=1e-7)
+    err, nres = _check(inst.f, inst.mask, g, rep, u, tol=1e-7)
+    print("270x480 rgb", err, nres, rep)
+
+
+def test_sparse_mask_parity():
+    """A 1.4% mask, where the restricted preconditioner can give directions
+    nearly orthogonal to the residual (the descent safeguard takes over)."""
+    f = synth.textured_image(270, 480, 1, 5, 25)
+    m = synth.gradient_mask(f, 0.014)
+    g, rep, u = _run(f, m, rel_tol=1e-7)
+    err, nres = _check(f, m, g, rep, u, tol=1e-7)
+    print("sparse", err, nres, rep)
+
+
+def test_4k_rgb_full_size_properties():
+    """The benchmark's workload and parameters at full size. The oracle cannot
+    solve the 4K normal equations in test time, so it checks what holds at any
+    size: u = B g satisfies the inpainting system for the returned g to the
+    tight tolerance of the final check (FP64 residual by the oracle), u equals g
+    on the mask, the reported MSE is the MSE of u, and it fell."""
+    inst = synth.config2()
+    g, rep, u = _run(inst.f, inst.mask)
+    assert rep["status"] == 0 and rep["rel_normal_residual"] <= 1e-6, rep
+    K = inst.mask != 0
+    assert np.isfinite(g).all() and np.all(g[:, ~K] == 0)
+    rr = oi.relres(u, g, inst.mask)
+    assert rr.max() <= 1e-9, rr
+    assert np.array_equal(u[:, K], g[:, K])
+    mse = float(((u - inst.f) ** 2).mean())
+    assert abs(mse - rep["mse_final"]) <= 1e-9 * mse, (mse, rep)
+    assert rep["mse_final"] < rep["mse_initial"]
+    print("4k tonal", rr, rep)
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 40), (1, 33, 1), (1, 5, 7), (3, 31, 40)])
 def test_small_shapes(shape):
     C, H, W = shape
