@@ -86,6 +86,15 @@ def test_sparse_mask_parity():
     print("sparse", err, nres, rep)
 
 
+@pytest.mark.parametrize("mode", [hdi.RAS, hdi.CGNR])
+def test_other_modes_on_a_sparse_mask(mode):
+    """Stationary RAS (Alg. 2) and CGNR also reach the optimum on a 1.4% mask."""
+    f = synth.textured_image(270, 480, 1, 5, 25)
+    m = synth.gradient_mask(f, 0.014)
+    g, rep, u = _run(f, m, mode=mode, rel_tol=1e-7, max_outer=400)
+    _check(f, m, g, rep, u, tol=1e-7)
+
+
 def test_4k_rgb_full_size_properties():
     """The benchmark's workload and parameters at full size. The oracle cannot
     solve the 4K normal equations in test time, so it checks what holds at any
