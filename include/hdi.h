@@ -276,7 +276,9 @@ size_t hdi_densify_workspace_bytes(int32_t width, int32_t height);
  * cell; cells rank by (sum of round(e * 2^20) descending, key ascending); the
  * chosen pixel maximises e, ties to the smaller index.
  *   mask     H x W uint8, in/out (device); at least one pixel set
- *   err      H x W float32 error map, e >= 0 (device)
+ *   err      H x W float32 error map (device): 0 <= e <= 2^43 / (W H), so that
+ *            the fixed-point cell sums stay exact; anything else (negative,
+ *            NaN, Inf, too large) is HDI_ERR_ARG before the mask is touched
  *   n_add    pixels to add (>= 0)
  *   added    nullable int32 output (device), capacity n_add: the added
  *            linear indices in ascending order

@@ -20,6 +20,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cmath>
 #include <climits>
 
 #include "hdi_internal.h"
@@ -279,6 +280,15 @@ __global__ void k_copy_i32(int n, const int *__restrict__ a, int *__restrict__ b
 
 // ------------------------------------------------------------------ host
 
+// flag[0] = 1 if an error value is negative, not finite or above emax (the
+// bound that keeps the 2^-20 fixed-point cell sums exact in 64 bits)
+__global__ void k_check_err(int N, const float *__restrict__ err, float emax, int *__restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float e = err[i];
+    if (!(e >= 0.f && e <= emax)) flag[0] = 1;
+}
+
 struct DensWs {
     int *colnear, *seg_first, *seg_last, *labels, *owner;
     int *seed_idx, *seed_pos, *chunk_cnt, *chunk_off, *total;
@@ -362,12 +372,20 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
     const int nseg = (H + SEG - 1) / SEG;
     // seeds in ascending order (the Voronoi cell order) and their ranks
     launch_compact(N, mask, d.chunk_cnt, d.chunk_off, d.total, d.seed_idx, d.seed_pos, s);
-    int m = 0;
-    D_TRY(hipMemcpyAsync(&m, d.total, sizeof(int), hipMemcpyDeviceToHost, s));
+    const float emax = (float)std::min(std::ldexp(1.0, 43) / N, 3.0e38);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, 1, 0, d.total + 1);
+    hipLaunchKernelGGL(k_check_err, gd(N), dim3(256), 0, s, N, err, emax, d.total + 1);
+    int mb[2] = {0, 0};
+    D_TRY(hipMemcpyAsync(mb, d.total, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     D_TRY(hipStreamSynchronize(s));
+    const int m = mb[0];
     if (m == 0) {
         set_error("empty mask: densification needs at least one mask pixel");
         return HDI_ERR_EMPTY_MASK;
+    }
+    if (mb[1]) {
+        set_error("error map holds a value that is negative, not finite or above %g", (double)emax);
+        return HDI_ERR_ARG;
     }
     // 1 labels
     hipLaunchKernelGGL(k_col_seg, gd((long)W * nseg), dim3(256), 0, s, W, H, nseg, mask, d.colnear, d.seg_first,

@@ -91,6 +91,15 @@ def test_errors():
     m[2, 2] = 1
     with pytest.raises(hdi.HdiError):
         hdi.densify_step(m, e, 3, partition=7)
+    # invalid error values are rejected before the mask changes
+    for bad in (-1.0, float("nan"), float("inf")):
+        e2 = e.clone()
+        e2[5, 5] = bad
+        before = m.clone()
+        with pytest.raises(hdi.HdiError) as ei:
+            hdi.densify_step(m, e2, 3)
+        assert ei.value.status == 1
+        assert torch.equal(m, before)
 
 
 def test_error_map_rgb_bit_exact():
