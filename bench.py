@@ -236,7 +236,7 @@ def batch_bench(torch, hdi, synth, dev, n_images=64, reps=3):
     return res
 
 
-def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=200, seed=5):
+def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=500, seed=5, tonal_workers=3):
     """Serving stream: Poisson arrivals of inpaint and tonal requests over sizes
     {256^2, 1024x768, 1920x1080, 3840x2160}, gray or RGB, 1-8% masks, at 0.8x
     and 1.5x the plain path's capacity; latency from submission to result."""
@@ -280,7 +280,7 @@ def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=200, seed=5):
     def run(load, plain):
         lam = load * mu_plain
         arrive = np.cumsum(gaps) / lam
-        srv = hdi.Server(32 << 30, max_slots=32, tonal_workers=2, plain=plain, device=dev)
+        srv = hdi.Server(32 << 30, max_slots=32, tonal_workers=tonal_workers, plain=plain, device=dev)
         try:
             tickets = []
             t0 = time.perf_counter()
@@ -303,7 +303,7 @@ def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=200, seed=5):
 
     res = {"workload": f"{n_requests} Poisson arrivals, inpaint/tonal 50/50, sizes 256^2..3840x2160, gray/RGB, "
                        f"1-8% FS-gradient masks (one image per size and channel count)",
-           "mu_plain_per_s": round(mu_plain, 2)}
+           "mu_plain_per_s": round(mu_plain, 2), "tonal_workers": tonal_workers}
     for load in (0.8, 1.5):
         res[f"load_{load}"] = {"lambda_per_s": round(load * mu_plain, 2), "served": run(load, False),
                                "plain": run(load, True)}
@@ -321,7 +321,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-densify", action="store_true", help="skip the densification-loop measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "

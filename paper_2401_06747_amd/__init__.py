@@ -212,7 +212,7 @@ class Server:
     bytes of a caller-owned arena. `plain=True` runs one request at a time
     through inpaint_solve / tonal_optimize (the control)."""
 
-    def __init__(self, arena_bytes: int, max_slots: int = 64, tonal_workers: int = 2, plain: bool = False,
+    def __init__(self, arena_bytes: int, max_slots: int = 64, tonal_workers: int = 3, plain: bool = False,
                  device="cuda:0"):
         L = _lib.lib()
         self.device = torch.device(device)
