@@ -67,11 +67,15 @@ typedef struct {
  *   coarse_iters CG iterations on the coarsest level, which is a single block
  *                (Sec. 3.3; default 64)
  *   flags        HDI_FLAG_* bits
+ *   small_from   first level smoothed with 16x16 blocks (half the overlap):
+ *                0 automatic (from level 1, the first level with fewer than
+ *                4096 blocks of 32x32 over all channels, where the smoother is
+ *                bound by the latency of its steps), -1 none, k >= 1 level k
  * Each refinement round applies one V-cycle with one pre- and one
  * post-smoothing step (Sec. 3.3).                                            */
 typedef struct {
     double rel_tol;
-    int32_t max_outer, overlap, local_iters, coarse_iters, flags;
+    int32_t max_outer, overlap, local_iters, coarse_iters, flags, small_from;
 } hdi_solve_params;
 
 #define HDI_FLAG_NO_FMG 1   /* cold start from u = C f instead of the reduced

@@ -30,10 +30,11 @@ class SolveParams:
     local_iters: int = 0       # 0 -> 8
     coarse_iters: int = 0      # 0 -> 64
     flags: int = 0
+    small_from: int = 0        # first level with 16x16 blocks: 0 automatic, -1 none, k level k
 
     def c(self):
         return _lib.hdi_solve_params(self.rel_tol, self.max_outer, self.overlap, self.local_iters,
-                                     self.coarse_iters, self.flags)
+                                     self.coarse_iters, self.flags, self.small_from)
 
 
 @dataclass

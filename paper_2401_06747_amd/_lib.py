@@ -15,7 +15,8 @@ class hdi_image(ctypes.Structure):
 
 class hdi_solve_params(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("overlap", ctypes.c_int32),
-                ("local_iters", ctypes.c_int32), ("coarse_iters", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("local_iters", ctypes.c_int32), ("coarse_iters", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("small_from", ctypes.c_int32)]
 
 
 class hdi_solve_report(ctypes.Structure):

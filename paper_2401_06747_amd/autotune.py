@@ -22,11 +22,12 @@ from ._lib import check
 OVERLAPS = (2, 4, 6)
 LOCAL_ITERS = (4, 6, 8, 12)
 COARSE_ITERS = (32, 64)
+SMALL_FROM = (0, -1)          # 16x16 blocks on the coarse levels: automatic rule, or none
 
 
 def candidates():
-    return [SolveParams(overlap=o, local_iters=k, coarse_iters=c)
-            for o in OVERLAPS for k in LOCAL_ITERS for c in COARSE_ITERS]
+    return [SolveParams(overlap=o, local_iters=k, coarse_iters=c, small_from=t)
+            for o in OVERLAPS for k in LOCAL_ITERS for c in COARSE_ITERS for t in SMALL_FROM]
 
 
 def bucket(shape, density: float) -> str:
@@ -69,5 +70,6 @@ class Autotuner:
                             ctypes.byref(best), ctypes.byref(ms), _stream_ptr(f.device))
         check(st)
         p = cands[best.value]
-        return {"params": {"overlap": p.overlap, "local_iters": p.local_iters, "coarse_iters": p.coarse_iters},
+        return {"params": {"overlap": p.overlap, "local_iters": p.local_iters, "coarse_iters": p.coarse_iters,
+                           "small_from": p.small_from},
                 "ms": float(ms.value)}

@@ -29,9 +29,9 @@ namespace hdi {
     } while (0)
 
 static constexpr int POINTS = 1 << 30;          // segment unit of point (256-pixel chunk) phases
-static constexpr int ADMIT_PHASES = 5 * MAX_LEVELS + 2;
+static constexpr int ADMIT_PHASES = 7 * MAX_LEVELS + 2;   // smoothing phases split by block size
 static constexpr int RES_PHASES = 3;
-static constexpr int VC_PHASES = 4 * MAX_LEVELS;
+static constexpr int VC_PHASES = 7 * MAX_LEVELS;
 
 __global__ void kb_zero_counts(int n, unsigned int *c) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,24 +222,32 @@ int32_t Engine::admit(const std::vector<EJob *> &news, std::vector<EJob *> &ende
     auto tiles = [](const Level &L) { return (long)L.bx.count * L.by.count; };
     BPhase init_u = seg_admit_.begin(d_seg_admit_);
     for (EJob *j : go) seg_admit_.add(init_u, j->slot, 0, chunks(j->h.lev[0]), POINTS);
-    std::vector<BPhase> drestrict(maxL), fmg_coarse(maxL), fmg_prolong(maxL), fmg_smooth(maxL);
+    // smoothing phases come in one launch per block size (index 0: 32x32, 1: 16x16)
+    auto ti = [](const Level &L) { return L.tile == TILE_SMALL ? 1 : 0; };
+    std::vector<BPhase> drestrict(maxL), fmg_prolong(maxL), fmg_coarse(2 * maxL), fmg_smooth(2 * maxL);
     for (int l = 0; l + 1 < maxL; ++l) {   // data restriction l -> l+1
         drestrict[l] = seg_admit_.begin(d_seg_admit_);
         for (EJob *j : go)
             if (fmg(j) && l + 1 < j->h.nlev) seg_admit_.add(drestrict[l], j->slot, l, chunks(j->h.lev[l + 1]), POINTS);
     }
     for (int l = 1; l < maxL; ++l) {
-        fmg_coarse[l] = seg_admit_.begin(d_seg_admit_);
-        for (EJob *j : go)
-            if (fmg(j) && j->h.nlev > 1 && l == j->h.nlev - 1)
-                seg_admit_.add(fmg_coarse[l], j->slot, l, tiles(j->h.lev[l]) * j->h.C, (int)tiles(j->h.lev[l]));
+        for (int tv = 0; tv < 2; ++tv) {
+            fmg_coarse[2 * l + tv] = seg_admit_.begin(d_seg_admit_);
+            for (EJob *j : go)
+                if (fmg(j) && j->h.nlev > 1 && l == j->h.nlev - 1 && ti(j->h.lev[l]) == tv)
+                    seg_admit_.add(fmg_coarse[2 * l + tv], j->slot, l, tiles(j->h.lev[l]) * j->h.C,
+                                   (int)tiles(j->h.lev[l]));
+        }
         fmg_prolong[l] = seg_admit_.begin(d_seg_admit_);
         for (EJob *j : go)
             if (fmg(j) && l < j->h.nlev - 1) seg_admit_.add(fmg_prolong[l], j->slot, l, chunks(j->h.lev[l]), POINTS);
-        fmg_smooth[l] = seg_admit_.begin(d_seg_admit_);
-        for (EJob *j : go)
-            if (fmg(j) && l < j->h.nlev - 1)
-                seg_admit_.add(fmg_smooth[l], j->slot, l, tiles(j->h.lev[l]) * j->h.C, (int)tiles(j->h.lev[l]));
+        for (int tv = 0; tv < 2; ++tv) {
+            fmg_smooth[2 * l + tv] = seg_admit_.begin(d_seg_admit_);
+            for (EJob *j : go)
+                if (fmg(j) && l < j->h.nlev - 1 && ti(j->h.lev[l]) == tv)
+                    seg_admit_.add(fmg_smooth[2 * l + tv], j->slot, l, tiles(j->h.lev[l]) * j->h.C,
+                                   (int)tiles(j->h.lev[l]));
+        }
     }
     BPhase prolong0 = seg_admit_.begin(d_seg_admit_);
     for (EJob *j : go)
@@ -252,10 +260,11 @@ int32_t Engine::admit(const std::vector<EJob *> &news, std::vector<EJob *> &ende
                          hipMemcpyHostToDevice, s));
     launch_b_init_u(init_u, d_img_, s);
     for (int l = 0; l + 1 < maxL; ++l) launch_b_data_restrict(l == 0, drestrict[l], d_lev_, d_img_, s);
+    const int tile_of[2] = {TILE, TILE_SMALL};
     for (int l = maxL - 1; l >= 1; --l) {
-        launch_b_schwarz(2, true, fmg_coarse[l], d_lev_, d_img_, s);
+        for (int tv = 0; tv < 2; ++tv) launch_b_schwarz(2, true, tile_of[tv], fmg_coarse[2 * l + tv], d_lev_, d_img_, s);
         launch_b_fmg_prolong(fmg_prolong[l], d_lev_, d_img_, s);
-        launch_b_schwarz(2, false, fmg_smooth[l], d_lev_, d_img_, s);
+        for (int tv = 0; tv < 2; ++tv) launch_b_schwarz(2, false, tile_of[tv], fmg_smooth[2 * l + tv], d_lev_, d_img_, s);
     }
     launch_b_fmg_prolong0(prolong0, d_lev_, d_img_, s);
     B_TRY(hipGetLastError());
@@ -336,34 +345,42 @@ int32_t Engine::round(std::vector<EJob *> &ended, hipStream_t s) {
     int maxL = 0;
     for (EJob *j : go) maxL = std::max(maxL, j->h.nlev);
     seg_vc_.v.clear();
-    std::vector<BPhase> pre(maxL), coarsest(maxL), restr(maxL), post(maxL);
+    // smoothing phases come in one launch per block size (index 0: 32x32, 1: 16x16)
+    std::vector<BPhase> pre(2 * maxL), coarsest(2 * maxL), restr(maxL), post(2 * maxL);
     for (int l = 0; l < maxL; ++l) {
-        auto tiles = [&](BPhase &ph, bool above_coarsest) {
+        auto tiles = [&](BPhase &ph, bool above_coarsest, int tile) {
             for (EJob *j : go)
-                if (above_coarsest ? l < j->h.nlev - 1 : l == j->h.nlev - 1) {
+                if ((above_coarsest ? l < j->h.nlev - 1 : l == j->h.nlev - 1) && j->h.lev[l].tile == tile) {
                     const Level &L = j->h.lev[l];
                     const long nt = (long)L.bx.count * L.by.count;
                     seg_vc_.add(ph, j->slot, l, nt * j->h.C, (int)nt);
                 }
         };
-        pre[l] = seg_vc_.begin(d_seg_vc_);
-        tiles(pre[l], true);
-        coarsest[l] = seg_vc_.begin(d_seg_vc_);
-        tiles(coarsest[l], false);
+        for (int tv = 0; tv < 2; ++tv) {
+            const int tile = tv ? TILE_SMALL : TILE;
+            pre[2 * l + tv] = seg_vc_.begin(d_seg_vc_);
+            tiles(pre[2 * l + tv], true, tile);
+            coarsest[2 * l + tv] = seg_vc_.begin(d_seg_vc_);
+            tiles(coarsest[2 * l + tv], false, tile);
+            post[2 * l + tv] = seg_vc_.begin(d_seg_vc_);
+            tiles(post[2 * l + tv], true, tile);
+        }
         restr[l] = seg_vc_.begin(d_seg_vc_);
         for (EJob *j : go)
             if (l < j->h.nlev - 1)
                 seg_vc_.add(restr[l], j->slot, l, ((long)j->h.lev[l + 1].W * j->h.lev[l + 1].H + 255) / 256, POINTS);
-        post[l] = seg_vc_.begin(d_seg_vc_);
-        tiles(post[l], true);
     }
     B_TRY(hipMemcpyAsync(d_seg_vc_, seg_vc_.v.data(), sizeof(int4) * seg_vc_.v.size(), hipMemcpyHostToDevice, s));
+    const int tile_of[2] = {TILE, TILE_SMALL};
     for (int l = 0; l < maxL; ++l) {
-        launch_b_schwarz(0, false, pre[l], d_lev_, d_img_, s);
-        launch_b_schwarz(0, true, coarsest[l], d_lev_, d_img_, s);
+        for (int tv = 0; tv < 2; ++tv) {
+            launch_b_schwarz(0, false, tile_of[tv], pre[2 * l + tv], d_lev_, d_img_, s);
+            launch_b_schwarz(0, true, tile_of[tv], coarsest[2 * l + tv], d_lev_, d_img_, s);
+        }
         launch_b_restrict(restr[l], d_lev_, d_img_, s);
     }
-    for (int l = maxL - 2; l >= 0; --l) launch_b_schwarz(1, false, post[l], d_lev_, d_img_, s);
+    for (int l = maxL - 2; l >= 0; --l)
+        for (int tv = 0; tv < 2; ++tv) launch_b_schwarz(1, false, tile_of[tv], post[2 * l + tv], d_lev_, d_img_, s);
     B_TRY(hipGetLastError());
     for (EJob *j : go) j->rounds += 1;
     return HDI_OK;
@@ -374,7 +391,8 @@ int32_t Engine::round(std::vector<EJob *> &ended, hipStream_t s) {
 static bool plan_batch(Engine &e, std::vector<EJob> &jobs, Arena &a) {
     if (!e.plan(a, (int)jobs.size())) return false;
     for (EJob &j : jobs)
-        if (!plan_hierarchy(j.h, a, j.job.img.width, j.job.img.height, j.job.img.channels, j.overlap, j.job.mask))
+        if (!plan_hierarchy(j.h, a, j.job.img.width, j.job.img.height, j.job.img.channels, j.overlap, j.job.mask,
+                            j.cfg.small_from))
             return false;
     return true;
 }

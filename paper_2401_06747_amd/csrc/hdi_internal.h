@@ -9,34 +9,36 @@
 
 namespace hdi {
 
-constexpr int TILE = 32;          // Schwarz block edge (Sec. 3.3 uses 32x32)
+constexpr int TILE = 32;          // Schwarz block edge of the fine levels (Sec. 3.3 uses 32x32)
+constexpr int TILE_SMALL = 16;    // block edge of the small-tile smoother
 constexpr int MAX_LEVELS = 16;
 constexpr int RED_THREADS = 256;  // threads of the reduction kernels
 
 void set_error(const char *fmt, ...);
 
-// Geometry of the overlapping 32x32 blocks along one dimension (Sec. 3.1, 3.3).
+// Geometry of the overlapping tile x tile blocks along one dimension (Sec. 3.1, 3.3).
 struct Blocks1D {
     int n;       // pixels along the dimension
     int count;   // number of blocks
-    int stride;  // start of block i is min(i*stride, n-32)
+    int stride;  // start of block i is min(i*stride, n-tile)
 };
 
-inline Blocks1D make_blocks(int n, int overlap) {
+inline Blocks1D make_blocks(int n, int overlap, int tile = TILE) {
     Blocks1D b;
     b.n = n;
-    if (n <= TILE) {
+    if (n <= tile) {
         b.count = 1;
-        b.stride = TILE;
+        b.stride = tile;
     } else {
-        b.stride = TILE - overlap;
-        b.count = (n - TILE + b.stride - 1) / b.stride + 1;
+        b.stride = tile - overlap;
+        b.count = (n - tile + b.stride - 1) / b.stride + 1;
     }
     return b;
 }
 
 struct Level {
     int W, H;
+    int tile;        // block edge of this level's smoother (32 or 16)
     Blocks1D bx, by;
     uint8_t *mask;   // level mask (level 0: the caller's mask)
     float *r;        // right-hand side of the correction equation, C x H x W
@@ -71,11 +73,17 @@ struct Hierarchy {
 };
 
 // Lay out the hierarchy in the arena (base == nullptr: size query only).
-bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask0);
+// small_from: the first level smoothed with 16x16 blocks, which use half the
+// overlap (even, at least 2); 0 picks it from the block counts, -1 keeps
+// 32x32 blocks on every level
+bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask0,
+                    int small_from = -1);
+inline int small_overlap(int overlap) { return overlap / 2 >= 2 ? (overlap / 2) & ~1 : 2; }
 
 struct SolveCfg {
     double rel_tol;
     int max_outer, local_iters, coarse_iters, vcycles, flags;
+    int small_from;  // hdi_solve_params::small_from (0 automatic, -1 none)
     int64_t known;   // number of known pixels (for the byte accounting)
 };
 
@@ -146,8 +154,10 @@ void launch_b_count(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t 
 void launch_b_init_u(const BPhase &ph, const BImg *I, hipStream_t s);
 void launch_b_residual(const BPhase &ph, int C, const BImg *I, const uint8_t *flags, const BLev *L, hipStream_t s);
 void launch_b_reduce(const BPhase &ph, const BImg *I, hipStream_t s);
-// mode 0 pre-smoothing (coarsest: uses coarse_iters), 1 post, 2 FMG (coarsest: e_in = aux)
-void launch_b_schwarz(int mode, bool coarsest, const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
+// mode 0 pre-smoothing (coarsest: uses coarse_iters), 1 post, 2 FMG (coarsest: e_in = aux);
+// tile: the block edge of the level in every segment of the launch
+void launch_b_schwarz(int mode, bool coarsest, int tile, const BPhase &ph, const BLev *L, const BImg *I,
+                      hipStream_t s);
 void launch_b_restrict(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
 void launch_b_data_restrict(bool from_f, const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
 void launch_b_fmg_prolong(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);

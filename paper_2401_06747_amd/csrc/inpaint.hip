@@ -82,7 +82,8 @@ void set_error(const char *fmt, ...) {
         }                                                                                      \
     } while (0)
 
-bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask0) {
+bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask0,
+                    int small_from) {
     h.C = C;
     int l = 0;
     int w = W, hh = H;
@@ -90,8 +91,17 @@ bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, co
         Level &L = h.lev[l];
         L.W = w;
         L.H = hh;
-        L.bx = make_blocks(w, overlap);
-        L.by = make_blocks(hh, overlap);
+        if (small_from == 0 && l >= 1) {
+            // automatic: switch once a level has too few 32x32 blocks to keep
+            // the chip busy (about 4 waves per SIMD), and stay switched
+            const long nb = (long)make_blocks(w, overlap).count * make_blocks(hh, overlap).count * C;
+            if (nb < 4096) small_from = l;
+        }
+        const bool small = small_from > 0 && l >= small_from;
+        L.tile = small ? TILE_SMALL : TILE;
+        const int ov = small ? small_overlap(overlap) : overlap;
+        L.bx = make_blocks(w, ov, L.tile);
+        L.by = make_blocks(hh, ov, L.tile);
         const size_t n = (size_t)w * hh;
         L.mask = l == 0 ? const_cast<uint8_t *>(mask0) : (uint8_t *)a.take(n);
         L.r = (float *)a.take(n * C * sizeof(float));
@@ -125,7 +135,7 @@ static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Pr
     }
     Level &Lc = h.lev[l + 1];
     const double N = (double)L.W * L.H, Nc = (double)Lc.W * Lc.H;
-    const double blk_px = (double)L.bx.count * L.by.count * std::min(TILE, L.W) * std::min(TILE, L.H) * C;
+    const double blk_px = (double)L.bx.count * L.by.count * std::min(L.tile, L.W) * std::min(L.tile, L.H) * C;
     const double cg_flops = 15.0 * blk_px * cfg.local_iters;
     if (prof) prof->begin(1, N * (1 + 8.0 * C), s, cg_flops);
     launch_smooth_pre(L, C, cfg.local_iters, L.ea, s);
@@ -261,13 +271,16 @@ int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap) {
     cfg.coarse_iters = (p && p->coarse_iters > 0) ? p->coarse_iters : 64;
     cfg.vcycles = 1;
     cfg.flags = p ? p->flags : 0;
+    cfg.small_from = p ? p->small_from : 0;
     overlap = (p && p->overlap > 0) ? p->overlap : 4;
     if (overlap < 2 || overlap > 16 || (overlap & 1)) {
         set_error("overlap %d outside 2..16 or odd", overlap);
         return HDI_ERR_ARG;
     }
-    if (!(cfg.rel_tol < 1.0) || cfg.local_iters > 256 || cfg.coarse_iters > 4096 || cfg.max_outer > 100000) {
-        set_error("parameter out of range (rel_tol < 1, local_iters <= 256, coarse_iters <= 4096)");
+    if (!(cfg.rel_tol < 1.0) || cfg.local_iters > 256 || cfg.coarse_iters > 4096 || cfg.max_outer > 100000 ||
+        cfg.small_from < -1 || cfg.small_from >= MAX_LEVELS) {
+        set_error("parameter out of range (rel_tol < 1, local_iters <= 256, coarse_iters <= 4096, "
+                  "small_from -1..%d)", MAX_LEVELS - 1);
         return HDI_ERR_ARG;
     }
     return HDI_OK;
@@ -335,7 +348,7 @@ int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double
     hipStream_t s = (hipStream_t)stream;
     Arena a{(char *)ws, ws_bytes, 0};
     Hierarchy h;
-    plan_hierarchy(h, a, img.width, img.height, img.channels, overlap, mask);
+    plan_hierarchy(h, a, img.width, img.height, img.channels, overlap, mask, cfg.small_from);
     st = prepare_mask(h, s);
     if (st) return st;
     const int C = img.channels;

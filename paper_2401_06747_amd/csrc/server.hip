@@ -293,7 +293,8 @@ struct hdi_server {
                 j.job = hdi_job{t->req.img, t->mask, t->f, t->out};
                 j.user = t;
                 Arena a{t->ws, t->ws_bytes, 0};
-                plan_hierarchy(j.h, a, t->req.img.width, t->req.img.height, t->req.img.channels, j.overlap, t->mask);
+                plan_hierarchy(j.h, a, t->req.img.width, t->req.img.height, t->req.img.channels, j.overlap, t->mask,
+                               j.cfg.small_from);
                 news.push_back(&j);
             }
             int32_t st = eng.admit(news, ended, compute);

@@ -435,77 +435,108 @@ __device__ __forceinline__ float prolong_at(const float *__restrict__ ec, int Wc
 
 // ------------------------------------------------------------------ Schwarz block smoother
 
-// One restricted additive Schwarz step (Sec. 3.1) on 32x32 blocks: each block
-// solves its local problem A_i v_i = R_i r^n with zero Dirichlet values outside
-// the block (interior block boundaries) and the reflecting condition at the
-// image border, by `iters` steps of conjugate gradients (Sec. 3.3). The
-// correction is written back only on the pixels the block owns (the middle of
-// each overlap splits ownership), which is a partition of unity with 0/1
-// weights (eq. partition-of-unity-discrete).
+// One restricted additive Schwarz step (Sec. 3.1) on T x T blocks (T = 32 or
+// 16): each block solves its local problem A_i v_i = R_i r^n with zero
+// Dirichlet values outside the block (interior block boundaries) and the
+// reflecting condition at the image border, by `iters` steps of conjugate
+// gradients (Sec. 3.3). The correction is written back only on the pixels the
+// block owns (the middle of each overlap splits ownership), which is a
+// partition of unity with 0/1 weights (eq. partition-of-unity-discrete).
 //
 // Layout: one wavefront (64 lanes) per block; lane (bx, by) = (lane & 7,
-// lane >> 3) holds the 4x4 pixels (4bx + i, 4by + j) in registers. The search
-// direction is exchanged through LDS (a 34 x 40 float tile with a zero halo),
-// dot products use wavefront shuffles, so the block needs no barrier beyond
-// its own wave.
+// lane >> 3) holds the PS x PS pixels (PS bx + i, PS by + j), PS = T / 8, in
+// registers. The current vector is exchanged through LDS (a (T+2)-row float
+// tile with a zero halo ring), dot products use wavefront shuffles, so the
+// block needs no barrier beyond its own wave. Small tiles give four times as
+// many waves with a quarter of the work each, which pays on the coarse levels
+// of the V-cycle, where there are few blocks and the latency of each step
+// dominates.
 //
 // MODE 0: pre-smoothing from e = 0 (reads r only)
 // MODE 1: post-smoothing of e_in + P ec (reads e_in with a 1-pixel halo and
 //         the coarse correction ec around the block)
 // MODE 2: FMG smoothing from the prolongated guess e_in (like MODE 1 with ec = 0)
-constexpr int LDS_W = 40;   // row pitch of the LDS tiles (floats), 16-byte aligned rows
-constexpr int COL0 = 4;     // LDS column of block column 0 (col 3 and 36 are the halo)
+constexpr int COL0 = 4;     // LDS column of block column 0 (columns 3 and T + 4 are the halo)
 
-template <int MODE>
+template <int T> struct TileGeom {
+    static constexpr int PS = T / 8;          // pixels per lane and dimension
+    static constexpr int NPX = PS * PS;       // pixels per lane
+    static constexpr int LW = T + 8;          // LDS row pitch (floats; rows stay 16-byte aligned)
+    static constexpr int NC = T / 2 + 4;      // coarse correction staged around the block
+};
+
+// PS consecutive floats of one LDS row, as one vector access
+template <int PS>
+__device__ __forceinline__ void lds_put(float *dst, const float *v) {
+    if constexpr (PS == 4)
+        *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+    else
+        *reinterpret_cast<float2 *>(dst) = make_float2(v[0], v[1]);
+}
+template <int PS>
+__device__ __forceinline__ void lds_get(const float *src, float *v) {
+    if constexpr (PS == 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(src);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else {
+        const float2 a = *reinterpret_cast<const float2 *>(src);
+        v[0] = a.x; v[1] = a.y;
+    }
+}
+
+template <int MODE, int T>
 __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, int sx, int sy, int iters,
                                               const uint8_t *__restrict__ mask, const float *__restrict__ r,
                                               const float *__restrict__ e_in, const float *__restrict__ ec, int Wc,
                                               int Hc, float *__restrict__ e_out, const int t, const int c) {
-    // s_p: the search direction with a zero ring during CG; before that it
+    using G = TileGeom<T>;
+    constexpr int PS = G::PS, NPX = G::NPX, LW = G::LW, NC = G::NC;
+    // s_p: the vector of the current CG step with a zero ring; before that it
     // holds the starting correction with its 1-pixel halo (MODE 1/2)
-    __shared__ __attribute__((aligned(16))) float s_p[TILE + 2][LDS_W];
-    __shared__ uint8_t s_m[TILE + 2][TILE + 2];
-    __shared__ float s_c[MODE == 1 ? 20 : 1][20];   // coarse correction around the block (MODE 1)
+    __shared__ __attribute__((aligned(16))) float s_p[T + 2][LW];
+    __shared__ uint8_t s_m[T + 2][T + 2];
+    __shared__ float s_c[MODE == 1 ? NC : 1][NC];   // coarse correction around the block (MODE 1)
 
     const int tx = t % ntx, ty = t / ntx;
-    const int Tx = min(TILE, W), Ty = min(TILE, H);
+    const int Tx = min(T, W), Ty = min(T, H);
     const int x0 = min(tx * sx, W - Tx), y0 = min(ty * sy, H - Ty);
     const int N = W * H;
     const float *rc = r + (size_t)c * N;
     const int lane = threadIdx.x;
     const int bx = lane & 7, by = lane >> 3;
 
-    // The lane's own 4x4 right-hand side goes straight to registers (8 lanes
-    // cover a 32-pixel row); addresses are clamped so every load is unconditional.
-    float rown[16];
+    // The lane's own right-hand side goes straight to registers (8 lanes
+    // cover a block row); addresses are clamped so every load is unconditional.
+    float rown[NPX];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < PS; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int xc = min(x0 + 4 * bx + i, W - 1), yc = min(y0 + 4 * by + j, H - 1);
-            rown[j * 4 + i] = r ? rc[yc * W + xc] : 0.f;
+        for (int i = 0; i < PS; ++i) {
+            const int xc = min(x0 + PS * bx + i, W - 1), yc = min(y0 + PS * by + j, H - 1);
+            rown[j * PS + i] = r ? rc[yc * W + xc] : 0.f;
         }
     // MODE 1: the coarse correction around the block, with clamped coordinates
     // so that the clamped bilinear lookup becomes plain indexing; its loads are
     // in flight together with the first staging batch.
     const int X0 = ((x0 - 1) >> 1) - 1, Y0 = ((y0 - 1) >> 1) - 1;
-    constexpr int NCV = (400 + 63) / 64;
+    constexpr int NCS = NC * NC;
+    constexpr int NCV = (NCS + 63) / 64;
     float cv[MODE == 1 ? NCV : 1];
     if (MODE == 1) {
         const float *ecc = ec + (size_t)c * Wc * Hc;
 #pragma unroll
         for (int h = 0; h < NCV; ++h) {
-            const int k = min(lane + 64 * h, 399);
-            const int X = min(max(X0 + k % 20, 0), Wc - 1), Y = min(max(Y0 + k / 20, 0), Hc - 1);
+            const int k = min(lane + 64 * h, NCS - 1);
+            const int X = min(max(X0 + k % NC, 0), Wc - 1), Y = min(max(Y0 + k / NC, 0), Hc - 1);
             cv[h] = ecc[Y * Wc + X];
         }
     }
     // Stage mask and (MODE 1/2) the starting correction for the block and a
-    // 1-pixel halo, in coalesced rows of 34. s_m: 0 unknown, 1 known, 2 outside
-    // the image. In MODE 1, e_in is exactly 0 on known pixels; in MODE 2 it
-    // holds the data there. MODE 0 starts from zero.
-    constexpr int NST = (TILE + 2) * (TILE + 2);
-    constexpr int NIT = (NST + 63) / 64;     // 19 rounds of 64 lanes
+    // 1-pixel halo, in coalesced rows of T + 2. s_m: 0 unknown, 1 known, 2
+    // outside the image. In MODE 1, e_in is exactly 0 on known pixels; in
+    // MODE 2 it holds the data there. MODE 0 starts from zero.
+    constexpr int NST = (T + 2) * (T + 2);
+    constexpr int NIT = (NST + 63) / 64;
     constexpr int HALF = (NIT + 1) / 2;      // staged in two batches to bound register use
 #pragma unroll
     for (int batch = 0; batch < 2; ++batch) {
@@ -514,7 +545,7 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
 #pragma unroll
         for (int h = 0; h < HALF; ++h) {
             const int k = lane + 64 * (batch * HALF + h);
-            const int ly = k / (TILE + 2), lx = k % (TILE + 2);
+            const int ly = k / (T + 2), lx = k % (T + 2);
             const int xc = min(max(x0 + lx - 1, 0), W - 1), yc = min(max(y0 + ly - 1, 0), H - 1);
             const int pc = yc * W + xc;
             mraw[h] = mask[pc];
@@ -524,7 +555,7 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
 #pragma unroll
             for (int h = 0; h < NCV; ++h) {
                 const int k = lane + 64 * h;
-                if (k < 400) s_c[k / 20][k % 20] = cv[h];
+                if (k < NCS) s_c[k / NC][k % NC] = cv[h];
             }
             __syncthreads();
         }
@@ -532,7 +563,7 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
         for (int h = 0; h < HALF; ++h) {
             const int k = lane + 64 * (batch * HALF + h);
             if (k < NST) {
-                const int ly = k / (TILE + 2), lx = k % (TILE + 2);
+                const int ly = k / (T + 2), lx = k % (T + 2);
                 const int x = x0 + lx - 1, y = y0 + ly - 1;
                 const bool in = x >= 0 && x < W && y >= 0 && y < H;
                 const int mk = in ? (mraw[h] != 0) : 2;
@@ -560,12 +591,12 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     // Local right-hand side r - A e_start on the block's unknown pixels; the
     // CG iterate v starts at e_start (so it is the final correction), and the
     // local residual at the right-hand side.
-    float v[16], rl[16], dg[16];
+    float v[NPX], rl[NPX], dg[NPX];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < PS; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int lx = 4 * bx + i, ly = 4 * by + j, k = j * 4 + i;
+        for (int i = 0; i < PS; ++i) {
+            const int lx = PS * bx + i, ly = PS * by + j, k = j * PS + i;
             const int x = x0 + lx, y = y0 + ly;
             float res = 0.f, d = 0.f, e0 = 0.f;
             const bool inside = lx < Tx && ly < Ty;
@@ -585,13 +616,13 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
         }
     __syncthreads();   // every lane has read the starting correction before the ring is cleared
     if (MODE != 0) {
-        // zero ring (Dirichlet values outside the block): rows 0 and 33, and
-        // the two halo columns of rows 1..32
-        for (int k = lane; k < 2 * (TILE + 2) + 2 * TILE; k += 64) {
-            if (k < 2 * (TILE + 2))
-                s_p[k < TILE + 2 ? 0 : TILE + 1][COL0 - 1 + k % (TILE + 2)] = 0.f;
+        // zero ring (Dirichlet values outside the block): rows 0 and T + 1, and
+        // the two halo columns of rows 1..T
+        for (int k = lane; k < 2 * (T + 2) + 2 * T; k += 64) {
+            if (k < 2 * (T + 2))
+                s_p[k < T + 2 ? 0 : T + 1][COL0 - 1 + k % (T + 2)] = 0.f;
             else
-                s_p[1 + (k - 2 * (TILE + 2)) / 2][(k & 1) ? COL0 + TILE : COL0 - 1] = 0.f;
+                s_p[1 + (k - 2 * (T + 2)) / 2][(k & 1) ? COL0 + T : COL0 - 1] = 0.f;
         }
     }
 
@@ -602,37 +633,32 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     // `iters` steps or once the block residual has fallen to the FP32 rounding
     // floor (squared norm 1e-14 of the start); the reciprocals also need normal
     // (not denormal) divisors.
-    float p[16], sv[16];
+    float p[NPX], sv[NPX];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) p[k] = sv[k] = 0.f;
+    for (int k = 0; k < NPX; ++k) p[k] = sv[k] = 0.f;
     float gamma_prev = 1.f, alpha_prev = 1.f, rr_floor = 0.f;
     for (int it = 0; it < iters; ++it) {
         // publish r
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float4 w4 = make_float4(rl[j * 4 + 0], rl[j * 4 + 1], rl[j * 4 + 2], rl[j * 4 + 3]);
-            *reinterpret_cast<float4 *>(&s_p[4 * by + j + 1][COL0 + 4 * bx]) = w4;
-        }
+        for (int j = 0; j < PS; ++j) lds_put<PS>(&s_p[PS * by + j + 1][COL0 + PS * bx], &rl[j * PS]);
         __syncthreads();
-        const float4 up = *reinterpret_cast<const float4 *>(&s_p[4 * by][COL0 + 4 * bx]);
-        const float4 dn = *reinterpret_cast<const float4 *>(&s_p[4 * by + 5][COL0 + 4 * bx]);
-        float lf[4], rt[4];
+        float upv[PS], dnv[PS], lf[PS], rt[PS];
+        lds_get<PS>(&s_p[PS * by][COL0 + PS * bx], upv);
+        lds_get<PS>(&s_p[PS * by + PS + 1][COL0 + PS * bx], dnv);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            lf[j] = s_p[4 * by + j + 1][COL0 + 4 * bx - 1];
-            rt[j] = s_p[4 * by + j + 1][COL0 + 4 * bx + 4];
+        for (int j = 0; j < PS; ++j) {
+            lf[j] = s_p[PS * by + j + 1][COL0 + PS * bx - 1];
+            rt[j] = s_p[PS * by + j + 1][COL0 + PS * bx + PS];
         }
-        const float upv[4] = {up.x, up.y, up.z, up.w};
-        const float dnv[4] = {dn.x, dn.y, dn.z, dn.w};
-        float w[16];
+        float w[NPX];
         float gamma = 0.f, delta = 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < PS; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = j * 4 + i;
-                const float n = (j > 0 ? rl[k - 4] : upv[i]) + (j < 3 ? rl[k + 4] : dnv[i]) +
-                                (i > 0 ? rl[k - 1] : lf[j]) + (i < 3 ? rl[k + 1] : rt[j]);
+            for (int i = 0; i < PS; ++i) {
+                const int k = j * PS + i;
+                const float n = (j > 0 ? rl[k - PS] : upv[i]) + (j < PS - 1 ? rl[k + PS] : dnv[i]) +
+                                (i > 0 ? rl[k - 1] : lf[j]) + (i < PS - 1 ? rl[k + 1] : rt[j]);
                 w[k] = dg[k] > 0.f ? dg[k] * rl[k] - n : 0.f;
                 gamma += rl[k] * rl[k];
                 delta += w[k] * rl[k];
@@ -645,7 +671,7 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
         if (!(denom >= FLT_MIN)) break;
         const float alpha = gamma * __builtin_amdgcn_rcpf(denom);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < NPX; ++k) {
             p[k] = rl[k] + beta * p[k];
             sv[k] = w[k] + beta * sv[k];
             v[k] += alpha * p[k];
@@ -665,22 +691,22 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     // it kept its start (0 in MODE 0/1, the data in MODE 2)
     float *eo = e_out + (size_t)c * N;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < PS; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int lx = 4 * bx + i, ly = 4 * by + j;
+        for (int i = 0; i < PS; ++i) {
+            const int lx = PS * bx + i, ly = PS * by + j;
             const int x = x0 + lx, y = y0 + ly;
-            if (lx < Tx && ly < Ty && x >= xlo && x < xhi && y >= ylo && y < yhi) eo[y * W + x] = v[j * 4 + i];
+            if (lx < Tx && ly < Ty && x >= xlo && x < xhi && y >= ylo && y < yhi) eo[y * W + x] = v[j * PS + i];
         }
 }
 
-template <int MODE>
+template <int MODE, int T>
 __global__ void __launch_bounds__(64)
 k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
           const uint8_t *__restrict__ mask, const float *__restrict__ r, const float *__restrict__ e_in,
           const float *__restrict__ ec, int Wc, int Hc, float *__restrict__ e_out) {
-    schwarz_block<MODE>(W, H, ntx, nty, sx, sy, iters, mask, r, e_in, ec, Wc, Hc, e_out,
-                        xcd_remap(blockIdx.x, ntx * nty), blockIdx.y);
+    schwarz_block<MODE, T>(W, H, ntx, nty, sx, sy, iters, mask, r, e_in, ec, Wc, Hc, e_out,
+                           xcd_remap(blockIdx.x, ntx * nty), blockIdx.y);
 }
 
 // ------------------------------------------------------------------ reduced FMG (Sec. 3.2)
@@ -796,24 +822,30 @@ void launch_update(int W, int H, int C, const uint8_t *mask, const float *e, dou
     hipLaunchKernelGGL(k_update, grid1((long)W * H, 256), dim3(256), 0, s, W * H, C, mask, e, u);
 }
 
+template <int MODE>
+static void launch_schwarz(const Level &L, int C, int iters, const float *r, const float *e_in, const float *ec,
+                           int Wc, int Hc, float *e_out, hipStream_t s) {
+    const dim3 g(L.bx.count * L.by.count, C);
+    if (L.tile == 16)
+        hipLaunchKernelGGL((k_schwarz<MODE, 16>), g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count,
+                           L.bx.stride, L.by.stride, iters, L.mask, r, e_in, ec, Wc, Hc, e_out);
+    else
+        hipLaunchKernelGGL((k_schwarz<MODE, 32>), g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count,
+                           L.bx.stride, L.by.stride, iters, L.mask, r, e_in, ec, Wc, Hc, e_out);
+}
+
 void launch_smooth_pre(const Level &L, int C, int iters, float *e_out, hipStream_t s) {
-    dim3 g(L.bx.count * L.by.count, C);
-    hipLaunchKernelGGL(k_schwarz<0>, g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count, L.bx.stride,
-                       L.by.stride, iters, L.mask, L.r, (const float *)nullptr, (const float *)nullptr, 1, 1, e_out);
+    launch_schwarz<0>(L, C, iters, L.r, nullptr, nullptr, 1, 1, e_out, s);
 }
 
 void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, const float *e_in, const float *ec,
                         float *e_out, hipStream_t s) {
-    dim3 g(L.bx.count * L.by.count, C);
-    hipLaunchKernelGGL(k_schwarz<1>, g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count, L.bx.stride,
-                       L.by.stride, iters, L.mask, L.r, e_in, ec, Lc.W, Lc.H, e_out);
+    launch_schwarz<1>(L, C, iters, L.r, e_in, ec, Lc.W, Lc.H, e_out, s);
 }
 
 void launch_smooth_fmg(const Level &L, int C, int iters, const float *e_in, float *e_out, hipStream_t s) {
-    dim3 g(L.bx.count * L.by.count, C);
     // the full problem A u = C d has a zero right-hand side on unknown pixels
-    hipLaunchKernelGGL(k_schwarz<2>, g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count, L.bx.stride,
-                       L.by.stride, iters, L.mask, (const float *)nullptr, e_in, (const float *)nullptr, 1, 1, e_out);
+    launch_schwarz<2>(L, C, iters, nullptr, e_in, nullptr, 1, 1, e_out, s);
 }
 
 void launch_restrict_residual(const Level &L, const Level &Lc, int C, const float *e, hipStream_t s) {
@@ -932,7 +964,7 @@ kb_reduce(const int4 *__restrict__ seg, int nseg, const BImg *__restrict__ I) {
     reduce_partials_block(im.nblk, im.partials, im.norms, it.a);
 }
 
-template <int MODE, bool COARSEST>
+template <int MODE, bool COARSEST, int T>
 __global__ void __launch_bounds__(64)
 kb_schwarz(const int4 *__restrict__ seg, int nseg, int n, const BLev *__restrict__ L, const BImg *__restrict__ I) {
     const SegItem it = seg_item(seg, nseg, xcd_remap(blockIdx.x, n));
@@ -940,14 +972,14 @@ kb_schwarz(const int4 *__restrict__ seg, int nseg, int n, const BLev *__restrict
     const BLev &l = L[it.img * MAX_LEVELS + it.lev];
     const int iters = COARSEST ? im.coarse_iters : im.local_iters;
     if (MODE == 0)
-        schwarz_block<0>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, nullptr, nullptr, 1, 1, l.ea, it.a,
-                         it.b);
+        schwarz_block<0, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, nullptr, nullptr, 1, 1, l.ea,
+                            it.a, it.b);
     else if (MODE == 1)
-        schwarz_block<1>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, l.ea, l.ec, l.Wc, l.Hc, l.eb, it.a,
-                         it.b);
+        schwarz_block<1, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, l.ea, l.ec, l.Wc, l.Hc, l.eb,
+                            it.a, it.b);
     else
-        schwarz_block<2>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, nullptr, COARSEST ? l.aux : l.eb,
-                         nullptr, 1, 1, l.ea, it.a, it.b);
+        schwarz_block<2, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, nullptr, COARSEST ? l.aux : l.eb,
+                            nullptr, 1, 1, l.ea, it.a, it.b);
 }
 
 __global__ void kb_restrict(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L,
@@ -1004,14 +1036,23 @@ void launch_b_residual(const BPhase &ph, int C, const BImg *I, const uint8_t *fl
 void launch_b_reduce(const BPhase &ph, const BImg *I, hipStream_t s) {
     if (ph.n) hipLaunchKernelGGL(kb_reduce, dim3(ph.n), dim3(1024), 0, s, SEG_ARGS(ph), I);
 }
-void launch_b_schwarz(int mode, bool coarsest, const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s) {
-    if (!ph.n) return;
+template <int T>
+static void launch_b_schwarz_t(int mode, bool coarsest, const BPhase &ph, const BLev *L, const BImg *I,
+                               hipStream_t s) {
     const dim3 g(ph.n), b(64);
-    if (mode == 0 && !coarsest) hipLaunchKernelGGL((kb_schwarz<0, false>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
-    if (mode == 0 && coarsest) hipLaunchKernelGGL((kb_schwarz<0, true>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
-    if (mode == 1) hipLaunchKernelGGL((kb_schwarz<1, false>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
-    if (mode == 2 && !coarsest) hipLaunchKernelGGL((kb_schwarz<2, false>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
-    if (mode == 2 && coarsest) hipLaunchKernelGGL((kb_schwarz<2, true>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 0 && !coarsest) hipLaunchKernelGGL((kb_schwarz<0, false, T>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 0 && coarsest) hipLaunchKernelGGL((kb_schwarz<0, true, T>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 1) hipLaunchKernelGGL((kb_schwarz<1, false, T>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 2 && !coarsest) hipLaunchKernelGGL((kb_schwarz<2, false, T>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+    if (mode == 2 && coarsest) hipLaunchKernelGGL((kb_schwarz<2, true, T>), g, b, 0, s, SEG_ARGS(ph), ph.n, L, I);
+}
+void launch_b_schwarz(int mode, bool coarsest, int tile, const BPhase &ph, const BLev *L, const BImg *I,
+                      hipStream_t s) {
+    if (!ph.n) return;
+    if (tile == 16)
+        launch_b_schwarz_t<16>(mode, coarsest, ph, L, I, s);
+    else
+        launch_b_schwarz_t<32>(mode, coarsest, ph, L, I, s);
 }
 void launch_b_restrict(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s) {
     if (ph.n) hipLaunchKernelGGL(kb_restrict, dim3(ph.n), dim3(256), 0, s, SEG_ARGS(ph), L, I);

@@ -62,8 +62,9 @@ struct TonalWs {
     double *partials, *sums;                      // reductions
 };
 
-static bool plan_tonal(TonalWs &t, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask) {
-    if (!plan_hierarchy(t.h, a, W, H, C, overlap, mask)) return false;
+static bool plan_tonal(TonalWs &t, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask,
+                       int small_from = -1) {
+    if (!plan_hierarchy(t.h, a, W, H, C, overlap, mask, small_from)) return false;
     const size_t N = (size_t)W * H;
     const int nch = (int)((N + 1023) / 1024);
     t.pos = (int *)a.take(N * sizeof(int));
@@ -444,7 +445,7 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
     T_TRY(hipEventRecord(e0, s));
     Arena a{(char *)ws, ws_bytes, 0};
     TonalWs t;
-    plan_tonal(t, a, img.width, img.height, img.channels, ov_inner, mask);
+    plan_tonal(t, a, img.width, img.height, img.channels, ov_inner, mask, inner.small_from);
     st = prepare_mask(t.h, s);
     if (st) return st;
     const int N = img.width * img.height, C = img.channels;

@@ -6,9 +6,10 @@ from paper_2401_06747_amd import autotune
 
 def test_candidates_are_valid_parameter_sets():
     c = autotune.candidates()
-    assert len(c) == len(autotune.OVERLAPS) * len(autotune.LOCAL_ITERS) * len(autotune.COARSE_ITERS)
+    assert len(c) == (len(autotune.OVERLAPS) * len(autotune.LOCAL_ITERS) * len(autotune.COARSE_ITERS)
+                      * len(autotune.SMALL_FROM))
     assert all(p.overlap % 2 == 0 and 2 <= p.overlap <= 16 for p in c)
-    assert len({(p.overlap, p.local_iters, p.coarse_iters) for p in c}) == len(c)
+    assert len({(p.overlap, p.local_iters, p.coarse_iters, p.small_from) for p in c}) == len(c)
 
 
 def test_bucket_groups_similar_images():

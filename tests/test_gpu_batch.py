@@ -91,7 +91,7 @@ def test_empty_mask_in_batch_is_an_error():
 def test_batch_with_per_job_overlaps():
     items = _batch_items(4, seed=2)
     fs, ms = _t(items)
-    params = [hdi.SolveParams(overlap=o) for o in (2, 4, 6, 16)]
+    params = [hdi.SolveParams(overlap=o, small_from=t) for o, t in ((2, 1), (4, -1), (6, 2), (16, 0))]
     us, reps = hdi.solve_batch(fs, ms, params=params)
     for f, m, u, p, rep in zip(fs, ms, us, params, reps):
         assert rep["status"] == 0
@@ -107,14 +107,15 @@ def test_autotune_picks_a_converging_candidate_and_caches(tmp_path):
     path = tmp_path / "tune.json"
     tuner = autotune.Autotuner(str(path), reps=1)
     p = tuner.params_for(ft, mt)
-    assert (p.overlap, p.local_iters, p.coarse_iters) in {(c.overlap, c.local_iters, c.coarse_iters)
-                                                          for c in autotune.candidates()}
+    assert (p.overlap, p.local_iters, p.coarse_iters, p.small_from) in {
+        (c.overlap, c.local_iters, c.coarse_iters, c.small_from) for c in autotune.candidates()}
     u, rep = hdi.inpaint_solve(ft, mt, params=p)
     assert rep["status"] == 0
     assert oi.relres(u.cpu().numpy(), f, m).max() <= 1e-6 * 1.0001
     # a second tuner reads the cache instead of measuring again
     again = autotune.Autotuner(str(path)).params_for(ft, mt)
-    assert (again.overlap, again.local_iters, again.coarse_iters) == (p.overlap, p.local_iters, p.coarse_iters)
+    assert (again.overlap, again.local_iters, again.coarse_iters, again.small_from) == (
+        p.overlap, p.local_iters, p.coarse_iters, p.small_from)
 
 
 def test_full_uneven_batch_equals_plain_solves():

@@ -88,7 +88,10 @@ def test_single_pixel_and_full_mask():
     m[7, 50] = 1
     u, rep = _run(f, m)
     assert rep["status"] == 0
-    np.testing.assert_allclose(u[0], np.float32(f[0, 7, 50]), rtol=2e-6)
+    # one mask pixel: u is the constant f_k; the solve stops at relative residual
+    # 1e-6, and this system is the worst-conditioned case, so the solution bar
+    # (relative error 1e-5) applies rather than a tighter one
+    np.testing.assert_allclose(u[0], np.float32(f[0, 7, 50]), rtol=1e-5)
     u, rep = _run(f, np.ones((40, 70), np.uint8))
     assert rep["status"] == 0 and np.array_equal(u[0], f[0])
 
@@ -149,3 +152,17 @@ def test_poisoned_workspace_gives_identical_results():
     u1, r1 = hdi.inpaint_solve(ft, mt, ws=ws1)
     assert r0["status"] == 0 and r1["status"] == 0
     assert torch.equal(u0, u1)
+
+
+@pytest.mark.parametrize("small_from", [1, 2])
+@pytest.mark.parametrize("shape", [(3, 270, 480), (1, 45, 300), (1, 333, 37), (3, 97, 130)])
+def test_small_tile_coarse_levels(shape, small_from):
+    """16x16 blocks (2x2 pixels per lane) from a given level on, with ragged and
+    narrow coarse levels (below 16 pixels in one dimension)."""
+    C, H, W = shape
+    inst = synth.config2(H, W, C, 0.04, item=30 + small_from)
+    u, rep = _run(inst.f, inst.mask, small_from=small_from)
+    assert rep["status"] == 0, rep
+    ref = oi.inpaint(inst.f, inst.mask)
+    assert oi.rel_l2(u, ref).max() <= 1e-5
+    assert oi.relres(u, inst.f, inst.mask).max() <= 1e-6 * 1.0001
