@@ -9,4 +9,6 @@ Everything is float64 and follows the paper's definitions directly:
   tonal.py    -- tonal optimisation (Sec. 5, eqs. tonal-opt-minimisation and
                  tonal-normal-equations)
   densify.py  -- one Delaunay/Voronoi densification step (Sec. 4.1, Alg. 1)
+  spatial.py  -- the Laplacian-dithered initial mask and the densification
+                 loop around it (Sec. 4.2, Alg. 1)
 """
