@@ -291,6 +291,57 @@ int32_t densify_step(int32_t width, int32_t height, uint8_t *mask, const float *
                      int32_t partition, int32_t *added, int64_t *n_added, void *ws, size_t ws_bytes,
                      void *stream);
 
+/* ------------------------------------------------------------------ spatial optimisation */
+
+/* Initial mask by random dithering of the Laplacian magnitude (Sec. 4.2): one
+ * coin flip per pixel with a probability proportional to
+ * l = sum_c |Delta f_c| (5-point stencil, reflecting boundary, FP64). Pixel p
+ * joins iff rand_p < alpha l_p, alpha = n0 / (S 2^-16) with S the exact 64-bit
+ * sum of round(l 2^16), so the expected size is n0 (a constant image uses
+ * n0 / N). Deterministic for given uniforms.
+ *   f      C x H x W float32 (device); rand H x W float64 uniforms in [0, 1)
+ *   mask   H x W uint8 output (device); count: host output, its size
+ *   ws     device workspace of hdi_initial_mask_workspace_bytes(img) bytes   */
+size_t hdi_initial_mask_workspace_bytes(hdi_image img);
+int32_t hdi_initial_mask(hdi_image img, const float *f, const double *rand, int64_t n0, uint8_t *mask,
+                         int64_t *count, void *ws, size_t ws_bytes, void *stream);
+
+typedef struct {
+    double density;          /* final mask density d: floor(d W H) pixels, 0 < d <= 1 */
+    double t;                /* factor of the added counts from step to step (1: equal steps) */
+    int64_t n0;              /* expected initial size (0: round(floor(d W H) / (n_steps + 1))) */
+    int32_t n_steps;         /* densification steps (Alg. 1; the paper's experiments use 20) */
+    int32_t partition;       /* HDI_PART_DELAUNAY or HDI_PART_VORONOI */
+    hdi_solve_params solve;  /* parameters of every inpainting solve */
+} hdi_spatial_params;
+
+typedef struct {
+    int64_t initial_count, final_count;
+    int32_t solve_rounds;      /* refinement rounds over all solves */
+    double rel_residual[3];    /* of the final solve */
+    float ms;                  /* device time of the whole optimisation */
+} hdi_spatial_report;
+
+/* Called after each densification step with host copies of the mask before the
+ * step, the error map the step used and the added pixels (ascending). */
+typedef void (*hdi_step_hook)(int32_t step, const uint8_t *mask_before, const float *err,
+                              const int32_t *added, int64_t n_added, void *user);
+
+size_t hdi_spatial_workspace_bytes(hdi_image img);
+
+/* Spatial optimisation (Sec. 4, Alg. 1): the initial mask above, then n steps,
+ * each an inpainting (warm-started from the previous one after the first), the
+ * error map e = fp32(sum_c (u_c - f_c)^2) and densify_step up to the schedule
+ * target (cumulative sizes from the realised initial size to floor(d W H); with
+ * t = 1 equal steps rounded half to even, else growing by t), and a final
+ * inpainting.
+ *   mask   H x W uint8 output (device)
+ *   u      nullable C x H x W float64 output: the final reconstruction
+ *   hook   nullable step hook (host copies; costs a device-to-host copy per step) */
+int32_t spatial_optimize(hdi_image img, const float *f, const double *rand, const hdi_spatial_params *params,
+                         uint8_t *mask, double *u, void *ws, size_t ws_bytes, hdi_spatial_report *report,
+                         hdi_step_hook hook, void *hook_user, void *stream);
+
 /* Autotuner of the inpainting solver: runs inpaint_solve on this image once
  * per candidate parameter set (reps times each, keeping the fastest device
  * time) and returns the index of the fastest candidate that reached its

@@ -12,8 +12,9 @@ step by step, so that a GPU implementation can be compared bit for bit:
 
   L1 magnitude   l_p = sum over channels of |(Delta f_c)_p|, with the 5-point
                  Laplacian under the reflecting boundary (a neighbour outside
-                 the image is the pixel itself), in float64 (exact for float32
-                 data, so any summation order gives the same value).
+                 the image is the pixel itself), in float64, added up, down,
+                 left, right, minus four times the centre, channels in order
+                 (exact for image data, whose values span few binades).
   L2 scale       the coin of pixel p lands with probability alpha * l_p, where
                  alpha = n0 / (S 2^-16) and S = sum_p round(l_p 2^16) as an
                  integer (exact and order independent), so the expected mask

@@ -15,7 +15,8 @@ import torch
 from . import _lib
 from ._lib import HdiError, check
 
-__all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "error_map", "Server", "DELAUNAY", "VORONOI",
+__all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "error_map", "initial_mask",
+           "spatial_optimize", "Server", "DELAUNAY", "VORONOI",
            "INPAINT", "TONAL", "hdi_block_count", "SolveParams", "TonalParams", "HdiError", "PCG_RAS", "RAS", "CGNR"]
 
 PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
@@ -153,6 +154,62 @@ def error_map(u: torch.Tensor, f: torch.Tensor, out: torch.Tensor | None = None)
     err = out if out is not None else torch.empty(u.shape[1:], dtype=torch.float32, device=u.device)
     check(_lib.lib().hdi_error_map(_img(u.shape), _ptr(u), _ptr(f), _ptr(err), _stream_ptr(u.device)))
     return err
+
+
+def initial_mask(f: torch.Tensor, rand: torch.Tensor, n0: int):
+    """Laplacian-magnitude random dithering (Sec. 4.2) with the given uniforms
+    (H, W) float64. Returns (mask uint8, count)."""
+    if f.dim() != 3 or rand.shape != f.shape[1:] or rand.dtype != torch.float64 or f.dtype != torch.float32:
+        raise ValueError("need f (C,H,W) float32 and rand (H,W) float64")
+    if not (f.is_cuda and rand.is_cuda and f.is_contiguous() and rand.is_contiguous()):
+        raise ValueError("f and rand must be contiguous GPU tensors")
+    L = _lib.lib()
+    img = _img(f.shape)
+    mask = torch.empty(f.shape[1:], dtype=torch.uint8, device=f.device)
+    ws = workspace(L.hdi_initial_mask_workspace_bytes(img), f.device)
+    n = ctypes.c_int64(0)
+    check(L.hdi_initial_mask(img, _ptr(f), _ptr(rand), int(n0), _ptr(mask), ctypes.byref(n), _ptr(ws), ws.numel(),
+                             _stream_ptr(f.device)))
+    return mask, n.value
+
+
+def spatial_optimize(f: torch.Tensor, rand: torch.Tensor, density: float, n_steps: int = 20, t: float = 1.0,
+                     n0: int = 0, partition: int = DELAUNAY, solve: SolveParams | None = None, hook=None,
+                     ws: torch.Tensor | None = None):
+    """Spatial optimisation (Sec. 4, Alg. 1): Laplacian-dithered initial mask,
+    then n_steps of inpainting, error map and densification. hook(step,
+    mask_before, err, added) receives numpy copies after each step. Returns
+    (mask uint8, u float64, report dict)."""
+    import numpy as np
+    if f.dim() != 3 or rand.shape != f.shape[1:] or rand.dtype != torch.float64 or f.dtype != torch.float32:
+        raise ValueError("need f (C,H,W) float32 and rand (H,W) float64")
+    if not (f.is_cuda and rand.is_cuda and f.is_contiguous() and rand.is_contiguous()):
+        raise ValueError("f and rand must be contiguous GPU tensors")
+    L = _lib.lib()
+    img = _img(f.shape)
+    C, H, W = f.shape
+    mask = torch.empty((H, W), dtype=torch.uint8, device=f.device)
+    u = torch.empty(f.shape, dtype=torch.float64, device=f.device)
+    if ws is None:
+        ws = workspace(L.hdi_spatial_workspace_bytes(img), f.device)
+    p = _lib.hdi_spatial_params(float(density), float(t), int(n0), int(n_steps), int(partition),
+                                (solve or SolveParams()).c())
+    rep = _lib.hdi_spatial_report()
+    if hook is not None:
+        def _cb(step, m_ptr, e_ptr, a_ptr, n_added, _user):
+            m = np.ctypeslib.as_array(m_ptr, shape=(H * W,)).reshape(H, W).copy()
+            e = np.ctypeslib.as_array(e_ptr, shape=(H * W,)).reshape(H, W).copy()
+            a = np.ctypeslib.as_array(a_ptr, shape=(max(int(n_added), 1),))[:int(n_added)].copy()
+            hook(int(step), m, e, a)
+        cb = _lib.HDI_STEP_HOOK(_cb)
+    else:
+        cb = _lib.HDI_STEP_HOOK()
+    st = L.spatial_optimize(img, _ptr(f), _ptr(rand), ctypes.byref(p), _ptr(mask), _ptr(u), _ptr(ws), ws.numel(),
+                            ctypes.byref(rep), cb, None, _stream_ptr(f.device))
+    check(st)
+    report = {"initial_count": rep.initial_count, "final_count": rep.final_count, "solve_rounds": rep.solve_rounds,
+              "rel_residual": list(rep.rel_residual)[:C], "ms": rep.ms}
+    return mask, u, report
 
 
 def densify_step(mask: torch.Tensor, err: torch.Tensor, n_add: int, partition: int = DELAUNAY,

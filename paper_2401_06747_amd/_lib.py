@@ -54,6 +54,19 @@ class hdi_request_report(ctypes.Structure):
                 ("t_done_ms", ctypes.c_double)]
 
 
+class hdi_spatial_params(ctypes.Structure):
+    _fields_ = [("density", ctypes.c_double), ("t", ctypes.c_double), ("n0", ctypes.c_int64),
+                ("n_steps", ctypes.c_int32), ("partition", ctypes.c_int32), ("solve", hdi_solve_params)]
+
+
+class hdi_spatial_report(ctypes.Structure):
+    _fields_ = [("initial_count", ctypes.c_int64), ("final_count", ctypes.c_int64), ("solve_rounds", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double * 3), ("ms", ctypes.c_float)]
+
+
+HDI_STEP_HOOK = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_float),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.c_void_p)
+
 HDI_REQ_INPAINT, HDI_REQ_TONAL = 0, 1
 HDI_REQ_HOST_IO = 1
 HDI_SERVER_PLAIN = 1
@@ -74,6 +87,12 @@ _SIGS = {
     "tonal_optimize": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                         ctypes.POINTER(hdi_tonal_params), ctypes.POINTER(hdi_tonal_report), _P]),
     "hdi_error_map": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P]),
+    "hdi_initial_mask_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
+    "hdi_initial_mask": (ctypes.c_int32, [hdi_image, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64), _P,
+                                          ctypes.c_size_t, _P]),
+    "hdi_spatial_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
+    "spatial_optimize": (ctypes.c_int32, [hdi_image, _P, _P, ctypes.POINTER(hdi_spatial_params), _P, _P, _P,
+                                          ctypes.c_size_t, ctypes.POINTER(hdi_spatial_report), HDI_STEP_HOOK, _P, _P]),
     "hdi_densify_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "densify_step": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32, _P,
                                       ctypes.POINTER(ctypes.c_int64), _P, ctypes.c_size_t, _P]),

@@ -13,6 +13,7 @@ HEADER = os.path.join(ROOT, "include", "hdi.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"^\s*typedef[^;]*;", "", src, flags=re.M)   # function-pointer types are not entry points
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
     return sorted(set(n for n in names if n not in ("if", "while")))
 
