@@ -80,6 +80,14 @@ typedef struct {
 
 #define HDI_FLAG_NO_FMG 1   /* cold start from u = C f instead of the reduced
                                full-multigrid initialisation (Sec. 3.2) */
+#define HDI_FLAG_CG 2       /* comparator: plain FP64 conjugate gradients on the
+                               unknown pixels (Sec. 2.1) instead of the multigrid
+                               method; the baseline of the paper's tonal
+                               experiments nests it in CGNR (Sec. 6.1). The same
+                               rel_tol criterion on the true FP64 residual; the cap
+                               is 1000 * max_outer CG steps, outer_iters reports
+                               CG steps and vcycles 0. Single solves only:
+                               hdi_solve_batch and the server reject it. */
 
 typedef struct {
     double rel_residual[3];  /* achieved FP64 relative residual per channel */
@@ -166,7 +174,9 @@ typedef struct {
     double mse_initial;          /* ||f - B g0||^2 / (C N) at the start */
     double mse_final;            /* the same at the returned g */
     double rel_normal_residual;  /* true relative normal residual, max over channels */
-    int32_t outer_iters, inner_solves, inner_vcycles;
+    int32_t outer_iters, inner_solves;
+    int32_t inner_vcycles;       /* V-cycles of the inner solves (CG steps when
+                                    the inner parameters set HDI_FLAG_CG) */
     float ms;
 } hdi_tonal_report;
 

@@ -17,9 +17,12 @@ from ._lib import HdiError, check
 
 __all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "error_map", "initial_mask",
            "spatial_optimize", "Server", "DELAUNAY", "VORONOI",
-           "INPAINT", "TONAL", "hdi_block_count", "SolveParams", "TonalParams", "HdiError", "PCG_RAS", "RAS", "CGNR"]
+           "INPAINT", "TONAL", "hdi_block_count", "SolveParams", "TonalParams", "HdiError", "PCG_RAS", "RAS", "CGNR",
+           "FLAG_NO_FMG", "FLAG_CG"]
 
 PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
+# solve flags: cold start without the FMG initial guess; plain FP64 CG instead of multigrid (comparator)
+FLAG_NO_FMG, FLAG_CG = _lib.HDI_FLAG_NO_FMG, _lib.HDI_FLAG_CG
 DELAUNAY, VORONOI = _lib.HDI_PART_DELAUNAY, _lib.HDI_PART_VORONOI
 
 

@@ -7,6 +7,7 @@ LIB_PATH = os.path.join(HERE, "libhdi.so")
 
 HDI_OK, HDI_ERR_ARG, HDI_ERR_EMPTY_MASK, HDI_ERR_NO_CONVERGENCE, HDI_ERR_WORKSPACE, HDI_ERR_HIP, HDI_ERR_BUDGET = range(7)
 HDI_FLAG_NO_FMG = 1
+HDI_FLAG_CG = 2
 
 
 class hdi_image(ctypes.Structure):

@@ -432,6 +432,10 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
         }
         int32_t st = fill_cfg(params ? &params[i] : nullptr, ej[i].cfg, ej[i].overlap);
         if (st) return st;
+        if (ej[i].cfg.flags & HDI_FLAG_CG) {
+            set_error("job %d: batches run the multigrid solver only (HDI_FLAG_CG is for single solves)", i);
+            return HDI_ERR_ARG;
+        }
         ej[i].job = jobs[i];
         ej[i].slot = i;
     }

@@ -70,7 +70,12 @@ struct Hierarchy {
     int nblk;           // blocks of the residual kernel
     int nlev_full;      // levels down to one block
     unsigned int known[MAX_LEVELS];  // host copy of counts
+    // plain CG solver (HDI_FLAG_CG): three FP64 C x H x W vectors (residual and
+    // two search directions) aliasing the multigrid buffers (a solve uses one
+    // method or the other), its block partial sums and scalars
+    double *cg_r, *cg_p[2], *cg_part, *cg_scal;
 };
+constexpr int CG_BLOCKS = 1024;   // workgroups of the CG kernels (grid-stride)
 
 // Lay out the hierarchy in the arena (base == nullptr: size query only).
 // small_from: the first level smoothed with 16x16 blocks, which use half the
@@ -162,6 +167,14 @@ void launch_b_restrict(const BPhase &ph, const BLev *L, const BImg *I, hipStream
 void launch_b_data_restrict(bool from_f, const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
 void launch_b_fmg_prolong(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
 void launch_b_fmg_prolong0(const BPhase &ph, const BLev *L, const BImg *I, hipStream_t s);
+
+// Plain CG (comparator): start computes r = b - A u, r.r and b.b (beta = 0);
+// one iteration is direction, alpha, update, beta (scalars stay on the device).
+template <typename TD>
+void launch_cg_start(int W, int H, int C, const uint8_t *mask, const double *u, const TD *data, const double *src,
+                     double *r, double *part, double *scal, hipStream_t s);
+void launch_cg_iteration(int W, int H, int C, const uint8_t *mask, double *u, double *r, const double *p_old,
+                         double *p_new, double *part, double *scal, hipStream_t s);
 
 // Coarse masks, known counts and the number of levels for a new mask.
 int32_t prepare_mask(Hierarchy &h, hipStream_t s);

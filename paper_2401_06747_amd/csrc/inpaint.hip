@@ -85,6 +85,16 @@ void set_error(const char *fmt, ...) {
 bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask0,
                     int small_from) {
     h.C = C;
+    // small buffers first, so that the large ones form one region the CG
+    // vectors can alias
+    h.counts = (unsigned int *)a.take(MAX_LEVELS * sizeof(unsigned int));
+    const dim3 g = residual_grid(W, H);
+    h.nblk = (int)(g.x * g.y);
+    h.partials = (double *)a.take((size_t)C * h.nblk * 2 * sizeof(double));
+    h.norms = (double *)a.take((size_t)C * 2 * sizeof(double));
+    h.cg_part = (double *)a.take((size_t)C * CG_BLOCKS * 2 * sizeof(double));
+    h.cg_scal = (double *)a.take(64 * sizeof(double));
+    const size_t big0 = (a.used + 255) & ~(size_t)255;
     int l = 0;
     int w = W, hh = H;
     for (;;) {
@@ -114,12 +124,14 @@ bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, co
         hh = (hh + 1) / 2;
     }
     h.nlev = h.nlev_full = l;
-    h.counts = (unsigned int *)a.take(MAX_LEVELS * sizeof(unsigned int));
-    const dim3 g = residual_grid(W, H);
-    h.nblk = (int)(g.x * g.y);
     h.u_alt = (double *)a.take((size_t)W * H * C * sizeof(double));
-    h.partials = (double *)a.take((size_t)C * h.nblk * 2 * sizeof(double));
-    h.norms = (double *)a.take((size_t)C * 2 * sizeof(double));
+    // CG vectors over the same region (extended where small images leave it short)
+    const size_t vec = ((size_t)W * H * C * sizeof(double) + 255) & ~(size_t)255;
+    if (a.used < big0 + 3 * vec) a.take(big0 + 3 * vec - a.used);
+    auto at = [&](int k) { return a.base ? (double *)(a.base + big0 + k * vec) : nullptr; };
+    h.cg_r = at(0);
+    h.cg_p[0] = at(1);
+    h.cg_p[1] = at(2);
     return a.base == nullptr || a.used <= a.size;
 }
 
@@ -167,6 +179,62 @@ static void fmg_init(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     launch_fmg_prolong0(W, H, C, mask, h.lev[1], cur, u, s);
 }
 
+// Plain FP64 conjugate gradients on the unknown pixels (comparator, Sec. 2.1
+// and the GPU baseline of Sec. 6.1). The recursive residual is read back every
+// CG_CHECK steps; once it meets the tolerance the true residual is recomputed
+// and, if that misses it, CG restarts from it. Returns the status; rounds
+// counts CG steps.
+constexpr int CG_CHECK = 10;
+
+template <typename TD>
+static int32_t solve_cg(Hierarchy &h, int W, int H, int C, const uint8_t *mask, const TD *data, const double *src,
+                        double *u, const SolveCfg &cfg, double *rel, int &rounds, hipStream_t s, Prof *prof) {
+    const double N = (double)W * H, nU = N - (double)cfg.known;
+    const int64_t cap = (int64_t)cfg.max_outer * 1000;
+    double sc[3 * 8];
+    int cur = 0;
+    bool from_true = true;   // the residual in cg_r was just recomputed
+    if (prof) prof->begin(0, N * (1 + 16.0 * C) + C * (double)cfg.known * sizeof(TD) + (src ? 8.0 * C * nU : 0.0), s);
+    launch_cg_start<TD>(W, H, C, mask, u, data, src, h.cg_r, h.cg_part, h.cg_scal, s);
+    if (prof) prof->end(s);
+    for (;;) {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(sc, h.cg_scal, sizeof(double) * 8 * C, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double worst = 0.0;
+        bool finite = true;
+        for (int c = 0; c < C; ++c) {
+            const double rr = sc[8 * c], bb = sc[8 * c + 1];
+            finite = finite && std::isfinite(rr) && std::isfinite(bb);
+            rel[c] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+            worst = std::fmax(worst, rel[c]);
+        }
+        if (!finite) {
+            set_error("non-finite residual: the input holds NaN/Inf or the iteration diverged");
+            return HDI_ERR_ARG;
+        }
+        if (worst <= cfg.rel_tol) {
+            if (from_true) return HDI_OK;
+            launch_cg_start<TD>(W, H, C, mask, u, data, src, h.cg_r, h.cg_part, h.cg_scal, s);
+            from_true = true;
+            continue;
+        }
+        if (rounds >= cap) {
+            set_error("relative residual %.3e above tolerance %.3e after %d CG steps", worst, cfg.rel_tol, rounds);
+            return HDI_ERR_NO_CONVERGENCE;
+        }
+        // per step and unknown pixel-channel: direction reads r, p and writes p;
+        // the update reads p, u, r and writes u, r (8 bytes each), mask twice
+        if (prof) prof->begin(4, CG_CHECK * (nU * C * 64.0 + 2.0 * N), s);
+        for (int k = 0; k < CG_CHECK && rounds < cap; ++k, ++rounds) {
+            launch_cg_iteration(W, H, C, mask, u, h.cg_r, h.cg_p[cur], h.cg_p[cur ^ 1], h.cg_part, h.cg_scal, s);
+            cur ^= 1;
+        }
+        if (prof) prof->end(s);
+        from_true = false;
+    }
+}
+
 template <typename TD>
 int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, const TD *data, const double *src,
                      double *u, bool warm, const SolveCfg &cfg, hdi_solve_report *rep, hipStream_t s, Prof *prof) {
@@ -178,6 +246,26 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipEventRecord(ev0, s));
+    if (cfg.flags & HDI_FLAG_CG) {
+        launch_init_u<TD>(W, H, C, mask, data, warm ? u : nullptr, u, s);
+        double rel[3] = {0, 0, 0};
+        int steps = 0;
+        const int32_t st = solve_cg<TD>(h, W, H, C, mask, data, src, u, cfg, rel, steps, s, prof);
+        HIP_TRY(hipEventRecord(ev1, s));
+        HIP_TRY(hipEventSynchronize(ev1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        if (prof) prof->flush();
+        if (rep) {
+            for (int c = 0; c < 3; ++c) rep->rel_residual[c] = c < C ? rel[c] : 0.0;
+            rep->outer_iters = steps;
+            rep->vcycles = 0;
+            rep->ms = ms;
+        }
+        return st;
+    }
     const double N = (double)W * H, nK = (double)cfg.known, nU = N - nK;
     (void)nU;
     if (prof) prof->begin(5, 0.0, s);
@@ -273,6 +361,10 @@ int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap) {
     cfg.flags = p ? p->flags : 0;
     cfg.small_from = p ? p->small_from : 0;
     overlap = (p && p->overlap > 0) ? p->overlap : 4;
+    if (cfg.flags & ~(HDI_FLAG_NO_FMG | HDI_FLAG_CG)) {
+        set_error("unknown solve flags 0x%x", cfg.flags);
+        return HDI_ERR_ARG;
+    }
     if (overlap < 2 || overlap > 16 || (overlap & 1)) {
         set_error("overlap %d outside 2..16 or odd", overlap);
         return HDI_ERR_ARG;

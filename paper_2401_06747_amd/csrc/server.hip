@@ -421,6 +421,10 @@ int32_t hdi_server_submit(hdi_server *srv, const hdi_request *req, uint64_t *tic
     t->req.tonal = nullptr;
     int32_t st = fill_cfg(&t->req.solve, t->ej.cfg, t->ej.overlap);
     if (st) return st;
+    if (t->ej.cfg.flags & HDI_FLAG_CG) {
+        set_error("the server runs the multigrid solver only (HDI_FLAG_CG is for single solves)");
+        return HDI_ERR_ARG;
+    }
     if (req->kind == HDI_REQ_TONAL && !(srv->flags & HDI_SERVER_PLAIN) && srv->tonal_streams.empty()) {
         set_error("this server has no tonal workers");
         return HDI_ERR_ARG;

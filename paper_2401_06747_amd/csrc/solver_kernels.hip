@@ -883,6 +883,204 @@ template void launch_residual<double>(int, int, int, const uint8_t *, const doub
 template void launch_data_restrict0<float>(int, int, int, const uint8_t *, const float *, const Level &, hipStream_t);
 template void launch_data_restrict0<double>(int, int, int, const uint8_t *, const double *, const Level &, hipStream_t);
 
+// ------------------------------------------------------------------ plain CG (comparator)
+//
+// Unpreconditioned conjugate gradients in FP64 on the unknown pixels (the
+// reduced system L_UU u_U = b_U - L_UK f_K, symmetric positive definite when
+// the mask is non-empty), the classical solver of Sec. 2.1 that the paper's
+// GPU baseline for tonal optimisation nests inside CGNR (Sec. 6.1). Vectors
+// are C x H x W with zeros on known pixels; each channel has its own step
+// sizes. Every kernel runs CG_BLOCKS workgroups in a grid-stride loop, so its
+// per-workgroup partial sums have a fixed order, and one workgroup per channel
+// reduces them in a fixed order: results do not depend on scheduling.
+// scal[c * 8 + k]: k = 0 r.r, 1 b.b, 2 alpha, 3 beta, 4 p.q.
+constexpr int CG_THREADS = 256;
+
+template <int C>
+__device__ __forceinline__ void cg_block_partials(double (&a)[C], double (&b)[C], double *__restrict__ part) {
+    __shared__ double s[CG_THREADS / 64][2 * C];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double x = wave_sum_d(a[c]), y = wave_sum_d(b[c]);
+        if (lane == 0) { s[wid][2 * c] = x; s[wid][2 * c + 1] = y; }
+    }
+    __syncthreads();
+    if (threadIdx.x < C) {
+        const int c = threadIdx.x;
+        double x = 0.0, y = 0.0;
+        for (int w = 0; w < CG_THREADS / 64; ++w) { x += s[w][2 * c]; y += s[w][2 * c + 1]; }
+        part[((size_t)c * CG_BLOCKS + blockIdx.x) * 2 + 0] = x;
+        part[((size_t)c * CG_BLOCKS + blockIdx.x) * 2 + 1] = y;
+    }
+}
+
+// r = b - A u for every pixel (0 on known pixels in the stored r, whose row is
+// the identity with u = data there), partial sums of the true residual's r.r
+// and of b.b with b = data on known pixels and src (or 0) elsewhere.
+template <typename TD, int C>
+__global__ void __launch_bounds__(CG_THREADS)
+k_cg_start(int W, int H, const uint8_t *__restrict__ mask, const double *__restrict__ u,
+           const TD *__restrict__ data, const double *__restrict__ src, double *__restrict__ r,
+           double *__restrict__ part) {
+    const int N = W * H;
+    double rr[C], bb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) rr[c] = bb[c] = 0.0;
+    for (int i = blockIdx.x * CG_THREADS + threadIdx.x; i < N; i += CG_BLOCKS * CG_THREADS) {
+        const int x = i % W, y = i / W;
+        const bool known = mask[i] != 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const double *uc = u + (size_t)c * N;
+            double b, res;
+            if (known) {
+                b = data ? (double)data[(size_t)c * N + i] : 0.0;
+                res = b - uc[i];
+            } else {
+                b = src ? src[(size_t)c * N + i] : 0.0;
+                double au = deg_of(x, y, W, H) * uc[i];
+                if (x > 0) au -= uc[i - 1];
+                if (x < W - 1) au -= uc[i + 1];
+                if (y > 0) au -= uc[i - W];
+                if (y < H - 1) au -= uc[i + W];
+                res = b - au;
+            }
+            r[(size_t)c * N + i] = known ? 0.0 : res;
+            rr[c] += res * res;
+            bb[c] += b * b;
+        }
+    }
+    cg_block_partials<C>(rr, bb, part);
+}
+
+// p_new = r + beta p_old (beta = 0: p_new = r, p_old unread), and the partial
+// sums of p_new.(A p_new) over unknown pixels (p_new is 0 on known pixels).
+// A p_new is not stored: the update recomputes it from p_new, which costs a
+// stencil but saves writing and reading one vector per step.
+template <int C>
+__global__ void __launch_bounds__(CG_THREADS)
+k_cg_direction(int W, int H, const uint8_t *__restrict__ mask, const double *__restrict__ r,
+               const double *__restrict__ p_old, double *__restrict__ p_new, const double *__restrict__ scal,
+               double *__restrict__ part) {
+    const int N = W * H;
+    double pq[C], zero[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) pq[c] = zero[c] = 0.0;
+    for (int i = blockIdx.x * CG_THREADS + threadIdx.x; i < N; i += CG_BLOCKS * CG_THREADS) {
+        const int x = i % W, y = i / W;
+        const bool known = mask[i] != 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const double beta = scal[c * 8 + 3];
+            const double *rc = r + (size_t)c * N, *pc = p_old + (size_t)c * N;
+            auto pn = [&](int j) { return beta != 0.0 ? rc[j] + beta * pc[j] : rc[j]; };
+            const double p0 = pn(i);
+            double qv = 0.0;
+            if (!known) {
+                qv = deg_of(x, y, W, H) * p0;
+                if (x > 0) qv -= pn(i - 1);
+                if (x < W - 1) qv -= pn(i + 1);
+                if (y > 0) qv -= pn(i - W);
+                if (y < H - 1) qv -= pn(i + W);
+            }
+            p_new[(size_t)c * N + i] = p0;
+            pq[c] += p0 * qv;
+        }
+    }
+    cg_block_partials<C>(pq, zero, part);
+}
+
+// q = A p, u += alpha p, r -= alpha q on unknown pixels, partial sums of the
+// new r.r.
+template <int C>
+__global__ void __launch_bounds__(CG_THREADS)
+k_cg_update(int W, int H, const uint8_t *__restrict__ mask, double *__restrict__ u, double *__restrict__ r,
+            const double *__restrict__ p, const double *__restrict__ scal, double *__restrict__ part) {
+    const int N = W * H;
+    double rr[C], zero[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) rr[c] = zero[c] = 0.0;
+    for (int i = blockIdx.x * CG_THREADS + threadIdx.x; i < N; i += CG_BLOCKS * CG_THREADS) {
+        if (mask[i]) continue;
+        const int x = i % W, y = i / W;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const size_t j = (size_t)c * N + i;
+            const double *pc = p + (size_t)c * N;
+            double q = deg_of(x, y, W, H) * pc[i];
+            if (x > 0) q -= pc[i - 1];
+            if (x < W - 1) q -= pc[i + 1];
+            if (y > 0) q -= pc[i - W];
+            if (y < H - 1) q -= pc[i + W];
+            const double alpha = scal[c * 8 + 2];
+            u[j] += alpha * pc[i];
+            const double rn = r[j] - alpha * q;
+            r[j] = rn;
+            rr[c] += rn * rn;
+        }
+    }
+    cg_block_partials<C>(rr, zero, part);
+}
+
+// One workgroup of 1024 threads per channel: fixed-order sum of the CG_BLOCKS
+// partial pairs, then the scalar step. step 0: r.r and b.b of the start
+// (beta = 0); 1: alpha = r.r / p.q; 2: beta = r.r_new / r.r, r.r = r.r_new.
+// A zero denominator (exact convergence) gives a zero step.
+__global__ void __launch_bounds__(1024) k_cg_scalars(int step, const double *__restrict__ part, double *__restrict__ scal) {
+    const int c = blockIdx.x;
+    const double2 v = reinterpret_cast<const double2 *>(part)[(size_t)c * CG_BLOCKS + threadIdx.x];
+    const double a = wave_sum_d(v.x), b = wave_sum_d(v.y);
+    __shared__ double s[16][2];
+    if ((threadIdx.x & 63) == 0) { s[threadIdx.x >> 6][0] = a; s[threadIdx.x >> 6][1] = b; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double x = 0.0, y = 0.0;
+    for (int w = 0; w < 16; ++w) { x += s[w][0]; y += s[w][1]; }
+    double *sc = scal + c * 8;
+    if (step == 0) {
+        sc[0] = x;
+        sc[1] = y;
+        sc[3] = 0.0;
+    } else if (step == 1) {
+        sc[4] = x;
+        sc[2] = x > 0.0 ? sc[0] / x : 0.0;
+    } else {
+        sc[3] = sc[0] > 0.0 ? x / sc[0] : 0.0;
+        sc[0] = x;
+    }
+}
+
+static_assert(CG_BLOCKS == 1024, "k_cg_scalars reduces one partial per thread");
+
+template <typename TD>
+void launch_cg_start(int W, int H, int C, const uint8_t *mask, const double *u, const TD *data, const double *src,
+                     double *r, double *part, double *scal, hipStream_t s) {
+    if (C == 3)
+        k_cg_start<TD, 3><<<CG_BLOCKS, CG_THREADS, 0, s>>>(W, H, mask, u, data, src, r, part);
+    else
+        k_cg_start<TD, 1><<<CG_BLOCKS, CG_THREADS, 0, s>>>(W, H, mask, u, data, src, r, part);
+    k_cg_scalars<<<C, 1024, 0, s>>>(0, part, scal);
+}
+template void launch_cg_start<float>(int, int, int, const uint8_t *, const double *, const float *, const double *,
+                                     double *, double *, double *, hipStream_t);
+template void launch_cg_start<double>(int, int, int, const uint8_t *, const double *, const double *,
+                                      const double *, double *, double *, double *, hipStream_t);
+
+void launch_cg_iteration(int W, int H, int C, const uint8_t *mask, double *u, double *r, const double *p_old,
+                         double *p_new, double *part, double *scal, hipStream_t s) {
+    if (C == 3) {
+        k_cg_direction<3><<<CG_BLOCKS, CG_THREADS, 0, s>>>(W, H, mask, r, p_old, p_new, scal, part);
+        k_cg_scalars<<<C, 1024, 0, s>>>(1, part, scal);
+        k_cg_update<3><<<CG_BLOCKS, CG_THREADS, 0, s>>>(W, H, mask, u, r, p_new, scal, part);
+    } else {
+        k_cg_direction<1><<<CG_BLOCKS, CG_THREADS, 0, s>>>(W, H, mask, r, p_old, p_new, scal, part);
+        k_cg_scalars<<<C, 1024, 0, s>>>(1, part, scal);
+        k_cg_update<1><<<CG_BLOCKS, CG_THREADS, 0, s>>>(W, H, mask, u, r, p_new, scal, part);
+    }
+    k_cg_scalars<<<C, 1024, 0, s>>>(2, part, scal);
+}
+
 // ------------------------------------------------------------------ batched kernels
 // One launch serves several images: each workgroup finds its segment in the
 // launch's segment table (one entry per image and level taking part), looks up

@@ -107,7 +107,7 @@ struct TonalCtx {
         int32_t st = solve_system<double>(t.h, W, H, C, mask, t.img_d, nullptr, u, warm, c, &rep, s, prof);
         if (st) set_error("inner B solve (tol %.1e, warm %d): %s", tol, (int)warm, hdi_last_error());
         ++solves;
-        vcycles += rep.vcycles;
+        vcycles += (c.flags & HDI_FLAG_CG) ? rep.outer_iters : rep.vcycles;
         return st;
     }
     // out = B^T y for an image y (whose K part is read from y, or from yK if
@@ -121,7 +121,7 @@ struct TonalCtx {
         int32_t st = solve_system<double>(t.h, W, H, C, mask, (const double *)nullptr, ysrc, w, warm, c, &rep, s, prof);
         if (st) set_error("inner B^T solve (tol %.1e, warm %d): %s", tol, (int)warm, hdi_last_error());
         ++solves;
-        vcycles += rep.vcycles;
+        vcycles += (c.flags & HDI_FLAG_CG) ? rep.outer_iters : rep.vcycles;
         launch_gather_Bt(W, H, m, C, t.idx, mask, y, yK, w, out, s);
         return st;
     }
