@@ -11,4 +11,6 @@ Everything is float64 and follows the paper's definitions directly:
   densify.py  -- one Delaunay/Voronoi densification step (Sec. 4.1, Alg. 1)
   spatial.py  -- the Laplacian-dithered initial mask and the densification
                  loop around it (Sec. 4.2, Alg. 1)
+  tonal_init.py -- Voronoi initialisation of tonal optimisation: Richardson
+                 steps on cell-averaged interpolation constraints (Sec. 5.3)
 """
