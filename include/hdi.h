@@ -198,6 +198,59 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
                        void *ws, size_t ws_bytes, const hdi_tonal_params *params,
                        hdi_tonal_report *report, void *stream);
 
+/* ------------------------------------------------------------------ Voronoi initialisation */
+
+/* Starting values for tonal optimisation, Sec. 5.3: make the inpainting match
+ * weighted local averages of f around each mask pixel, C W B g = C W f, by
+ * Richardson steps g <- g + tau C W (f - B g) from g = f, stopping once the MSE
+ * rises and keeping the best iterate. W averages over (weighting):          */
+#define HDI_VINIT_DIRECT 0       /* the 3x3 window around the mask pixel, clipped
+                                    to the image (one step at tau = 1 is the
+                                    error balancing of Galic et al.) */
+#define HDI_VINIT_VORONOI 1      /* the mask pixel's Voronoi cell, equal weights */
+#define HDI_VINIT_VORONOI_LOG 2  /* the Voronoi cell, weights 1 / (1 + ln(1 + d))
+                                    at distance d from the mask pixel (default) */
+#define HDI_VINIT_FROM_F 1       /* flags: start from g = f on the mask */
+#define HDI_VINIT_NO_STOP 2      /* flags: take max_iters steps regardless of the MSE */
+#define HDI_VINIT_TRACE 64       /* MSE values kept in the report */
+
+/*   weighting  HDI_VINIT_*;  max_iters  Richardson steps at most (default 20,
+ *   at most 1000);  tau  step size (default 1; the paper asks for a stable one,
+ *   the MSE stop guards the rest);  flags  HDI_VINIT_FROM_F | HDI_VINIT_NO_STOP;
+ *   solve  parameters of the inpaintings (zero fields: defaults). */
+typedef struct {
+    int32_t weighting, max_iters;
+    double tau;
+    int32_t flags;
+    hdi_solve_params solve;
+} hdi_vinit_params;
+
+typedef struct {
+    int32_t steps;                  /* Richardson steps taken */
+    int32_t best;                   /* index of the returned iterate (0: the start) */
+    int32_t solves;                 /* inpaintings */
+    double mse[HDI_VINIT_TRACE];    /* ||f - B g^k||^2 / (C N) for k = 0..steps (first 64) */
+    float ms;                       /* device time of the call */
+} hdi_vinit_report;
+
+/* Bytes of workspace voronoi_init needs for this image. 0 on bad sizes. */
+size_t hdi_vinit_workspace_bytes(hdi_image img);
+
+/* Voronoi initialisation (Sec. 5.3).
+ *   mask  H x W uint8 (device);  f  C x H x W float32 image (device)
+ *   g     C x H x W float64 (device). In: the starting values on the mask
+ *         (ignored with HDI_VINIT_FROM_F). Out: the best iterate on the mask,
+ *         0 elsewhere; pass it to tonal_optimize as its start.
+ *   u     nullable C x H x W float64 output: B g of the returned g (device)
+ *   ws    workspace of at least hdi_vinit_workspace_bytes(img) (device)
+ * Cell averages are sums of round(W_ij (f_j - u_j) 2^32) in 64-bit integers
+ * (exact and order independent); a value |f - u| >= 2^30 (a diverging step
+ * size) returns HDI_ERR_ARG. Returns HDI_ERR_EMPTY_MASK for an all-zero mask
+ * and the inpainting's status if a solve fails. */
+int32_t voronoi_init(hdi_image img, const uint8_t *mask, const float *f, double *g, double *u,
+                     void *ws, size_t ws_bytes, const hdi_vinit_params *params,
+                     hdi_vinit_report *report, void *stream);
+
 /* ------------------------------------------------------------------ serving */
 
 /* A request loop over one device: inpainting and tonal requests of any sizes

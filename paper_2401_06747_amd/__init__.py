@@ -18,12 +18,14 @@ from ._lib import HdiError, check
 __all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "error_map", "initial_mask",
            "spatial_optimize", "Server", "DELAUNAY", "VORONOI",
            "INPAINT", "TONAL", "hdi_block_count", "SolveParams", "TonalParams", "HdiError", "PCG_RAS", "RAS", "CGNR",
-           "FLAG_NO_FMG", "FLAG_CG"]
+           "FLAG_NO_FMG", "FLAG_CG", "voronoi_init", "VINIT_DIRECT", "VINIT_VORONOI", "VINIT_VORONOI_LOG"]
 
 PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
 # solve flags: cold start without the FMG initial guess; plain FP64 CG instead of multigrid (comparator)
 FLAG_NO_FMG, FLAG_CG = _lib.HDI_FLAG_NO_FMG, _lib.HDI_FLAG_CG
 DELAUNAY, VORONOI = _lib.HDI_PART_DELAUNAY, _lib.HDI_PART_VORONOI
+VINIT_DIRECT, VINIT_VORONOI, VINIT_VORONOI_LOG = (_lib.HDI_VINIT_DIRECT, _lib.HDI_VINIT_VORONOI,
+                                                  _lib.HDI_VINIT_VORONOI_LOG)
 
 
 @dataclass
@@ -145,6 +147,35 @@ def tonal_optimize(f: torch.Tensor, mask: torch.Tensor, g0: torch.Tensor | None 
         report["message"] = L.hdi_last_error().decode()
     if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
         check(st)
+    return (g, report, u) if want_u else (g, report)
+
+
+def voronoi_init(f: torch.Tensor, mask: torch.Tensor, weighting: int = VINIT_VORONOI_LOG, max_iters: int = 20,
+                 tau: float = 1.0, stop: bool = True, g0: torch.Tensor | None = None,
+                 solve: SolveParams | None = None, ws: torch.Tensor | None = None, want_u: bool = False):
+    """Starting values for tonal optimisation (Sec. 5.3): Richardson steps on
+    C W B g = C W f from g = f (or g0) on the mask, keeping the best iterate.
+    Returns (g float64 with zeros off the mask, report dict[, u = B g])."""
+    _check_inputs(f, mask)
+    L = _lib.lib()
+    img = _img(f.shape)
+    flags = 0 if stop else _lib.HDI_VINIT_NO_STOP
+    if g0 is None:
+        flags |= _lib.HDI_VINIT_FROM_F
+        g = torch.empty(f.shape, dtype=torch.float64, device=f.device)
+    else:
+        if g0.shape != f.shape or g0.dtype != torch.float64:
+            raise ValueError("g0 must be float64 shaped like f")
+        g = g0.clone()
+    if ws is None:
+        ws = workspace(L.hdi_vinit_workspace_bytes(img), f.device)
+    u = torch.empty(f.shape, dtype=torch.float64, device=f.device) if want_u else None
+    p = _lib.hdi_vinit_params(weighting, max_iters, tau, flags, (solve or SolveParams()).c())
+    rep = _lib.hdi_vinit_report()
+    check(L.voronoi_init(img, _ptr(mask), _ptr(f), _ptr(g), _ptr(u), _ptr(ws), ws.numel(), ctypes.byref(p),
+                         ctypes.byref(rep), _stream_ptr(f.device)))
+    report = {"steps": rep.steps, "best": rep.best, "solves": rep.solves,
+              "mse": list(rep.mse)[:min(rep.steps, _lib.HDI_VINIT_TRACE - 1) + 1], "ms": rep.ms}
     return (g, report, u) if want_u else (g, report)
 
 

@@ -65,6 +65,19 @@ class hdi_spatial_report(ctypes.Structure):
                 ("rel_residual", ctypes.c_double * 3), ("ms", ctypes.c_float)]
 
 
+HDI_VINIT_TRACE = 64
+
+
+class hdi_vinit_params(ctypes.Structure):
+    _fields_ = [("weighting", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("solve", hdi_solve_params)]
+
+
+class hdi_vinit_report(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("best", ctypes.c_int32), ("solves", ctypes.c_int32),
+                ("mse", ctypes.c_double * HDI_VINIT_TRACE), ("ms", ctypes.c_float)]
+
+
 HDI_STEP_HOOK = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_float),
                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.c_void_p)
 
@@ -75,6 +88,8 @@ HDI_TONAL_PCG_RAS, HDI_TONAL_RAS, HDI_TONAL_CGNR = 0, 1, 2
 HDI_TONAL_INIT_FROM_F = 1
 HDI_TONAL_TRACE = 2
 HDI_PART_DELAUNAY, HDI_PART_VORONOI = 0, 1
+HDI_VINIT_DIRECT, HDI_VINIT_VORONOI, HDI_VINIT_VORONOI_LOG = 0, 1, 2
+HDI_VINIT_FROM_F, HDI_VINIT_NO_STOP = 1, 2
 
 _P = ctypes.c_void_p
 _SIGS = {
@@ -87,6 +102,9 @@ _SIGS = {
     "hdi_tonal_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
     "tonal_optimize": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                         ctypes.POINTER(hdi_tonal_params), ctypes.POINTER(hdi_tonal_report), _P]),
+    "hdi_vinit_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
+    "voronoi_init": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                      ctypes.POINTER(hdi_vinit_params), ctypes.POINTER(hdi_vinit_report), _P]),
     "hdi_error_map": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P]),
     "hdi_initial_mask_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
     "hdi_initial_mask": (ctypes.c_int32, [hdi_image, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64), _P,

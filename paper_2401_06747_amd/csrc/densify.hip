@@ -289,8 +289,23 @@ __global__ void k_check_err(int N, const float *__restrict__ err, float emax, in
     if (!(e >= 0.f && e <= emax)) flag[0] = 1;
 }
 
+static inline dim3 gd(long n) { return dim3((unsigned)std::max<long>(1, (n + 255) / 256)); }
+
+size_t voronoi_scratch_ints(int W, int H) {
+    return (size_t)W * H + 2 * (size_t)((H + SEG - 1) / SEG) * W;
+}
+
+void launch_voronoi_labels(int W, int H, const uint8_t *mask, int *scratch, int *labels, hipStream_t s) {
+    const int N = W * H, nseg = (H + SEG - 1) / SEG;
+    int *colnear = scratch, *seg_first = scratch + N, *seg_last = seg_first + (size_t)nseg * W;
+    hipLaunchKernelGGL(k_col_seg, gd((long)W * nseg), dim3(256), 0, s, W, H, nseg, mask, colnear, seg_first,
+                       seg_last);
+    hipLaunchKernelGGL(k_col_fix, gd((long)W * nseg), dim3(256), 0, s, W, H, nseg, seg_first, seg_last, colnear);
+    hipLaunchKernelGGL(k_labels, gd(N), dim3(256), 0, s, W, H, colnear, labels);
+}
+
 struct DensWs {
-    int *colnear, *seg_first, *seg_last, *labels, *owner;
+    int *colnear, *labels, *owner;   // colnear: voronoi_scratch_ints(W, H) ints
     int *seed_idx, *seed_pos, *chunk_cnt, *chunk_off, *total;
     int *ta, *tb, *tc, *ua, *ub, *uc;
     int *ord0, *ord1, *flag, *off;
@@ -314,12 +329,9 @@ static size_t cub_tmp_bytes(int maxn) {
 
 static bool plan_densify(DensWs &d, Arena &a, int W, int H) {
     const size_t N = (size_t)W * H;
-    const int nseg = (H + SEG - 1) / SEG;
     const size_t maxT = 2 * (size_t)std::max(W - 1, 1) * std::max(H - 1, 1);
     const size_t maxC = maxT + N;   // triangles + Voronoi cells
-    d.colnear = (int *)a.take(N * 4);
-    d.seg_first = (int *)a.take((size_t)nseg * W * 4);
-    d.seg_last = (int *)a.take((size_t)nseg * W * 4);
+    d.colnear = (int *)a.take(voronoi_scratch_ints(W, H) * 4);
     d.labels = (int *)a.take(N * 4);
     d.owner = (int *)a.take(N * 4);
     d.seed_idx = (int *)a.take(N * 4);
@@ -364,12 +376,9 @@ static size_t densify_ws_bytes(int W, int H) {
         }                                                                                            \
     } while (0)
 
-static inline dim3 gd(long n) { return dim3((unsigned)std::max<long>(1, (n + 255) / 256)); }
-
 static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *err, long long n_add, int partition,
                            int32_t *added, int64_t *n_added, hipStream_t s) {
     const int N = W * H;
-    const int nseg = (H + SEG - 1) / SEG;
     // seeds in ascending order (the Voronoi cell order) and their ranks
     launch_compact(N, mask, d.chunk_cnt, d.chunk_off, d.total, d.seed_idx, d.seed_pos, s);
     const float emax = (float)std::min(std::ldexp(1.0, 43) / N, 3.0e38);
@@ -388,11 +397,7 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
         return HDI_ERR_ARG;
     }
     // 1 labels
-    hipLaunchKernelGGL(k_col_seg, gd((long)W * nseg), dim3(256), 0, s, W, H, nseg, mask, d.colnear, d.seg_first,
-                       d.seg_last);
-    hipLaunchKernelGGL(k_col_fix, gd((long)W * nseg), dim3(256), 0, s, W, H, nseg, d.seg_first, d.seg_last,
-                       d.colnear);
-    hipLaunchKernelGGL(k_labels, gd(N), dim3(256), 0, s, W, H, d.colnear, d.labels);
+    launch_voronoi_labels(W, H, mask, d.colnear, d.labels, s);
     int T = 0;
     if (partition == HDI_PART_DELAUNAY && W > 1 && H > 1) {
         // 2 triangles: emit, sort by (a, b, c) with two stable radix passes, merge duplicates

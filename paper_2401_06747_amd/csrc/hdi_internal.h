@@ -176,6 +176,11 @@ void launch_cg_start(int W, int H, int C, const uint8_t *mask, const double *u, 
 void launch_cg_iteration(int W, int H, int C, const uint8_t *mask, double *u, double *r, const double *p_old,
                          double *p_new, double *part, double *scal, hipStream_t s);
 
+// Exact Voronoi labels (nearest mask pixel by squared distance, then index)
+// into labels[W*H], using voronoi_scratch_ints(W, H) ints of scratch.
+size_t voronoi_scratch_ints(int W, int H);
+void launch_voronoi_labels(int W, int H, const uint8_t *mask, int *scratch, int *labels, hipStream_t s);
+
 // Coarse masks, known counts and the number of levels for a new mask.
 int32_t prepare_mask(Hierarchy &h, hipStream_t s);
 
