@@ -347,6 +347,75 @@ def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=500, seed=5, tonal_wo
     return res
 
 
+def comparators_bench(torch, hdi, synth, dev, configs=((2160, 3840, 0.05), (2160, 3840, 0.01), (540, 960, 0.05))):
+    """The paper's comparisons on this GPU (Sec. 6.3), per configuration: a
+    mask from spatial optimisation, then inpainting by plain CG against the
+    multigrid method, the tonal initialisations (3x3 error balancing, Voronoi
+    cells with constant or inverse-log weights), and tonal optimisation by CGNR
+    with CG inpaintings (the paper's baseline), CGNR with multigrid
+    inpaintings, stationary RAS and flexible CG with the RAS preconditioner,
+    each from f and from the Voronoi initialisation, all stopped once an
+    iteration improves the MSE by less than 0.1%."""
+    psnr = lambda m: float(10.0 * np.log10(255.0 ** 2 / m))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    results = []
+    for H, W, density in configs:
+        f = torch.tensor(synth.textured_image(H, W, 3, 2, 7), dtype=torch.float32, device=dev)
+        rand = torch.tensor(synth.rng_for(2, 7, 3000).random((H, W)), device=dev)
+        mask, _, _ = hdi.spatial_optimize(f, rand, density, n_steps=20)
+        out = {"workload": f"{W}x{H}x3 RGB, {density:.0%} mask from spatial optimisation (20 Delaunay steps)"}
+        cg = hdi.SolveParams(flags=hdi.FLAG_CG)
+        for name, prm in (("multigrid", None), ("cg", cg)):
+            hdi.inpaint_solve(f, mask, params=prm)
+            (_, rep), ms = timed(lambda: hdi.inpaint_solve(f, mask, params=prm))
+            out[f"inpaint_{name}"] = {"ms": round(ms, 2), "iterations": rep["outer_iters"]}
+        out["inpaint_speedup_multigrid_vs_cg"] = round(out["inpaint_cg"]["ms"] / out["inpaint_multigrid"]["ms"], 2)
+
+        _, opt = hdi.tonal_optimize(f, mask, params=hdi.TonalParams(rel_tol=1e-8))
+        out["psnr_optimum_db"] = round(psnr(opt["mse_final"]), 3)
+        out["psnr_f_db"] = round(psnr(hdi.voronoi_init(f, mask, max_iters=1, stop=False)[1]["mse"][0]), 3)
+        for wname, wgt in (("direct", hdi.VINIT_DIRECT), ("voronoi", hdi.VINIT_VORONOI),
+                           ("voronoi_log", hdi.VINIT_VORONOI_LOG)):
+            hdi.voronoi_init(f, mask, wgt)
+            (_, rep), ms = timed(lambda: hdi.voronoi_init(f, mask, wgt))
+            out[f"init_{wname}"] = {"ms": round(ms, 2), "steps": rep["best"],
+                                    "psnr_db": round(psnr(rep["mse"][rep["best"]]), 3)}
+
+        methods = (("cgnr_cg", hdi.CGNR, cg, False), ("cgnr_multigrid", hdi.CGNR, None, False),
+                   ("ras", hdi.RAS, None, False), ("ras_voronoi", hdi.RAS, None, True),
+                   ("pcg_ras", hdi.PCG_RAS, None, False), ("pcg_ras_voronoi", hdi.PCG_RAS, None, True))
+        for name, mode, inner, vor in methods:
+            prm = hdi.TonalParams(mode=mode, rel_tol=1e-6, max_outer=2000, inner=inner, mse_gain=1e-3)
+
+            def run():
+                g0 = hdi.voronoi_init(f, mask)[0] if vor else None
+                return hdi.tonal_optimize(f, mask, g0=g0, params=prm)
+
+            if name != "cgnr_cg":
+                run()   # warm-up (the baseline is slow enough to time cold)
+            (_, rep), ms = timed(run)
+            out[name] = {"ms": round(ms, 1), "outer_iters": rep["outer_iters"], "inner_solves": rep["inner_solves"],
+                         "psnr_db": round(psnr(rep["mse_final"]), 3), "status": rep["status"]}
+            log(f"comparators {W}x{H} {density:.0%}: {name} {out[name]}")
+        b = out["cgnr_cg"]["ms"]
+        out["speedup_cgnr_multigrid_vs_cgnr_cg"] = round(b / out["cgnr_multigrid"]["ms"], 2)
+        out["speedup_ras_voronoi_vs_cgnr_cg"] = round(b / out["ras_voronoi"]["ms"], 2)
+        out["speedup_ras_voronoi_vs_cgnr_multigrid"] = round(out["cgnr_multigrid"]["ms"] / out["ras_voronoi"]["ms"], 2)
+        out["speedup_best_vs_cgnr_cg"] = round(b / min(out[k]["ms"] for k in ("ras", "ras_voronoi", "pcg_ras",
+                                                                               "pcg_ras_voronoi")), 2)
+        results.append(out)
+        del f, rand, mask
+        torch.cuda.empty_cache()
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +427,7 @@ def main():
     ap.add_argument("--no-densify", action="store_true", help="skip the densification-loop measurement")
     ap.add_argument("--no-spatial", action="store_true", help="skip the full data-optimisation measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-comparators", action="store_true", help="skip the paper-comparator measurement")
     ap.add_argument("--serve-requests", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -434,6 +504,10 @@ def main():
     if not args.no_spatial:
         spatial = spatial_bench(torch, hdi, synth, dev, inst)
         log(f"spatial: {spatial}")
+    comparators = None
+    if not args.no_comparators:
+        comparators = comparators_bench(torch, hdi, synth, dev)
+        log(f"comparators: {comparators}")
     batch = None
     if not args.no_batch:
         batch = batch_bench(torch, hdi, synth, dev)
@@ -461,7 +535,7 @@ def main():
                    "tonal_outer_iters": rt["outer_iters"], "tonal_inner_solves": rt["inner_solves"],
                    "mse_initial": round(rt["mse_initial"], 4), "mse_final": round(rt["mse_final"], 4)},
         "roofline": roofline, "cpu_baseline": cpu, "copy_calibration": copy,
-        "densify": densify, "spatial": spatial, "batch": batch, "serving": serving,
+        "densify": densify, "spatial": spatial, "comparators": comparators, "batch": batch, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -163,11 +163,19 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
  *                stationary RAS iteration overshoot)
  *   flags        HDI_TONAL_INIT_FROM_F
  *   inner        parameters of the global inpainting solves (rel_tol is set
- *                per solve by the outer method)                              */
+ *                per solve by the outer method)
+ *   mse_gain     > 0: also stop once an outer iteration lowers the MSE by less
+ *                than this fraction of its previous value, the criterion the
+ *                paper proposes with CGNR (Sec. 5.1) and uses in its
+ *                comparisons with 1e-3 (Sec. 6.3). The MSE is the running
+ *                estimate ||f - B g||^2 / (C N) of the Krylov modes (the
+ *                evaluated one for stationary RAS); the report holds the final
+ *                values recomputed with tight solves. 0: off (default)     */
 typedef struct {
     double rel_tol;
     int32_t max_outer, mode, overlap, local_outer, local_inner, flags;
     hdi_solve_params inner;
+    double mse_gain;
 } hdi_tonal_params;
 
 typedef struct {

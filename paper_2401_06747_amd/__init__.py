@@ -53,10 +53,11 @@ class TonalParams:
     local_inner: int = 0       # 0 -> 24
     flags: int = 0
     inner: SolveParams | None = None
+    mse_gain: float = 0.0      # > 0: also stop when an iteration lowers the MSE by less than this fraction
 
     def c(self):
         return _lib.hdi_tonal_params(self.rel_tol, self.max_outer, self.mode, self.overlap, self.local_outer,
-                                     self.local_inner, self.flags, (self.inner or SolveParams()).c())
+                                     self.local_inner, self.flags, (self.inner or SolveParams()).c(), self.mse_gain)
 
 
 def _stream_ptr(dev) -> ctypes.c_void_p:

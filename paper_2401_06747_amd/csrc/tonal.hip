@@ -176,6 +176,7 @@ __global__ void k_gather_d(int m, int C, int N, const int *__restrict__ idx, con
 struct TonalCfg {
     double rel_tol;
     int max_outer, mode, overlap, local_outer, local_inner, flags;
+    double mse_gain;   // > 0: stop when an iteration improves the MSE by less than this fraction
 };
 
 static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double *u_out, hdi_tonal_report *rep) {
@@ -226,6 +227,8 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
     int32_t status = HDI_OK;
     double pq_prev[3] = {1, 1, 1};
     bool first = true;
+    double mse_prev = mse0;
+    bool mse_stop = false;
     while (!done) {
         if (it >= tc.max_outer) {
             status = HDI_ERR_NO_CONVERGENCE;
@@ -336,6 +339,23 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             T_ST(X.norms(t.rK, rnorm));
             for (int c = 0; c < C; ++c) rel[c] = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : rnorm[c];
         }
+        if (tc.mse_gain > 0.0) {
+            // relative MSE improvement of this iteration (Sec. 5.1): the
+            // evaluated error for stationary RAS, the running B g otherwise
+            double ss[3] = {0, 0, 0};
+            if (tc.mode == HDI_TONAL_RAS)
+                for (int c = 0; c < C; ++c) ss[c] = sse[c];
+            else
+                T_ST(X.image_residual(ss, t.ug));
+            double mse_now = 0.0;
+            for (int c = 0; c < C; ++c) mse_now += ss[c];
+            mse_now /= (double)C * X.N;
+            if (mse_prev - mse_now < tc.mse_gain * mse_prev) {
+                mse_stop = true;
+                break;
+            }
+            mse_prev = mse_now;
+        }
         if (tc.flags & HDI_TONAL_TRACE)
             fprintf(stderr, "[hdi tonal] it %d mode %d rel %.3e tol_in %.1e solves %d vcycles %d fallbacks %d\n", it,
                     tc.mode, worst(), tol_in, X.solves, X.vcycles, fallbacks);
@@ -373,7 +393,7 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             }
         }
     }
-    if (status != HDI_OK || it == 0) {
+    if (status != HDI_OK || it == 0 || mse_stop) {
         // the final state still needs B g and its error for the report
         T_ST(X.normal_residual(it > 0, tight, sse));
         T_ST(X.norms(t.rK, rnorm));
@@ -424,9 +444,10 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
     tc.local_outer = (params && params->local_outer > 0) ? params->local_outer : 3;
     tc.local_inner = (params && params->local_inner > 0) ? params->local_inner : 24;
     tc.flags = params ? params->flags : 0;
-    if (tc.mode < 0 || tc.mode > 2 || !(tc.rel_tol < 1.0) || tc.overlap < 2 || tc.overlap > 16 || (tc.overlap & 1) ||
+    tc.mse_gain = params ? params->mse_gain : 0.0;
+    if (tc.mode < 0 || tc.mode > 2 || !(tc.rel_tol < 1.0) || !(tc.mse_gain >= 0.0 && tc.mse_gain < 1.0) || tc.overlap < 2 || tc.overlap > 16 || (tc.overlap & 1) ||
         tc.local_outer > 64 || tc.local_inner > 256) {
-        set_error("tonal parameter out of range (mode 0..2, rel_tol < 1, even overlap 2..16)");
+        set_error("tonal parameter out of range (mode 0..2, rel_tol < 1, 0 <= mse_gain < 1, even overlap 2..16)");
         return HDI_ERR_ARG;
     }
     SolveCfg inner;

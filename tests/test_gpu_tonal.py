@@ -172,3 +172,31 @@ def test_poisoned_workspace_gives_identical_results(mode):
     g1, r1 = hdi.tonal_optimize(ft, mt, params=p, ws=torch.full((n,), 0xFF, dtype=torch.uint8, device=DEV))
     assert r0["status"] == 0 and r1["status"] == 0, (r0, r1)
     assert torch.equal(g0, g1)
+
+
+@pytest.mark.parametrize("mode", [hdi.PCG_RAS, hdi.RAS, hdi.CGNR])
+def test_mse_gain_stop(mode):
+    """Sec. 5.1 / 6.3: stopping once an iteration lowers the MSE by less than
+    0.1% ends well before the residual criterion, near the optimal MSE."""
+    inst = synth.config2(120, 180, 3, 0.04, item=31)
+    ft = torch.tensor(inst.f, dtype=torch.float32, device=DEV).contiguous()
+    mt = torch.tensor(inst.mask, dtype=torch.uint8, device=DEV).contiguous()
+    _, full = hdi.tonal_optimize(ft, mt, params=hdi.TonalParams(mode=mode, rel_tol=1e-7))
+    g, rep = hdi.tonal_optimize(ft, mt, params=hdi.TonalParams(mode=mode, rel_tol=1e-7, mse_gain=1e-3))
+    assert rep["status"] == 0 and full["status"] == 0
+    assert rep["outer_iters"] < full["outer_iters"]
+    mse_opt = ot.mse(ot.tonal_optimize(inst.f, inst.mask), inst.f, inst.mask)
+    m = ot.mse(g.cpu().numpy(), inst.f, inst.mask)
+    assert abs(m - rep["mse_final"]) <= 1e-6 * m          # the report holds the recomputed MSE
+    assert mse_opt * (1 - 1e-9) <= m <= 1.05 * mse_opt
+    assert m < rep["mse_initial"]
+    print(mode, "iterations", rep["outer_iters"], "of", full["outer_iters"], "MSE", m, "optimum", mse_opt)
+
+
+def test_mse_gain_out_of_range():
+    f = synth.textured_image(20, 30, 1, 5, 32)
+    m = synth.gradient_mask(f, 0.1)
+    ft = torch.tensor(f, dtype=torch.float32, device=DEV).contiguous()
+    mt = torch.tensor(m, dtype=torch.uint8, device=DEV).contiguous()
+    with pytest.raises(hdi.HdiError):
+        hdi.tonal_optimize(ft, mt, params=hdi.TonalParams(mse_gain=1.5))
