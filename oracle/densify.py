@@ -30,6 +30,23 @@ reading, step by step, so that a GPU implementation can be compared bit for bit:
                  index), until n_add pixels are added.
   S8 Voronoi     the partition="voronoi" variant (the paper's ablation, Sec. 6.2)
                  skips S2-S4: every pixel belongs to the Voronoi cell of V(p).
+
+The paper builds its Voronoi diagram with the jump flooding algorithm of Rong
+and Tan (Sec. 4.2), which is approximate. jfa_labels follows one reading of it,
+integer-exact so that it too can be compared bit for bit:
+
+  J1 passes      labels start as the pixel's own index on mask pixels and none
+                 elsewhere; a pass with step k gives every pixel the best label
+                 among those held before the pass at the nine pixels p + k (i, j),
+                 i, j in {-1, 0, 1}, inside the image, by (|p - s|^2, index(s));
+                 the steps are k0, k0/2, ..., 1.
+  J2 start       k0 = the largest power of two below max(W, H) unless given.
+  J3 loop        in the densification loop the next step's k0 is the smallest
+                 power of two at least the largest pixel-to-label distance of the
+                 current labels (the mask only grows, so that distance bounds the
+                 next one); the first step uses J2.
+A step with JFA labels runs S2-S8 on them unchanged (every mask pixel keeps its
+own label, so the Voronoi cells are still one per mask pixel).
 """
 from __future__ import annotations
 
@@ -67,6 +84,57 @@ def voronoi_labels(mask: np.ndarray, method: str = "auto") -> np.ndarray:
         todo = todo[~done]
         k = min(2 * k, seeds.size)
     return out.reshape(H, W)
+
+
+def jfa_default_step(H: int, W: int) -> int:
+    """J2: the largest power of two below max(W, H) (0: no passes)."""
+    n = max(H, W)
+    k = 1
+    while 2 * k < n:
+        k *= 2
+    return k if n > 1 else 0
+
+
+def jfa_labels(mask: np.ndarray, k0: int | None = None) -> np.ndarray:
+    """J1. int64 H x W labels after jump-flooding passes k0, k0/2, ..., 1."""
+    H, W = mask.shape
+    if not np.any(mask):
+        raise ValueError("empty mask")
+    lab = np.where(np.asarray(mask).ravel() != 0, np.arange(H * W), -1).reshape(H, W)
+    yy, xx = np.mgrid[0:H, 0:W]
+    k = jfa_default_step(H, W) if k0 is None else int(k0)
+    while k >= 1:
+        best_d = np.full((H, W), np.iinfo(np.int64).max, np.int64)
+        best_l = np.full((H, W), -1, np.int64)
+        for dy in (-k, 0, k):
+            for dx in (-k, 0, k):
+                ny, nx = yy + dy, xx + dx
+                ok = (ny >= 0) & (ny < H) & (nx >= 0) & (nx < W)
+                cand = np.where(ok, lab[np.clip(ny, 0, H - 1), np.clip(nx, 0, W - 1)], -1)
+                cy, cx = np.divmod(np.maximum(cand, 0), W)
+                d = (cy - yy) ** 2 + (cx - xx) ** 2
+                better = (cand >= 0) & ((d < best_d) | ((d == best_d) & (cand < best_l)))
+                best_d = np.where(better, d, best_d)
+                best_l = np.where(better, cand, best_l)
+        lab = best_l
+        k //= 2
+    return lab
+
+
+def label_max_d2(labels: np.ndarray) -> int:
+    """Largest squared distance from a pixel to its label."""
+    H, W = labels.shape
+    yy, xx = np.mgrid[0:H, 0:W]
+    ly, lx = np.divmod(labels, W)
+    return int(((ly - yy) ** 2 + (lx - xx) ** 2).max())
+
+
+def jfa_next_step(max_d2: int) -> int:
+    """J3: the smallest power of two at least sqrt(max_d2) (at least 1)."""
+    k = 1
+    while k * k < max_d2:
+        k *= 2
+    return k
 
 
 def _orient(ax, ay, bx, by, cx, cy):
@@ -138,13 +206,15 @@ def quantise(e: np.ndarray) -> np.ndarray:
     return np.rint(np.ldexp(np.asarray(e, np.float32).astype(np.float64), FIXED_SHIFT)).astype(np.uint64)
 
 
-def densify_step(mask: np.ndarray, err: np.ndarray, n_add: int, partition: str = "delaunay"):
+def densify_step(mask: np.ndarray, err: np.ndarray, n_add: int, partition: str = "delaunay",
+                 labels: np.ndarray | None = None):
     """One densification step. Returns (new mask, added pixel indices ascending,
-    and a dict of intermediate results for tests)."""
+    and a dict of intermediate results for tests). labels: the partition's
+    Voronoi labels if not the exact ones (S1), e.g. jfa_labels(mask)."""
     mask = np.asarray(mask).astype(np.uint8)
     err = np.asarray(err, np.float32)
     H, W = mask.shape
-    labels = voronoi_labels(mask)
+    labels = voronoi_labels(mask) if labels is None else np.asarray(labels, np.int64)
     tris = triangles(labels) if partition == "delaunay" else np.zeros((0, 3), np.int64)
     owner, ncells = ownership(labels, tris, partition)
     cells = owner.ravel()

@@ -86,9 +86,10 @@ def error_map(u: np.ndarray, f: np.ndarray) -> np.ndarray:
 
 
 def spatial_optimize(f: np.ndarray, density: float, n_steps: int, r: np.ndarray, t: float = 1.0,
-                     n0: int | None = None, partition: str = "delaunay"):
+                     n0: int | None = None, partition: str = "delaunay", jfa: bool = False):
     """L4: the whole loop with exact (direct) inpaintings. Returns (mask, u,
-    list of per-step added pixel arrays)."""
+    list of per-step added pixel arrays). jfa: the partition's labels come from
+    jump flooding with the shrinking start step of the densification oracle (J3)."""
     f = np.asarray(f, np.float64)
     if f.ndim == 2:
         f = f[None]
@@ -97,9 +98,14 @@ def spatial_optimize(f: np.ndarray, density: float, n_steps: int, r: np.ndarray,
     mask = initial_mask(f, start_size(n_target, n_steps) if n0 is None else n0, r)
     targets = od.schedule(int(mask.sum()), n_target, n_steps, t)
     steps = []
+    k0 = None
     for M in targets:
         u = oi.inpaint(f, mask)
         e = error_map(u, f)
-        mask, added, _ = od.densify_step(mask, e, max(M - int(mask.sum()), 0), partition)
+        labels = None
+        if jfa:
+            labels = od.jfa_labels(mask, k0)
+            k0 = od.jfa_next_step(od.label_max_d2(labels))
+        mask, added, _ = od.densify_step(mask, e, max(M - int(mask.sum()), 0), partition, labels)
         steps.append(added)
     return mask, oi.inpaint(f, mask), steps

@@ -94,3 +94,24 @@ def test_loop_bookkeeping():
     allp = np.concatenate(steps)
     assert np.unique(allp).size == allp.size
     np.testing.assert_allclose(u, oi.inpaint(f, mask))
+
+
+def test_loop_with_jump_flooding_labels():
+    """With J3's shrinking jump-flooding start the loop keeps its bookkeeping,
+    and its steps are densification steps on the jump-flooding labels."""
+    rng = np.random.default_rng(4)
+    H, W = 36, 50
+    f = rng.uniform(0, 255, (1, H, W))
+    r = rng.random((H, W))
+    mask, u, steps = osp.spatial_optimize(f, 0.06, 3, r, jfa=True)
+    n_target = int(np.floor(0.06 * H * W))
+    assert int(mask.sum()) == n_target
+    m = osp.initial_mask(f, osp.start_size(n_target, 3), r)
+    k0 = None
+    for k, M in enumerate(od.schedule(int(m.sum()), n_target, 3)):
+        lab = od.jfa_labels(m, k0)
+        k0 = od.jfa_next_step(od.label_max_d2(lab))
+        e = osp.error_map(oi.inpaint(f, m), f)
+        m, added, _ = od.densify_step(m, e, M - int(m.sum()), "delaunay", lab)
+        np.testing.assert_array_equal(added, steps[k])
+    np.testing.assert_array_equal(m, mask)
