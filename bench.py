@@ -179,30 +179,55 @@ def spatial_bench(torch, hdi, synth, dev, inst, density=0.05, steps=20, reps=3):
     rand = torch.tensor(synth.rng_for(2, 0, 3000).random((H, W)), device=dev)
     ws = hdi.workspace(hdi._lib.lib().hdi_spatial_workspace_bytes(hdi._img(f.shape)), dev)
 
-    def run():
+    def run(partition=hdi.DELAUNAY):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        mask, u, rep = hdi.spatial_optimize(f, rand, density, n_steps=steps, ws=ws)
+        mask, u, rep = hdi.spatial_optimize(f, rand, density, n_steps=steps, partition=partition, ws=ws)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         g, rt = hdi.tonal_optimize(f, mask)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        return (t1 - t0, t2 - t1), u, rep, rt
+        return (t1 - t0, t2 - t1), u, rep, rt, mask
 
     run()
     times = []
     for _ in range(reps):
-        tt, u, rep, rt = run()
+        tt, u, rep, rt, mask = run()
         times.append(tt)
     ts, tt = (float(np.median([x[i] for x in times])) for i in range(2))
     mse_sp = float(((u - f.double()) ** 2).mean())
     psnr = lambda m: float(10.0 * np.log10(255.0 ** 2 / m))
-    return {"workload": f"{W}x{H}x{C} RGB, {density:.0%} mask: Laplacian-dithered start ({rep['initial_count']} px), "
-                        f"{steps} Delaunay densification steps, then tonal optimisation (PCG_RAS, 1e-6)",
-            "spatial_ms": round(ts * 1e3, 1), "tonal_ms": round(tt * 1e3, 1), "total_ms": round((ts + tt) * 1e3, 1),
-            "final_count": rep["final_count"], "solve_rounds": rep["solve_rounds"],
-            "psnr_after_spatial_db": round(psnr(mse_sp), 3), "psnr_after_tonal_db": round(psnr(rt["mse_final"]), 3)}
+    out = {"workload": f"{W}x{H}x{C} RGB, {density:.0%} mask: Laplacian-dithered start ({rep['initial_count']} px), "
+                       f"{steps} Delaunay densification steps, then tonal optimisation (PCG_RAS, 1e-6)",
+           "spatial_ms": round(ts * 1e3, 1), "tonal_ms": round(tt * 1e3, 1), "total_ms": round((ts + tt) * 1e3, 1),
+           "final_count": rep["final_count"], "solve_rounds": rep["solve_rounds"],
+           "psnr_after_spatial_db": round(psnr(mse_sp), 3), "psnr_after_tonal_db": round(psnr(rt["mse_final"]), 3)}
+
+    # jump-flooding labels (Sec. 4.2): the labelling alone on the final mask,
+    # and the whole pipeline with them
+    lws = hdi.workspace(hdi._lib.lib().hdi_labels_workspace_bytes(W, H), dev)
+    ex, d2 = hdi.voronoi_labels(mask, 0, ws=lws)
+    kmin = 1
+    while kmin * kmin < d2:
+        kmin *= 2
+    lab_ms = {}
+    for name, step in (("exact", 0), ("jfa_default_start", -1), ("jfa_shrunk_start", kmin)):
+        hdi.voronoi_labels(mask, step, ws=lws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            lab, _ = hdi.voronoi_labels(mask, step, ws=lws)
+        torch.cuda.synchronize()
+        lab_ms[name] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+        if step:
+            lab_ms[name + "_mislabelled"] = round(float((lab != ex).double().mean()), 6)
+    run(hdi.DELAUNAY | hdi.JFA)
+    tj, uj, repj, rtj, _ = run(hdi.DELAUNAY | hdi.JFA)
+    out["jfa"] = {"labels_ms_on_final_mask": lab_ms, "shrunk_start": kmin, "spatial_ms": round(tj[0] * 1e3, 1),
+                  "psnr_after_spatial_db": round(psnr(float(((uj - f.double()) ** 2).mean())), 3),
+                  "psnr_after_tonal_db": round(psnr(rtj["mse_final"]), 3)}
+    return out
 
 
 def batch_bench(torch, hdi, synth, dev, n_images=64, reps=3):

@@ -327,6 +327,30 @@ void hdi_server_destroy(hdi_server *srv);
 
 #define HDI_PART_DELAUNAY 0   /* triangles of mask pixels (Sec. 4.1) */
 #define HDI_PART_VORONOI 1    /* Voronoi cells of mask pixels (the ablation of Sec. 6.2) */
+#define HDI_PART_JFA 4        /* or'ed in: labels by jump flooding (Sec. 4.2) instead of
+                                 the exact nearest mask pixel; passes with steps k0,
+                                 k0/2, ..., 1 over the nine pixels p + k (i, j),
+                                 i, j in {-1, 0, 1}, best by (squared distance, index),
+                                 k0 the largest power of two below max(W, H). Exact
+                                 integer arithmetic: reproducible, but a few pixels
+                                 can get a farther label than the nearest. */
+
+/* Bytes of workspace hdi_voronoi_labels needs. 0 on bad sizes. */
+size_t hdi_labels_workspace_bytes(int32_t width, int32_t height);
+
+/* Voronoi labels of a mask (Sec. 4.2: the diagram behind the Delaunay
+ * partition): labels[p] = the linear index of p's nearest mask pixel.
+ *   jfa_step  0: exact, ties to the smaller index (the labels densify_step
+ *             uses); -1: jump flooding from the default start; k > 0, a power of
+ *             two: jump flooding from k (fewer passes when every pixel lies
+ *             within about k of a mask pixel)
+ *   mask      H x W uint8 (device), at least one pixel set (else HDI_ERR_EMPTY_MASK)
+ *   labels    H x W int32 output (device)
+ *   max_d2    nullable host output: the largest squared pixel-to-label distance
+ *             (over labelled pixels: jump flooding from too small a start can
+ *             leave pixels at -1) */
+int32_t hdi_voronoi_labels(int32_t width, int32_t height, const uint8_t *mask, int32_t *labels, int32_t jfa_step,
+                           uint64_t *max_d2, void *ws, size_t ws_bytes, void *stream);
 
 /* Error map that drives densification (Sec. 4.1: the squared error of the
  * current reconstruction, summed over the colour channels):
@@ -382,7 +406,10 @@ typedef struct {
     double t;                /* factor of the added counts from step to step (1: equal steps) */
     int64_t n0;              /* expected initial size (0: round(floor(d W H) / (n_steps + 1))) */
     int32_t n_steps;         /* densification steps (Alg. 1; the paper's experiments use 20) */
-    int32_t partition;       /* HDI_PART_DELAUNAY or HDI_PART_VORONOI */
+    int32_t partition;       /* HDI_PART_DELAUNAY or HDI_PART_VORONOI, optionally | HDI_PART_JFA:
+                                jump-flooding labels whose start step shrinks with the
+                                mask (the smallest power of two at least the previous
+                                step's largest pixel-to-label distance) */
     hdi_solve_params solve;  /* parameters of every inpainting solve */
 } hdi_spatial_params;
 

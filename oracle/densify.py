@@ -122,11 +122,13 @@ def jfa_labels(mask: np.ndarray, k0: int | None = None) -> np.ndarray:
 
 
 def label_max_d2(labels: np.ndarray) -> int:
-    """Largest squared distance from a pixel to its label."""
+    """Largest squared distance from a pixel to its label (unlabelled pixels,
+    -1, are skipped)."""
     H, W = labels.shape
     yy, xx = np.mgrid[0:H, 0:W]
-    ly, lx = np.divmod(labels, W)
-    return int(((ly - yy) ** 2 + (lx - xx) ** 2).max())
+    ok = labels >= 0
+    ly, lx = np.divmod(np.where(ok, labels, 0), W)
+    return int(np.where(ok, (ly - yy) ** 2 + (lx - xx) ** 2, 0).max())
 
 
 def jfa_next_step(max_d2: int) -> int:

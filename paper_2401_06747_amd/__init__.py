@@ -18,12 +18,14 @@ from ._lib import HdiError, check
 __all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "error_map", "initial_mask",
            "spatial_optimize", "Server", "DELAUNAY", "VORONOI",
            "INPAINT", "TONAL", "hdi_block_count", "SolveParams", "TonalParams", "HdiError", "PCG_RAS", "RAS", "CGNR",
-           "FLAG_NO_FMG", "FLAG_CG", "voronoi_init", "VINIT_DIRECT", "VINIT_VORONOI", "VINIT_VORONOI_LOG"]
+           "FLAG_NO_FMG", "FLAG_CG", "voronoi_init", "VINIT_DIRECT", "VINIT_VORONOI", "VINIT_VORONOI_LOG",
+           "voronoi_labels", "JFA"]
 
 PCG_RAS, RAS, CGNR = _lib.HDI_TONAL_PCG_RAS, _lib.HDI_TONAL_RAS, _lib.HDI_TONAL_CGNR
 # solve flags: cold start without the FMG initial guess; plain FP64 CG instead of multigrid (comparator)
 FLAG_NO_FMG, FLAG_CG = _lib.HDI_FLAG_NO_FMG, _lib.HDI_FLAG_CG
 DELAUNAY, VORONOI = _lib.HDI_PART_DELAUNAY, _lib.HDI_PART_VORONOI
+JFA = _lib.HDI_PART_JFA   # or'ed into a partition: jump-flooding labels (Sec. 4.2)
 VINIT_DIRECT, VINIT_VORONOI, VINIT_VORONOI_LOG = (_lib.HDI_VINIT_DIRECT, _lib.HDI_VINIT_VORONOI,
                                                   _lib.HDI_VINIT_VORONOI_LOG)
 
@@ -265,6 +267,23 @@ def densify_step(mask: torch.Tensor, err: torch.Tensor, n_add: int, partition: i
                         _ptr(ws), ws.numel(), _stream_ptr(mask.device))
     check(st)
     return added[:n.value]
+
+
+def voronoi_labels(mask: torch.Tensor, jfa_step: int = 0, ws: torch.Tensor | None = None):
+    """Nearest-mask-pixel labels (int32 linear indices): exact for jfa_step 0,
+    jump flooding from the default start for -1 or from a given power of two.
+    Returns (labels, largest squared pixel-to-label distance)."""
+    if mask.dim() != 2 or mask.dtype != torch.uint8 or not (mask.is_cuda and mask.is_contiguous()):
+        raise ValueError("need a contiguous (H,W) uint8 GPU mask")
+    L = _lib.lib()
+    H, W = mask.shape
+    if ws is None:
+        ws = workspace(L.hdi_labels_workspace_bytes(W, H), mask.device)
+    labels = torch.empty((H, W), dtype=torch.int32, device=mask.device)
+    d2 = ctypes.c_uint64(0)
+    check(L.hdi_voronoi_labels(W, H, _ptr(mask), _ptr(labels), int(jfa_step), ctypes.byref(d2), _ptr(ws), ws.numel(),
+                               _stream_ptr(mask.device)))
+    return labels, int(d2.value)
 
 
 def solve_batch(fs, masks, params=None, ws: torch.Tensor | None = None, outs=None):

@@ -88,6 +88,7 @@ HDI_TONAL_PCG_RAS, HDI_TONAL_RAS, HDI_TONAL_CGNR = 0, 1, 2
 HDI_TONAL_INIT_FROM_F = 1
 HDI_TONAL_TRACE = 2
 HDI_PART_DELAUNAY, HDI_PART_VORONOI = 0, 1
+HDI_PART_JFA = 4
 HDI_VINIT_DIRECT, HDI_VINIT_VORONOI, HDI_VINIT_VORONOI_LOG = 0, 1, 2
 HDI_VINIT_FROM_F, HDI_VINIT_NO_STOP = 1, 2
 
@@ -113,6 +114,9 @@ _SIGS = {
     "spatial_optimize": (ctypes.c_int32, [hdi_image, _P, _P, ctypes.POINTER(hdi_spatial_params), _P, _P, _P,
                                           ctypes.c_size_t, ctypes.POINTER(hdi_spatial_report), HDI_STEP_HOOK, _P, _P]),
     "hdi_densify_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "hdi_labels_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "hdi_voronoi_labels": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_uint64), _P, ctypes.c_size_t, _P]),
     "densify_step": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32, _P,
                                       ctypes.POINTER(ctypes.c_int64), _P, ctypes.c_size_t, _P]),
     "hdi_autotune": (ctypes.c_int32, [hdi_image, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(hdi_solve_params),

@@ -108,6 +108,71 @@ __global__ void k_labels(int W, int H, const int *__restrict__ colnear, int *__r
     labels[i] = bi;
 }
 
+// Jump flooding (Sec. 4.2, after Rong and Tan): labels start as the pixel's own
+// index on mask pixels and -1 elsewhere; a pass with step k gives every pixel
+// the best label held before the pass at the nine pixels p + k (i, j),
+// i, j in {-1, 0, 1}, by (squared distance, index). Integer-exact, so the
+// result depends only on the mask and the steps.
+__global__ void k_jfa_init(int N, const uint8_t *__restrict__ mask, int *__restrict__ lab) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) lab[i] = mask[i] ? i : -1;
+}
+
+__global__ void k_jfa_pass(int W, int H, int k, const int *__restrict__ in, int *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W * H) return;
+    const int x = i % W, y = i / W;
+    long long bd = LLONG_MAX;
+    int bl = -1;
+    for (int dy = -k; dy <= k; dy += k) {
+        const int ny = y + dy;
+        if (ny < 0 || ny >= H) continue;
+        for (int dx = -k; dx <= k; dx += k) {
+            const int nx = x + dx;
+            if (nx < 0 || nx >= W) continue;
+            const int c = in[ny * W + nx];
+            if (c < 0) continue;
+            const long long ex = c % W - x, ey = c / W - y;
+            const long long d = ex * ex + ey * ey;
+            if (d < bd || (d == bd && c < bl)) { bd = d; bl = c; }
+        }
+    }
+    out[i] = bl;
+}
+
+// out[0]: the largest squared distance from a pixel to its label; out[1] is
+// set if a pixel has no label (jump flooding from too small a start step).
+// Grid-stride over RED_BLOCKS workgroups of 256 threads, one atomic each.
+constexpr int RED_BLOCKS = 1024;
+__global__ void __launch_bounds__(256)
+k_label_max_d2(int W, int H, const int *__restrict__ lab, unsigned long long *__restrict__ out) {
+    unsigned long long m = 0, none = 0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < (long)W * H; i += (long)RED_BLOCKS * 256) {
+        const int l = lab[i];
+        if (l < 0) {
+            none = 1;
+            continue;
+        }
+        const long long ex = l % W - i % W, ey = l / W - i / W;
+        m = max(m, (unsigned long long)(ex * ex + ey * ey));
+    }
+    __shared__ unsigned long long sm[256], sn[256];
+    sm[threadIdx.x] = m;
+    sn[threadIdx.x] = none;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + h]);
+            sn[threadIdx.x] |= sn[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(out, sm[0]);
+        if (sn[0]) atomicOr(out + 1, 1ull);
+    }
+}
+
 // ------------------------------------------------------------------ 2 triangles
 
 __device__ __forceinline__ long long orient(int W, int a, int b, int c) {
@@ -206,6 +271,16 @@ __global__ void k_fill_u64(int n, unsigned long long *__restrict__ p) {
     if (i < n) p[i] = 0ull;
 }
 
+// Whether any mask pixel is set (count > 0 afterwards): one atomic per wave
+// that sees one, and waves stop looking once the count is positive.
+__global__ void k_count_set(int N, const uint8_t *__restrict__ m, unsigned long long *__restrict__ count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool set = i < N && m[i] != 0;
+    const unsigned long long b = __ballot(set);
+    if ((threadIdx.x & 63) == 0 && b && __hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicAdd(count, (unsigned long long)__popcll(b));
+}
+
 // Closed-triangle coverage with the smallest rank winning (ranks follow the
 // key order). One thread per triangle walks its bounding box.
 __global__ void k_raster(int W, int T, const int *__restrict__ ua, const int *__restrict__ ub,
@@ -295,6 +370,31 @@ size_t voronoi_scratch_ints(int W, int H) {
     return (size_t)W * H + 2 * (size_t)((H + SEG - 1) / SEG) * W;
 }
 
+int jfa_default_step(int W, int H) {
+    const int n = std::max(W, H);
+    int k = 1;
+    while (2 * k < n) k *= 2;
+    return n > 1 ? k : 0;
+}
+
+void launch_jfa_labels(int W, int H, const uint8_t *mask, int k0, int *scratch, int *labels, hipStream_t s) {
+    const int N = W * H;
+    int passes = 0;
+    for (int k = k0; k >= 1; k /= 2) ++passes;
+    // ping-pong so that the last pass writes into labels
+    int *a = (passes % 2 == 0) ? labels : scratch, *b = (passes % 2 == 0) ? scratch : labels;
+    hipLaunchKernelGGL(k_jfa_init, gd(N), dim3(256), 0, s, N, mask, a);
+    for (int k = k0; k >= 1; k /= 2) {
+        hipLaunchKernelGGL(k_jfa_pass, gd(N), dim3(256), 0, s, W, H, k, a, b);
+        std::swap(a, b);
+    }
+}
+
+void launch_label_max_d2(int W, int H, const int *labels, unsigned long long *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, 2, out);
+    hipLaunchKernelGGL(k_label_max_d2, dim3(RED_BLOCKS), dim3(256), 0, s, W, H, labels, out);
+}
+
 void launch_voronoi_labels(int W, int H, const uint8_t *mask, int *scratch, int *labels, hipStream_t s) {
     const int N = W * H, nseg = (H + SEG - 1) / SEG;
     int *colnear = scratch, *seg_first = scratch + N, *seg_last = seg_first + (size_t)nseg * W;
@@ -310,7 +410,7 @@ struct DensWs {
     int *ta, *tb, *tc, *ua, *ub, *uc;
     int *ord0, *ord1, *flag, *off;
     unsigned int *keyc0, *keyc1, *count;
-    unsigned long long *keyab0, *keyab1, *E, *best, *rk0, *rk1;
+    unsigned long long *keyab0, *keyab1, *E, *best, *rk0, *rk1, *maxd2;
     uint8_t *newpix;
     void *tmp;
     size_t tmp_bytes;
@@ -348,6 +448,7 @@ static bool plan_densify(DensWs &d, Arena &a, int W, int H) {
     d.keyc0 = (unsigned int *)a.take(maxT * 4);
     d.keyc1 = (unsigned int *)a.take(maxT * 4);
     d.count = (unsigned int *)a.take(16);
+    d.maxd2 = (unsigned long long *)a.take(16);
     d.keyab0 = (unsigned long long *)a.take(maxT * 8);
     d.keyab1 = (unsigned long long *)a.take(maxT * 8);
     d.E = (unsigned long long *)a.take(maxC * 8);
@@ -377,7 +478,9 @@ static size_t densify_ws_bytes(int W, int H) {
     } while (0)
 
 static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *err, long long n_add, int partition,
-                           int32_t *added, int64_t *n_added, hipStream_t s) {
+                           int jfa_k0, int32_t *added, int64_t *n_added, uint64_t *max_d2, hipStream_t s) {
+    const bool jfa = (partition & HDI_PART_JFA) != 0;
+    partition &= ~HDI_PART_JFA;
     const int N = W * H;
     // seeds in ascending order (the Voronoi cell order) and their ranks
     launch_compact(N, mask, d.chunk_cnt, d.chunk_off, d.total, d.seed_idx, d.seed_pos, s);
@@ -396,8 +499,22 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
         set_error("error map holds a value that is negative, not finite or above %g", (double)emax);
         return HDI_ERR_ARG;
     }
-    // 1 labels
-    launch_voronoi_labels(W, H, mask, d.colnear, d.labels, s);
+    // 1 labels (exact, or by jump flooding)
+    if (jfa) {
+        launch_jfa_labels(W, H, mask, jfa_k0 > 0 ? jfa_k0 : jfa_default_step(W, H), d.colnear, d.labels, s);
+        // every later stage indexes by label: refuse unlabelled pixels
+        launch_label_max_d2(W, H, d.labels, d.maxd2, s);
+        unsigned long long r[2] = {0, 0};
+        D_TRY(hipMemcpyAsync(r, d.maxd2, sizeof r, hipMemcpyDeviceToHost, s));
+        D_TRY(hipStreamSynchronize(s));
+        if (r[1]) {
+            set_error("jump flooding from step %d left pixels without a label", jfa_k0);
+            return HDI_ERR_ARG;
+        }
+    } else {
+        launch_voronoi_labels(W, H, mask, d.colnear, d.labels, s);
+        if (max_d2) launch_label_max_d2(W, H, d.labels, d.maxd2, s);
+    }
     int T = 0;
     if (partition == HDI_PART_DELAUNAY && W > 1 && H > 1) {
         // 2 triangles: emit, sort by (a, b, c) with two stable radix passes, merge duplicates
@@ -455,10 +572,37 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
     D_TRY(hipMemcpyAsync(&na, d.total, sizeof(int), hipMemcpyDeviceToHost, s));
     D_TRY(hipStreamSynchronize(s));
     if (added && na > 0) hipLaunchKernelGGL(k_copy_i32, gd(na), dim3(256), 0, s, na, d.seed_idx, added);
+    if (max_d2) D_TRY(hipMemcpyAsync(max_d2, d.maxd2, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     D_TRY(hipGetLastError());
     D_TRY(hipStreamSynchronize(s));
     *n_added = na;
     return HDI_OK;
+}
+
+int32_t densify_step_ex(int W, int H, uint8_t *mask, const float *err, long long n_add, int partition, int jfa_k0,
+                        int32_t *added, int64_t *n_added, uint64_t *max_d2, void *ws, size_t ws_bytes, hipStream_t s) {
+    hdi_image img{W, H, 1};
+    if (!check_image(img)) return HDI_ERR_ARG;
+    if (!mask || !err || !n_added) {
+        set_error("mask, err and n_added must be non-null");
+        return HDI_ERR_ARG;
+    }
+    const int base = partition & ~HDI_PART_JFA;
+    if (n_add < 0 || (base != HDI_PART_DELAUNAY && base != HDI_PART_VORONOI) || jfa_k0 < 0 ||
+        (jfa_k0 & (jfa_k0 - 1))) {
+        set_error("n_add must be >= 0, partition HDI_PART_DELAUNAY or HDI_PART_VORONOI (optionally | HDI_PART_JFA) "
+                  "and a jump-flooding start a power of two");
+        return HDI_ERR_ARG;
+    }
+    const size_t need = densify_ws_bytes(W, H);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
+        return HDI_ERR_WORKSPACE;
+    }
+    Arena a{(char *)ws, ws_bytes, 0};
+    DensWs d;
+    plan_densify(d, a, W, H);
+    return run_densify(d, W, H, mask, err, n_add, partition, jfa_k0, added, n_added, max_d2, s);
 }
 
 // Error map of the densification loop: e = fp32(sum_c (u_c - f_c)^2), summed in
@@ -506,25 +650,59 @@ size_t hdi_densify_workspace_bytes(int32_t width, int32_t height) {
 
 int32_t densify_step(int32_t width, int32_t height, uint8_t *mask, const float *err, int64_t n_add,
                      int32_t partition, int32_t *added, int64_t *n_added, void *ws, size_t ws_bytes, void *stream) {
+    return densify_step_ex(width, height, mask, err, n_add, partition, 0, added, n_added, nullptr, ws, ws_bytes,
+                           (hipStream_t)stream);
+}
+
+size_t hdi_labels_workspace_bytes(int32_t width, int32_t height) {
+    if (width < 1 || height < 1 || (int64_t)width * height > (int64_t)1 << 30) return 0;
+    return voronoi_scratch_ints(width, height) * sizeof(int) + 2 * 256;
+}
+
+int32_t hdi_voronoi_labels(int32_t width, int32_t height, const uint8_t *mask, int32_t *labels, int32_t jfa_step,
+                           uint64_t *max_d2, void *ws, size_t ws_bytes, void *stream) {
     hdi_image img{width, height, 1};
     if (!check_image(img)) return HDI_ERR_ARG;
-    if (!mask || !err || !n_added) {
-        set_error("mask, err and n_added must be non-null");
+    if (!mask || !labels) {
+        set_error("mask and labels must be non-null device pointers");
         return HDI_ERR_ARG;
     }
-    if (n_add < 0 || (partition != HDI_PART_DELAUNAY && partition != HDI_PART_VORONOI)) {
-        set_error("n_add must be >= 0 and partition HDI_PART_DELAUNAY or HDI_PART_VORONOI");
+    if (jfa_step < -1 || (jfa_step > 0 && (jfa_step & (jfa_step - 1)))) {
+        set_error("jfa_step must be 0 (exact), -1 (jump flooding from the default step) or a power of two");
         return HDI_ERR_ARG;
     }
-    const size_t need = densify_ws_bytes(width, height);
+    const size_t need = hdi_labels_workspace_bytes(width, height);
     if (!ws || ws_bytes < need) {
         set_error("workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
         return HDI_ERR_WORKSPACE;
     }
+    hipStream_t s = (hipStream_t)stream;
+    const int N = width * height;
     Arena a{(char *)ws, ws_bytes, 0};
-    DensWs d;
-    plan_densify(d, a, width, height);
-    return run_densify(d, width, height, mask, err, n_add, partition, added, n_added, (hipStream_t)stream);
+    int *scratch = (int *)a.take(voronoi_scratch_ints(width, height) * sizeof(int));
+    unsigned long long *slot = (unsigned long long *)a.take(32);
+    // an empty mask has no labels
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, 4, slot);
+    hipLaunchKernelGGL(k_count_set, gd(N), dim3(256), 0, s, N, mask, slot + 2);
+    unsigned long long cnt = 0;
+    D_TRY(hipMemcpyAsync(&cnt, slot + 2, sizeof cnt, hipMemcpyDeviceToHost, s));
+    D_TRY(hipStreamSynchronize(s));
+    if (cnt == 0) {
+        set_error("empty mask: no labels");
+        return HDI_ERR_EMPTY_MASK;
+    }
+    if (jfa_step == 0)
+        launch_voronoi_labels(width, height, mask, scratch, labels, s);
+    else
+        launch_jfa_labels(width, height, mask, jfa_step > 0 ? jfa_step : jfa_default_step(width, height), scratch,
+                          labels, s);
+    if (max_d2) {
+        launch_label_max_d2(width, height, labels, slot, s);
+        D_TRY(hipMemcpyAsync(max_d2, slot, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    }
+    D_TRY(hipGetLastError());
+    D_TRY(hipStreamSynchronize(s));
+    return HDI_OK;
 }
 
 }  // extern "C"

@@ -181,6 +181,12 @@ void launch_cg_iteration(int W, int H, int C, const uint8_t *mask, double *u, do
 size_t voronoi_scratch_ints(int W, int H);
 void launch_voronoi_labels(int W, int H, const uint8_t *mask, int *scratch, int *labels, hipStream_t s);
 
+// densify_step with a jump-flooding start step (0: the default) when the
+// partition carries HDI_PART_JFA, and the largest squared pixel-to-label
+// distance of the labels it used (host, nullable).
+int32_t densify_step_ex(int W, int H, uint8_t *mask, const float *err, long long n_add, int partition, int jfa_k0,
+                        int32_t *added, int64_t *n_added, uint64_t *max_d2, void *ws, size_t ws_bytes, hipStream_t s);
+
 // Coarse masks, known counts and the number of levels for a new mask.
 int32_t prepare_mask(Hierarchy &h, hipStream_t s);
 

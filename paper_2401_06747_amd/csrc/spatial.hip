@@ -198,7 +198,7 @@ int32_t spatial_optimize(hdi_image img, const float *f, const double *rand, cons
     const hdi_spatial_params &P = *params;
     const long long N = (long long)img.width * img.height;
     if (!(P.density > 0.0 && P.density <= 1.0) || P.n_steps < 1 || P.n_steps > 10000 || !(P.t > 0.0) ||
-        (P.partition != HDI_PART_DELAUNAY && P.partition != HDI_PART_VORONOI)) {
+        ((P.partition & ~HDI_PART_JFA) != HDI_PART_DELAUNAY && (P.partition & ~HDI_PART_JFA) != HDI_PART_VORONOI)) {
         set_error("spatial parameters out of range (0 < density <= 1, 1 <= n_steps <= 10000, t > 0, partition)");
         return HDI_ERR_ARG;
     }
@@ -244,6 +244,7 @@ int32_t spatial_optimize(hdi_image img, const float *f, const double *rand, cons
     std::vector<uint8_t> h_mask;
     std::vector<float> h_err;
     std::vector<int32_t> h_added;
+    int jfa_k0 = 0;   // jump-flooding start of the next step (0: the default)
     for (int k = 0; k < P.n_steps; ++k) {
         st = hdi_error_map(img, cur, f, w.err, stream);
         if (st) return st;
@@ -257,9 +258,15 @@ int32_t spatial_optimize(hdi_image img, const float *f, const double *rand, cons
             S_TRY(hipStreamSynchronize(s));
         }
         int64_t n_added = 0;
-        st = densify_step(img.width, img.height, mask, w.err, want, P.partition, w.added, &n_added, w.dens,
-                          w.dens_bytes, stream);
+        uint64_t max_d2 = 0;
+        st = densify_step_ex(img.width, img.height, mask, w.err, want, P.partition, jfa_k0, w.added, &n_added,
+                             (P.partition & HDI_PART_JFA) ? &max_d2 : nullptr, w.dens, w.dens_bytes, s);
         if (st) return st;
+        if (P.partition & HDI_PART_JFA) {
+            // the mask only grows, so this step's largest distance bounds the next
+            jfa_k0 = 1;
+            while ((uint64_t)jfa_k0 * jfa_k0 < max_d2) jfa_k0 *= 2;
+        }
         count += n_added;
         if (hook) {
             h_added.resize(std::max<int64_t>(n_added, 1));

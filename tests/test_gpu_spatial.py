@@ -82,6 +82,6 @@ def test_error_maps_are_the_solutions_errors():
 def test_errors():
     f, r, ft, rt = _inputs(20, 30, 1, 9)
     for kw in ({"density": 0.0}, {"density": 1.5}, {"density": 0.1, "n_steps": 0}, {"density": 0.1, "t": 0.0},
-               {"density": 0.1, "partition": 5}):
+               {"density": 0.1, "partition": 2}, {"density": 0.1, "partition": 8}):
         with pytest.raises(hdi.HdiError):
             hdi.spatial_optimize(ft, rt, **kw)
