@@ -468,7 +468,10 @@ int64_t hdi_block_count(int32_t width, int32_t height, int32_t overlap);
  * device time in ms, the algorithmic bytes those launches must move (every
  * input element read once, every output element written once) and the
  * algorithmic floating-point operations of the block solvers (15 per pixel and
- * local CG step: stencil 5, two dot products 4, three vector updates 6). */
+ * local CG step: stencil 5, two dot products 4, three vector updates 6; 20 per
+ * pixel and local CGNR step of the tonal sweep). The tonal RAS sweep counts the
+ * local steps it actually takes (a local CG stops at its FP32 residual floor);
+ * the Schwarz smoother's figure assumes every configured step (an upper bound). */
 #define HDI_NUM_KERNEL_IDS 8
 void hdi_stats_enable(int32_t on);
 void hdi_stats_reset(void);

@@ -102,6 +102,10 @@ struct Prof {
     void begin(int id, double bytes, hipStream_t s, double flops = 0.0);
     void end(hipStream_t s);
     void flush();   // accumulate into the global counters and free the events
+    // FLOPs of the last ended record, when they are known only after the launch
+    void set_last_flops(double flops) {
+        if (on && n > 0) recs[n - 1].flops = flops;
+    }
 };
 Prof *prof_for_call();   // nullptr when timing is off
 

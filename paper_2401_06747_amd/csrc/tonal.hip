@@ -35,7 +35,8 @@ void launch_dots(int m, int C, int np, const double *const *a, const double *con
                  double *sums, hipStream_t s);
 void launch_axpby(int m, int C, const double *a, const double *b, const double *x, double *y, hipStream_t s);
 void launch_ras_local(int W, int H, int C, int m, int overlap, int nc, int ni, const uint8_t *mask, const int *pos,
-                      const double *r, double *z, hipStream_t s);
+                      const double *r, double *z, unsigned int *steps, hipStream_t s);
+void launch_sum_steps(int n, const unsigned int *steps, unsigned long long *totals, hipStream_t s);
 bool check_image(const hdi_image &img);
 int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap);
 
@@ -60,6 +61,8 @@ struct TonalWs {
     double *img_d, *uB, *wA, *rho;                 // full images C x N
     double *ug, *wr;                               // B g and L_UU^{-1} rho_U (running estimates)
     double *partials, *sums;                      // reductions
+    unsigned int *ras_steps;                      // per-wave step counts of a RAS sweep (statistics)
+    unsigned long long *ras_totals;
 };
 
 static bool plan_tonal(TonalWs &t, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask,
@@ -78,6 +81,10 @@ static bool plan_tonal(TonalWs &t, Arena &a, int W, int H, int C, int overlap, c
     for (double **v : imgs) *v = (double *)a.take(N * C * sizeof(double));
     t.partials = (double *)a.take(12 * 512 * sizeof(double));
     t.sums = (double *)a.take(16 * sizeof(double));
+    // sized for the narrowest block stride (overlap 16)
+    const size_t nwaves = (size_t)make_blocks(W, 16).count * make_blocks(H, 16).count * C;
+    t.ras_steps = (unsigned int *)a.take(nwaves * sizeof(unsigned int));
+    t.ras_totals = (unsigned long long *)a.take(2 * sizeof(unsigned long long));
     return a.base == nullptr || a.used <= a.size;
 }
 
@@ -247,18 +254,31 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
                 : std::min(1e-3, std::max(tight, fac * tc.rel_tol / std::max(rmin, 1e-300)));
 
         const Blocks1D tbx = make_blocks(X.W, tc.overlap), tby = make_blocks(X.H, tc.overlap);
-        const double ras_px = (double)tbx.count * tby.count * std::min(32, X.W) * std::min(32, X.H) * C;
-        // per local CGNR step: two local inpaintings of local_inner CG steps
-        const double ras_flops = ras_px * tc.local_outer * (2.0 * tc.local_inner * 15.0 + 20.0);
+        const double block_px = (double)std::min(32, X.W) * std::min(32, X.H);
         const double ras_bytes = (double)X.N * 5.0 + 16.0 * C * m;   // mask + pos, r in, z out
-        auto ras_sweep = [&]() {
-            if (X.prof) X.prof->begin(6, ras_bytes, s, ras_flops);
-            launch_ras_local(X.W, X.H, C, m, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK, t.zK, s);
-            if (X.prof) X.prof->end(s);
+        auto ras_sweep = [&]() -> int32_t {
+            if (!X.prof) {
+                launch_ras_local(X.W, X.H, C, m, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK,
+                                 t.zK, nullptr, s);
+                return HDI_OK;
+            }
+            // timed: the FLOPs are those of the local steps actually taken (a
+            // local CG stops early at its FP32 residual floor): 15 per block
+            // pixel and local CG step, 20 per block pixel and local CGNR step
+            X.prof->begin(6, ras_bytes, s, 0.0);
+            launch_ras_local(X.W, X.H, C, m, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK, t.zK,
+                             t.ras_steps, s);
+            X.prof->end(s);
+            launch_sum_steps(tbx.count * tby.count * C, t.ras_steps, t.ras_totals, s);
+            unsigned long long tot[2] = {0, 0};
+            T_TRY(hipMemcpyAsync(tot, t.ras_totals, sizeof tot, hipMemcpyDeviceToHost, s));
+            T_TRY(hipStreamSynchronize(s));
+            X.prof->set_last_flops(block_px * (15.0 * (double)tot[0] + 20.0 * (double)tot[1]));
+            return HDI_OK;
         };
         if (tc.mode == HDI_TONAL_RAS) {
             // Alg. 2: local corrections, then the global residual with warm starts
-            ras_sweep();
+            T_ST(ras_sweep());
             const double one[3] = {1, 1, 1}, om[3] = {omega, omega, omega};
             launch_axpby(m, C, om, one, t.zK, t.gK, s);
             ++it;
@@ -278,7 +298,7 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             // flexible CG (Notay's FCG with one stored direction)
             const double *z = t.rK;
             if (tc.mode == HDI_TONAL_PCG_RAS) {
-                ras_sweep();
+                T_ST(ras_sweep());
                 z = t.zK;
             }
             double beta[3] = {0, 0, 0};

@@ -286,9 +286,10 @@ struct LocalTile {
     }
 };
 
-// x = (L_UU of the block)^{-1} b by `iters` CG steps from 0; b and x are zero
-// off U. dg[k] = block-graph degree on U pixels, 0 elsewhere.
-__device__ __forceinline__ void local_cg(LocalTile &T, const float *dg, const float *b, float *x, int iters) {
+// x = (L_UU of the block)^{-1} b by `iters` CG steps from 0 (fewer once the
+// residual reaches the FP32 floor); b and x are zero off U. dg[k] = block-graph
+// degree on U pixels, 0 elsewhere. Returns the steps taken.
+__device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const float *b, float *x, int iters) {
     float r[16], p[16], q[16];
     float rr = 0.f;
 #pragma unroll
@@ -300,7 +301,8 @@ __device__ __forceinline__ void local_cg(LocalTile &T, const float *dg, const fl
     }
     rr = t_wave_sum(rr);
     const float floor_rr = rr * 1e-14f;
-    for (int it = 0; it < iters && rr > floor_rr && rr >= FLT_MIN; ++it) {
+    int it = 0;
+    for (; it < iters && rr > floor_rr && rr >= FLT_MIN; ++it) {
         T.nbsum(p, q);
         float pq = 0.f;
 #pragma unroll
@@ -324,11 +326,13 @@ __device__ __forceinline__ void local_cg(LocalTile &T, const float *dg, const fl
 #pragma unroll
         for (int k = 0; k < 16; ++k) p[k] = r[k] + beta * p[k];
     }
+    return it;
 }
 
 __global__ void __launch_bounds__(64)
 k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int ni, const uint8_t *__restrict__ mask,
-            const int *__restrict__ pos, const double *__restrict__ r, double *__restrict__ z) {
+            const int *__restrict__ pos, const double *__restrict__ r, double *__restrict__ z,
+            unsigned int *__restrict__ steps) {
     __shared__ __attribute__((aligned(16))) float s_x[TT + 2][TLDS_W];
     __shared__ __attribute__((aligned(16))) float s_t[TT][TT];   // t = B_i p between the two local solves
     const int ntiles = ntx * nty;
@@ -378,13 +382,14 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
 #pragma unroll
     for (int k = 0; k < 16; ++k) { v[k] = 0.f; p[k] = s[k]; }
     const float floor_ss = ss * 1e-14f;
+    int n_local = 0, n_outer = 0;   // steps taken (counted for the FLOP statistics)
     for (int it = 0; it < nc && ss > floor_ss && ss >= FLT_MIN; ++it) {
         float tmp[16], u[16];
         // t = B_i p: p on K, inpainted values on U
         T.nbsum(p, tmp);
 #pragma unroll
         for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tmp[k] : 0.f;
-        local_cg(T, dgU, tmp, u, ni);
+        n_local += local_cg(T, dgU, tmp, u, ni);
         // t is parked in LDS (the lane's own 4x4) while the second solve runs
 #pragma unroll
         for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] == 0.f ? p[k] : u[k];
@@ -395,7 +400,8 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
         // q = B_i^T t = t_K + sum over unknown neighbours of (L_UU^{-1} t_U)
 #pragma unroll
         for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tmp[k] : 0.f;
-        local_cg(T, dgU, tmp, u, ni);
+        n_local += local_cg(T, dgU, tmp, u, ni);
+        ++n_outer;
         T.nbsum(u, tmp);
         float pq = 0.f;
 #pragma unroll
@@ -426,6 +432,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
         for (int k = 0; k < 16; ++k) p[k] = s[k] + beta * p[k];
     }
 
+    if (steps && lane == 0) steps[blockIdx.y * gridDim.x + blockIdx.x] = ((unsigned)n_local << 8) | (unsigned)n_outer;
     // restricted write-back on owned mask pixels
     const int xlo = tx == 0 ? 0 : (min((tx - 1) * sx, W - Tx) + Tx + x0) / 2;
     const int xhi = tx == ntx - 1 ? W : (x0 + Tx + min((tx + 1) * sx, W - Tx)) / 2;
@@ -499,11 +506,46 @@ void launch_axpby(int m, int C, const double *a, const double *b, const double *
 }
 
 void launch_ras_local(int W, int H, int C, int m, int overlap, int nc, int ni, const uint8_t *mask, const int *pos,
-                      const double *r, double *z, hipStream_t s) {
+                      const double *r, double *z, unsigned int *steps, hipStream_t s) {
     const Blocks1D bx = make_blocks(W, overlap), by = make_blocks(H, overlap);
     dim3 g(bx.count * by.count, C);
     hipLaunchKernelGGL(k_ras_local, g, dim3(64), 0, s, W, H, m, bx.count, by.count, bx.stride, by.stride, nc, ni,
-                       mask, pos, r, z);
+                       mask, pos, r, z, steps);
+}
+
+// totals[0] += local CG steps, totals[1] += local CGNR steps over the n
+// per-wave counts of a sweep (integer sums: exact in any order)
+__global__ void k_sum_steps(int n, const unsigned int *__restrict__ steps, unsigned long long *__restrict__ totals) {
+    unsigned long long a = 0, b = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        a += steps[i] >> 8;
+        b += steps[i] & 0xFF;
+    }
+    __shared__ unsigned long long sa[256], sb[256];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(totals, sa[0]);
+        atomicAdd(totals + 1, sb[0]);
+    }
+}
+
+__global__ void k_zero_totals(int n, unsigned long long *__restrict__ p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+void launch_sum_steps(int n, const unsigned int *steps, unsigned long long *totals, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_totals, dim3(1), dim3(64), 0, s, 2, totals);
+    hipLaunchKernelGGL(k_sum_steps, dim3(64), dim3(256), 0, s, n, steps, totals);
 }
 
 }  // namespace hdi
