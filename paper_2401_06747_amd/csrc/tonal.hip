@@ -190,7 +190,7 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
     TonalWs &t = X.t;
     const int C = X.C, m = X.m;
     hipStream_t s = X.s;
-    const double tight = std::min(1e-10, 1e-4 * tc.rel_tol);
+    const double tight = std::min(1e-9, 1e-3 * tc.rel_tol);
 
     // ||B^T f|| (the scale of the relative normal residual)
     double bnorm[3], sse[3], r0[3], rel[3] = {0, 0, 0};
