@@ -8,46 +8,9 @@
 #include <cfloat>
 
 #include "hdi_internal.h"
+#include "wave.h"
 
 namespace hdi {
-
-// ------------------------------------------------------------------ helpers (local copies)
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int t_dpp_i(int x) {
-    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xF, false);
-}
-__device__ __forceinline__ float t_wave_sum(float v) {
-    v += __int_as_float(t_dpp_i<0xB1, 0xF>(__float_as_int(v)));
-    v += __int_as_float(t_dpp_i<0x4E, 0xF>(__float_as_int(v)));
-    v += __int_as_float(t_dpp_i<0x114, 0xF>(__float_as_int(v)));
-    v += __int_as_float(t_dpp_i<0x118, 0xF>(__float_as_int(v)));
-    v += __int_as_float(t_dpp_i<0x142, 0xA>(__float_as_int(v)));
-    v += __int_as_float(t_dpp_i<0x143, 0xC>(__float_as_int(v)));
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double t_dpp_d(double x) {
-    const int lo = t_dpp_i<CTRL, ROWS>(__double2loint(x));
-    const int hi = t_dpp_i<CTRL, ROWS>(__double2hiint(x));
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double t_wave_sum_d(double v) {
-    v += t_dpp_d<0xB1, 0xF>(v);
-    v += t_dpp_d<0x4E, 0xF>(v);
-    v += t_dpp_d<0x114, 0xF>(v);
-    v += t_dpp_d<0x118, 0xF>(v);
-    v += t_dpp_d<0x142, 0xA>(v);
-    v += t_dpp_d<0x143, 0xC>(v);
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ int t_xcd_remap(int bid, int n) {
-    const int q = n >> 3, rem = n & 7;
-    const int x = bid & 7, k = bid >> 3;
-    return x * q + min(x, rem) + k;
-}
 
 // ------------------------------------------------------------------ mask compaction
 
@@ -172,7 +135,7 @@ k_image_residual(int N, int C, const float *__restrict__ f, const double *__rest
         }
     __shared__ double s[4][3];
     for (int c = 0; c < C; ++c) {
-        const double a = t_wave_sum_d(acc[c]);
+        const double a = wave_sum_d(acc[c]);
         if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6][c] = a;
     }
     __syncthreads();
@@ -200,7 +163,7 @@ k_dots(int m, int C, int np, DotArgs args, double *__restrict__ partials, int nb
     __shared__ double s[4][12];
     for (int q = 0; q < np; ++q)
         for (int c = 0; c < C; ++c) {
-            const double v = t_wave_sum_d(acc[q][c]);
+            const double v = wave_sum_d(acc[q][c]);
             if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6][q * 3 + c] = v;
         }
     __syncthreads();
@@ -220,7 +183,7 @@ __global__ void k_sum_rows(int nk, int nblk, const double *__restrict__ partials
     if (k >= nk) return;
     double a = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 64) a += partials[(size_t)k * nblk + b];
-    a = t_wave_sum_d(a);
+    a = wave_sum_d(a);
     if (threadIdx.x == 0) out[k] = a;
 }
 
@@ -299,7 +262,7 @@ __device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const flo
         p[k] = b[k];
         rr += b[k] * b[k];
     }
-    rr = t_wave_sum(rr);
+    rr = wave_sum(rr);
     const float floor_rr = rr * 1e-14f;
     int it = 0;
     for (; it < iters && rr > floor_rr && rr >= FLT_MIN; ++it) {
@@ -310,7 +273,7 @@ __device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const flo
             q[k] = dg[k] > 0.f ? dg[k] * p[k] - q[k] : 0.f;
             pq += p[k] * q[k];
         }
-        pq = t_wave_sum(pq);
+        pq = wave_sum(pq);
         if (!(pq >= FLT_MIN)) break;
         const float alpha = rr * __builtin_amdgcn_rcpf(pq);
         float rr2 = 0.f;
@@ -320,7 +283,7 @@ __device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const flo
             r[k] -= alpha * q[k];
             rr2 += r[k] * r[k];
         }
-        rr2 = t_wave_sum(rr2);
+        rr2 = wave_sum(rr2);
         const float beta = rr2 * __builtin_amdgcn_rcpf(rr);
         rr = rr2;
 #pragma unroll
@@ -336,7 +299,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
     __shared__ __attribute__((aligned(16))) float s_x[TT + 2][TLDS_W];
     __shared__ __attribute__((aligned(16))) float s_t[TT][TT];   // t = B_i p between the two local solves
     const int ntiles = ntx * nty;
-    const int t = t_xcd_remap(blockIdx.x, ntiles);
+    const int t = xcd_remap(blockIdx.x, ntiles);
     const int c = blockIdx.y;
     const int tx = t % ntx, ty = t / ntx;
     const int Tx = min(TT, W), Ty = min(TT, H);
@@ -375,7 +338,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
             s[k] = known ? (float)r[(size_t)c * m + pk[k]] : 0.f;
             ss += s[k] * s[k];
         }
-    ss = t_wave_sum(ss);
+    ss = wave_sum(ss);
 
     // local CGNR on the mask pixels of the block
     float v[16], p[16];
@@ -415,7 +378,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
                 pq += p[k] * tmp[k];
             }
         }
-        pq = t_wave_sum(pq);
+        pq = wave_sum(pq);
         if (!(pq >= FLT_MIN)) break;
         const float alpha = ss * __builtin_amdgcn_rcpf(pq);
         float ss2 = 0.f;
@@ -425,7 +388,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
             s[k] -= alpha * tmp[k];
             ss2 += s[k] * s[k];
         }
-        ss2 = t_wave_sum(ss2);
+        ss2 = wave_sum(ss2);
         const float beta = ss2 * __builtin_amdgcn_rcpf(ss);
         ss = ss2;
 #pragma unroll
