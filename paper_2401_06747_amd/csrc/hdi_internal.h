@@ -74,6 +74,9 @@ struct Hierarchy {
     // two search directions) aliasing the multigrid buffers (a solve uses one
     // method or the other), its block partial sums and scalars
     double *cg_r, *cg_p[2], *cg_part, *cg_scal;
+    // set once a solve has handed its u_alt buffer to the caller (the region
+    // the CG vectors alias then holds the caller's data)
+    bool u_alt_moved = false;
 };
 constexpr int CG_BLOCKS = 1024;   // workgroups of the CG kernels (grid-stride)
 
@@ -195,9 +198,13 @@ int32_t densify_step_ex(int W, int H, uint8_t *mask, const float *err, long long
 int32_t prepare_mask(Hierarchy &h, hipStream_t s);
 
 // Host driver: solve A x = C data + (I - C) src on the caller's buffers.
+// swap: optional address of the caller's pointer to u. When the refinement ends
+// in the workspace copy, the two buffers trade places (*swap and h.u_alt are
+// exchanged) instead of copying the result back; then no CG solve may follow
+// on this hierarchy.
 template <typename TD>
 int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, const TD *data,
                      const double *src, double *u, bool warm, const SolveCfg &cfg,
-                     hdi_solve_report *rep, hipStream_t s, Prof *prof = nullptr);
+                     hdi_solve_report *rep, hipStream_t s, Prof *prof = nullptr, double **swap = nullptr);
 
 }  // namespace hdi

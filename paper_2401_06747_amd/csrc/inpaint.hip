@@ -237,7 +237,8 @@ static int32_t solve_cg(Hierarchy &h, int W, int H, int C, const uint8_t *mask, 
 
 template <typename TD>
 int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, const TD *data, const double *src,
-                     double *u, bool warm, const SolveCfg &cfg, hdi_solve_report *rep, hipStream_t s, Prof *prof) {
+                     double *u, bool warm, const SolveCfg &cfg, hdi_solve_report *rep, hipStream_t s, Prof *prof,
+                     double **swap) {
     if ((data == nullptr) == (src == nullptr)) {
         set_error("internal: a solve takes either data on the mask or a source off it");
         return HDI_ERR_ARG;
@@ -247,6 +248,10 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipEventRecord(ev0, s));
     if (cfg.flags & HDI_FLAG_CG) {
+        if (h.u_alt_moved) {
+            set_error("internal: a CG solve after a multigrid solve handed over its buffer");
+            return HDI_ERR_ARG;
+        }
         launch_init_u<TD>(W, H, C, mask, data, warm ? u : nullptr, u, s);
         double rel[3] = {0, 0, 0};
         int steps = 0;
@@ -316,7 +321,15 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         ++rounds;
         ++vcycles;
     }
-    if (cur != u) HIP_TRY(hipMemcpyAsync(u, cur, sizeof(double) * C * W * H, hipMemcpyDeviceToDevice, s));
+    if (cur != u) {
+        if (swap && *swap == u) {
+            *swap = cur;
+            h.u_alt = u;
+            h.u_alt_moved = true;
+        } else {
+            HIP_TRY(hipMemcpyAsync(u, cur, sizeof(double) * C * W * H, hipMemcpyDeviceToDevice, s));
+        }
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(ev1, s));
     HIP_TRY(hipEventSynchronize(ev1));
@@ -335,9 +348,11 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
 }
 
 template int32_t solve_system<float>(Hierarchy &, int, int, int, const uint8_t *, const float *, const double *,
-                                     double *, bool, const SolveCfg &, hdi_solve_report *, hipStream_t, Prof *);
+                                     double *, bool, const SolveCfg &, hdi_solve_report *, hipStream_t, Prof *,
+                                     double **);
 template int32_t solve_system<double>(Hierarchy &, int, int, int, const uint8_t *, const double *, const double *,
-                                      double *, bool, const SolveCfg &, hdi_solve_report *, hipStream_t, Prof *);
+                                      double *, bool, const SolveCfg &, hdi_solve_report *, hipStream_t, Prof *,
+                                      double **);
 
 bool check_image(const hdi_image &img) {
     if (img.width < 1 || img.height < 1 || (img.channels != 1 && img.channels != 3)) {

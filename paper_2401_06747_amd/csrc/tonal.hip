@@ -106,12 +106,14 @@ struct TonalCtx {
     int solves = 0, vcycles = 0;
 
     // u = B x for x given on K (compact); cold start with FMG unless warm.
-    int32_t apply_B(const double *xK, double *u, bool warm, double tol) {
+    // u: a workspace buffer, which may trade places with the hierarchy's
+    // second iterate buffer instead of receiving a copy
+    int32_t apply_B(const double *xK, double *&u, bool warm, double tol) {
         launch_scatter_K(m, C, N, t.idx, xK, t.img_d, s);
         SolveCfg c = inner;
         c.rel_tol = tol;
         hdi_solve_report rep;
-        int32_t st = solve_system<double>(t.h, W, H, C, mask, t.img_d, nullptr, u, warm, c, &rep, s, prof);
+        int32_t st = solve_system<double>(t.h, W, H, C, mask, t.img_d, nullptr, u, warm, c, &rep, s, prof, &u);
         if (st) set_error("inner B solve (tol %.1e, warm %d): %s", tol, (int)warm, hdi_last_error());
         ++solves;
         vcycles += (c.flags & HDI_FLAG_CG) ? rep.outer_iters : rep.vcycles;
@@ -121,11 +123,12 @@ struct TonalCtx {
     // y is null): w solves L_UU w = y_U (source problem, zero data), in the
     // buffer w (warm-started from its contents when warm).
     int32_t apply_Bt(const double *y, const double *yK, const double *ysrc, double *out, bool warm, double tol,
-                     double *w) {
+                     double *&w) {
         SolveCfg c = inner;
         c.rel_tol = tol;
         hdi_solve_report rep;
-        int32_t st = solve_system<double>(t.h, W, H, C, mask, (const double *)nullptr, ysrc, w, warm, c, &rep, s, prof);
+        int32_t st =
+            solve_system<double>(t.h, W, H, C, mask, (const double *)nullptr, ysrc, w, warm, c, &rep, s, prof, &w);
         if (st) set_error("inner B^T solve (tol %.1e, warm %d): %s", tol, (int)warm, hdi_last_error());
         ++solves;
         vcycles += (c.flags & HDI_FLAG_CG) ? rep.outer_iters : rep.vcycles;

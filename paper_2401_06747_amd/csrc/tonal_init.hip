@@ -343,7 +343,7 @@ int32_t voronoi_init(hdi_image img, const uint8_t *mask, const float *f, double 
     int solves = 0, steps = 0, best = 0;
     double trace[HDI_VINIT_TRACE] = {};
     double mse_prev = 0.0, mse = 0.0;
-    st = solve_system<double>(v.h, W, H, C, mask, gc, nullptr, uc, false, cfg, nullptr, s);
+    st = solve_system<double>(v.h, W, H, C, mask, gc, nullptr, uc, false, cfg, nullptr, s, nullptr, &uc);
     ++solves;
     if (st == HDI_OK) st = X.scan(uc, mse);
     if (st == HDI_OK) {
@@ -356,7 +356,7 @@ int32_t voronoi_init(hdi_image img, const uint8_t *mask, const float *f, double 
                 hipLaunchKernelGGL(k_vi_update<false>, gd(N), dim3(256), 0, s, W, H, C, tau, mask, f, uc, v.acc, gc,
                                    gn);
             V_TRY(hipMemcpyAsync(un, uc, bytes, hipMemcpyDeviceToDevice, s));   // warm start
-            st = solve_system<double>(v.h, W, H, C, mask, gn, nullptr, un, true, cfg, nullptr, s);
+            st = solve_system<double>(v.h, W, H, C, mask, gn, nullptr, un, true, cfg, nullptr, s, nullptr, &un);
             ++solves;
             if (st == HDI_OK) {
                 mse_prev = mse;

@@ -5,6 +5,7 @@
 // order. B g = A^{-1} C g is an inpainting solve; B^T y, by the symmetrised
 // form of Sec. 5.1, is y_k + sum_{j in N4(k), j unknown} w_j with
 // L_UU w_U = y_U (an inpainting solve with a source term and zero data).
+#include <algorithm>
 #include <cfloat>
 
 #include "hdi_internal.h"
@@ -152,22 +153,29 @@ k_image_residual(int N, int C, const float *__restrict__ f, const double *__rest
 // q < np; partials[q][c][blk]. Fixed grid => fixed summation order.
 struct DotArgs { const double *a[4]; const double *b[4]; };
 
+template <int NP, int C>
 __global__ void __launch_bounds__(256)
-k_dots(int m, int C, int np, DotArgs args, double *__restrict__ partials, int nblk) {
-    double acc[4][3];
-    for (int q = 0; q < 4; ++q)
-        for (int c = 0; c < 3; ++c) acc[q][c] = 0.0;
+k_dots(int m, DotArgs args, double *__restrict__ partials, int nblk) {
+    double acc[NP][C];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[q][c] = 0.0;
     for (int j = blockIdx.x * 256 + threadIdx.x; j < m; j += nblk * 256)
-        for (int q = 0; q < np; ++q)
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+#pragma unroll
             for (int c = 0; c < C; ++c) acc[q][c] += args.a[q][(size_t)c * m + j] * args.b[q][(size_t)c * m + j];
     __shared__ double s[4][12];
-    for (int q = 0; q < np; ++q)
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
         for (int c = 0; c < C; ++c) {
             const double v = wave_sum_d(acc[q][c]);
             if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6][q * 3 + c] = v;
         }
     __syncthreads();
-    if (threadIdx.x < np * 3) {
+    if (threadIdx.x < NP * 3) {
         const int q = threadIdx.x / 3, c = threadIdx.x % 3;
         if (c < C) {
             double v = 0.0;
@@ -454,7 +462,13 @@ void launch_dots(int m, int C, int np, const double *const *a, const double *con
         args.a[q] = q < np ? a[q] : nullptr;
         args.b[q] = q < np ? b[q] : nullptr;
     }
-    hipLaunchKernelGGL(k_dots, dim3(RED_BLOCKS), dim3(256), 0, s, m, C, np, args, partials, RED_BLOCKS);
+    // one instantiation per product count (1..4) and channel count keeps the
+    // sums in registers
+    using Kern = void (*)(int, DotArgs, double *, int);
+    static const Kern k3[4] = {k_dots<1, 3>, k_dots<2, 3>, k_dots<3, 3>, k_dots<4, 3>};
+    static const Kern k1[4] = {k_dots<1, 1>, k_dots<2, 1>, k_dots<3, 1>, k_dots<4, 1>};
+    const Kern kern = (C == 3 ? k3 : k1)[std::min(std::max(np, 1), 4) - 1];
+    hipLaunchKernelGGL(kern, dim3(RED_BLOCKS), dim3(256), 0, s, m, args, partials, RED_BLOCKS);
     // sums laid out [q][3]
     hipLaunchKernelGGL(k_sum_rows, dim3(np * 3), dim3(64), 0, s, np * 3, RED_BLOCKS, partials, sums);
 }
