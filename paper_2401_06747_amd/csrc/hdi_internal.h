@@ -114,8 +114,11 @@ Prof *prof_for_call();   // nullptr when timing is off
 
 // Kernel launchers (solver_kernels.hip).
 
+// u = data (or 0) on known pixels; on unknown pixels 0, or left unchanged
+// with keep_unknown (a warm start, or before the FMG prolongation writes them)
 template <typename TD>
-void launch_init_u(int W, int H, int C, const uint8_t *mask, const TD *data, const double *u0, double *u, hipStream_t s);
+void launch_init_u(int W, int H, int C, const uint8_t *mask, const TD *data, bool keep_unknown, double *u,
+                   hipStream_t s);
 dim3 residual_grid(int W, int H);
 template <typename TD>
 void launch_residual(int W, int H, int C, const uint8_t *mask, const double *u_in, const float *e, double *u_out,

@@ -252,7 +252,7 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
             set_error("internal: a CG solve after a multigrid solve handed over its buffer");
             return HDI_ERR_ARG;
         }
-        launch_init_u<TD>(W, H, C, mask, data, warm ? u : nullptr, u, s);
+        launch_init_u<TD>(W, H, C, mask, data, warm, u, s);
         double rel[3] = {0, 0, 0};
         int steps = 0;
         const int32_t st = solve_cg<TD>(h, W, H, C, mask, data, src, u, cfg, rel, steps, s, prof);
@@ -274,9 +274,9 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     const double N = (double)W * H, nK = (double)cfg.known, nU = N - nK;
     (void)nU;
     if (prof) prof->begin(5, 0.0, s);
-    launch_init_u<TD>(W, H, C, mask, data, warm ? u : nullptr, u, s);
-    if (!warm && !(cfg.flags & HDI_FLAG_NO_FMG) && src == nullptr && h.nlev > 1)
-        fmg_init<TD>(h, W, H, C, mask, data, u, cfg, s);
+    const bool fmg = !warm && !(cfg.flags & HDI_FLAG_NO_FMG) && src == nullptr && h.nlev > 1;
+    launch_init_u<TD>(W, H, C, mask, data, warm || fmg, u, s);
+    if (fmg) fmg_init<TD>(h, W, H, C, mask, data, u, cfg, s);
     if (prof) prof->end(s);
     HIP_TRY(hipGetLastError());
 

@@ -28,10 +28,15 @@ __device__ __forceinline__ void init_u_at(int i, int N, int C, const uint8_t *__
     }
 }
 
+// keep_unknown: leave u on unknown pixels as it is (a warm start, or a start
+// that the FMG prolongation overwrites there), so only known pixels are touched.
 template <typename TD>
 __global__ void k_init_u(int N, int C, const uint8_t *__restrict__ mask, const TD *__restrict__ data,
-                         const double *__restrict__ u0, double *__restrict__ u) {
-    init_u_at<TD>(blockIdx.x * blockDim.x + threadIdx.x, N, C, mask, data, u0, u);
+                         bool keep_unknown, double *__restrict__ u) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (keep_unknown && !mask[i]) return;
+    init_u_at<TD>(i, N, C, mask, data, nullptr, u);
 }
 
 // Fused refinement step and FP64 residual. With e != nullptr the iterate is
@@ -714,8 +719,9 @@ void launch_mask_pyramid(const Hierarchy &h, int nlev, unsigned int *counts, hip
 }
 
 template <typename TD>
-void launch_init_u(int W, int H, int C, const uint8_t *mask, const TD *data, const double *u0, double *u, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_u<TD>, grid1((long)W * H, 256), dim3(256), 0, s, W * H, C, mask, data, u0, u);
+void launch_init_u(int W, int H, int C, const uint8_t *mask, const TD *data, bool keep_unknown, double *u,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_init_u<TD>, grid1((long)W * H, 256), dim3(256), 0, s, W * H, C, mask, data, keep_unknown, u);
 }
 
 dim3 residual_grid(int W, int H) {
@@ -803,8 +809,8 @@ void launch_fmg_prolong0(int W, int H, int C, const uint8_t *mask, const Level &
     hipLaunchKernelGGL(k_fmg_prolong0, grid1((long)W * H, 256), dim3(256), 0, s, W, H, C, mask, ec, Lc.W, Lc.H, u);
 }
 
-template void launch_init_u<float>(int, int, int, const uint8_t *, const float *, const double *, double *, hipStream_t);
-template void launch_init_u<double>(int, int, int, const uint8_t *, const double *, const double *, double *, hipStream_t);
+template void launch_init_u<float>(int, int, int, const uint8_t *, const float *, bool, double *, hipStream_t);
+template void launch_init_u<double>(int, int, int, const uint8_t *, const double *, bool, double *, hipStream_t);
 template void launch_residual<float>(int, int, int, const uint8_t *, const double *, const float *, double *,
                                      const float *, const double *, float *, double *, double *, hipStream_t);
 template void launch_residual<double>(int, int, int, const uint8_t *, const double *, const float *, double *,
