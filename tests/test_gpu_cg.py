@@ -153,3 +153,17 @@ def test_cgnr_with_cg_inpainting_reaches_the_optimum(shape, p):
     np.testing.assert_allclose(u, ot.reconstruct(g, m), rtol=0, atol=1e-6 * 255)
     assert rep["inner_vcycles"] > rep["inner_solves"]    # CG steps of the inner solves
     print(shape, rep)
+
+
+def test_4k_rgb_cg_equals_multigrid():
+    """Full size: the comparator and the multigrid method reach the same
+    solution (4K RGB, 3% mask)."""
+    inst = synth.config2()
+    ft, mt = _t(inst.f, inst.mask)
+    ucg, rcg = hdi.inpaint_solve(ft, mt, params=hdi.SolveParams(flags=CG, rel_tol=1e-8))
+    umg, rmg = hdi.inpaint_solve(ft, mt, params=hdi.SolveParams(rel_tol=1e-8))
+    assert rcg["status"] == rmg["status"] == 0
+    for c in range(3):
+        d = torch.linalg.vector_norm(ucg[c] - umg[c]) / torch.linalg.vector_norm(umg[c])
+        assert float(d) <= 1e-6, (c, float(d))
+    print("4K CG steps", rcg["outer_iters"], "multigrid rounds", rmg["outer_iters"])

@@ -143,3 +143,23 @@ def test_errors():
         hdi.voronoi_init(ft, mt, tau=-1.0)
     with pytest.raises(hdi.HdiError):     # a step size far beyond stability diverges and is caught
         hdi.voronoi_init(ft, mt, tau=1e5, max_iters=10, stop=False)
+
+
+def test_4k_rgb_full_size_properties():
+    """The paper's setting at full size (4K RGB, 5% mask): properties that hold
+    at any size, with the reconstruction recomputed by an independent solve."""
+    H, W = 2160, 3840
+    f = synth.textured_image(H, W, 3, 2, 7)
+    m = synth.gradient_mask(f, 0.05)
+    ft, mt = _t(f, m)
+    tight = hdi.SolveParams(rel_tol=1e-9)
+    g, rep, u = hdi.voronoi_init(ft, mt, solve=tight, want_u=True)
+    tr = rep["mse"]
+    assert 1 <= rep["best"] <= rep["steps"] <= 20
+    assert all(tr[i] <= tr[i - 1] for i in range(1, rep["best"] + 1)) and tr[rep["best"]] < tr[0]
+    off = mt == 0
+    assert bool((g[:, off] == 0).all())
+    mse = float(((u - ft.double()) ** 2).mean())
+    assert abs(mse - tr[rep["best"]]) <= 1e-9 * mse
+    u2, r2 = hdi.inpaint_solve(ft, mt, params=tight)   # B f, the start
+    assert abs(float(((u2 - ft.double()) ** 2).mean()) - tr[0]) <= 1e-6 * tr[0]
