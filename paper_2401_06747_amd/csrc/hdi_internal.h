@@ -78,7 +78,7 @@ struct Hierarchy {
     // the CG vectors alias then holds the caller's data)
     bool u_alt_moved = false;
 };
-constexpr int CG_BLOCKS = 1024;   // workgroups of the CG kernels (grid-stride)
+constexpr int CG_BLOCKS = 4096;   // workgroups of the CG kernels (grid-stride)
 
 // Lay out the hierarchy in the arena (base == nullptr: size query only).
 // small_from: the first level smoothed with 16x16 blocks, which use half the

@@ -959,13 +959,19 @@ k_cg_update(int W, int H, const uint8_t *__restrict__ mask, double *__restrict__
 }
 
 // One workgroup of 1024 threads per channel: fixed-order sum of the CG_BLOCKS
-// partial pairs, then the scalar step. step 0: r.r and b.b of the start
+// partial pairs (thread t takes t, t + 1024, ...), then the scalar step. step 0: r.r and b.b of the start
 // (beta = 0); 1: alpha = r.r / p.q; 2: beta = r.r_new / r.r, r.r = r.r_new.
 // A zero denominator (exact convergence) gives a zero step.
 __global__ void __launch_bounds__(1024) k_cg_scalars(int step, const double *__restrict__ part, double *__restrict__ scal) {
     const int c = blockIdx.x;
-    const double2 v = reinterpret_cast<const double2 *>(part)[(size_t)c * CG_BLOCKS + threadIdx.x];
-    const double a = wave_sum_d(v.x), b = wave_sum_d(v.y);
+    double pa = 0.0, pb = 0.0;
+#pragma unroll
+    for (int k = 0; k < CG_BLOCKS / 1024; ++k) {
+        const double2 v = reinterpret_cast<const double2 *>(part)[(size_t)c * CG_BLOCKS + k * 1024 + threadIdx.x];
+        pa += v.x;
+        pb += v.y;
+    }
+    const double a = wave_sum_d(pa), b = wave_sum_d(pb);
     __shared__ double s[16][2];
     if ((threadIdx.x & 63) == 0) { s[threadIdx.x >> 6][0] = a; s[threadIdx.x >> 6][1] = b; }
     __syncthreads();
@@ -986,7 +992,7 @@ __global__ void __launch_bounds__(1024) k_cg_scalars(int step, const double *__r
     }
 }
 
-static_assert(CG_BLOCKS == 1024, "k_cg_scalars reduces one partial per thread");
+static_assert(CG_BLOCKS % 1024 == 0, "k_cg_scalars takes CG_BLOCKS / 1024 partials per thread");
 
 template <typename TD>
 void launch_cg_start(int W, int H, int C, const uint8_t *mask, const double *u, const TD *data, const double *src,
