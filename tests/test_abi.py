@@ -81,3 +81,40 @@ def test_argument_errors_need_no_gpu():
     st = lib.inpaint_solve(L.hdi_image(4, 4, 1), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
                            None, None, 0, None, ctypes.byref(rep), None)
     assert st == L.HDI_ERR_WORKSPACE
+
+
+def test_argument_errors_of_the_later_entry_points_need_no_gpu():
+    """Voronoi initialisation, labels, jump-flooding densification, the CG flag
+    and the MSE-gain stop validate their arguments before any HIP call."""
+    import ctypes
+    L = _lib()
+    lib = L.lib()
+    dev = ctypes.c_void_p(16)          # never dereferenced: every call below fails first
+    img = L.hdi_image(8, 6, 1)
+    assert lib.hdi_vinit_workspace_bytes(L.hdi_image(0, 6, 1)) == 0
+    assert lib.hdi_vinit_workspace_bytes(img) > lib.hdi_inpaint_workspace_bytes(img)
+    assert lib.hdi_labels_workspace_bytes(0, 5) == 0 and lib.hdi_labels_workspace_bytes(8, 6) > 0
+    vrep = L.hdi_vinit_report()
+    for bad in (L.hdi_vinit_params(3, 0, 1.0, 0, L.hdi_solve_params()),        # weighting
+                L.hdi_vinit_params(2, 1001, 1.0, 0, L.hdi_solve_params()),     # max_iters
+                L.hdi_vinit_params(2, 0, -1.0, 0, L.hdi_solve_params()),       # tau
+                L.hdi_vinit_params(2, 0, 1.0, 8, L.hdi_solve_params())):       # flags
+        assert lib.voronoi_init(img, dev, dev, dev, None, dev, 1 << 30, ctypes.byref(bad), ctypes.byref(vrep),
+                                None) == L.HDI_ERR_ARG
+    assert lib.voronoi_init(img, dev, dev, None, None, dev, 1 << 30, None, ctypes.byref(vrep), None) == L.HDI_ERR_ARG
+    assert lib.voronoi_init(img, dev, dev, dev, None, dev, 16, None, ctypes.byref(vrep), None) == L.HDI_ERR_WORKSPACE
+    d2 = ctypes.c_uint64(0)
+    assert lib.hdi_voronoi_labels(8, 6, dev, dev, 3, ctypes.byref(d2), dev, 1 << 20, None) == L.HDI_ERR_ARG
+    assert lib.hdi_voronoi_labels(8, 6, dev, dev, -2, ctypes.byref(d2), dev, 1 << 20, None) == L.HDI_ERR_ARG
+    assert lib.hdi_voronoi_labels(8, 6, dev, dev, 0, ctypes.byref(d2), dev, 8, None) == L.HDI_ERR_WORKSPACE
+    n = ctypes.c_int64(0)
+    for part in (2, 8, 2 | L.HDI_PART_JFA):
+        assert lib.densify_step(8, 6, dev, dev, 1, part, None, ctypes.byref(n), dev, 1 << 20, None) == L.HDI_ERR_ARG
+    rep = L.hdi_solve_report()
+    p = L.hdi_solve_params(0.0, 0, 0, 0, 0, 8, 0)    # unknown flag bit
+    assert lib.inpaint_solve(img, dev, dev, dev, None, dev, 1 << 30, ctypes.byref(p), ctypes.byref(rep),
+                             None) == L.HDI_ERR_ARG
+    trep = L.hdi_tonal_report()
+    tp = L.hdi_tonal_params(0.0, 0, 0, 0, 0, 0, 0, L.hdi_solve_params(), 1.5)   # mse_gain >= 1
+    assert lib.tonal_optimize(img, dev, dev, dev, None, dev, 1 << 30, ctypes.byref(tp), ctypes.byref(trep),
+                              None) == L.HDI_ERR_ARG
