@@ -448,20 +448,14 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
     Arena a{(char *)ws, ws_bytes, 0};
     Engine e;
     plan_batch(e, ej, a);
-    hipEvent_t e0, e1;
-    B_TRY(hipEventCreate(&e0));
-    B_TRY(hipEventCreate(&e1));
-    B_TRY(hipEventRecord(e0, s));
+    CallTimer tm;
+    B_TRY(tm.start(s));
     std::vector<EJob *> news, ended;
     for (EJob &j : ej) news.push_back(&j);
     int32_t st = e.admit(news, ended, s);
     while (st == HDI_OK && e.running() > 0) st = e.round(ended, s);
-    B_TRY(hipEventRecord(e1, s));
-    B_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
-    B_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    B_TRY(tm.stop(s, &ms));
     if (st) return st;
     int32_t worst = HDI_OK;
     for (int i = 0; i < n; ++i) {

@@ -95,6 +95,29 @@ struct SolveCfg {
     int64_t known;   // number of known pixels (for the byte accounting)
 };
 
+// Device time of one call: the start and stop events live as long as the
+// object, so every return path releases them.
+struct CallTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t start(hipStream_t s) {
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e == hipSuccess) e = hipEventRecord(a, s);
+        return e;
+    }
+    // records the stop event, waits for it, and stores the elapsed time in *ms
+    hipError_t stop(hipStream_t s, float *ms) {
+        hipError_t e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+        return e;
+    }
+    ~CallTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 // Optional per-kernel event timing (hdi_stats_*). One Prof per call; records
 // are resolved after the call's final synchronisation.
 struct Prof {
@@ -102,6 +125,7 @@ struct Prof {
     struct Rec { int id; double bytes, flops; hipEvent_t a, b; };
     Rec recs[4096];
     int n = 0;
+    bool pending = false;   // begin() made the events of recs[n]
     void begin(int id, double bytes, hipStream_t s, double flops = 0.0);
     void end(hipStream_t s);
     void flush();   // accumulate into the global counters and free the events

@@ -27,18 +27,25 @@ static KStats g_stats[HDI_NUM_KERNEL_IDS];
 static std::atomic<int> g_stats_on{0};
 
 void Prof::begin(int id, double bytes, hipStream_t s, double flops) {
+    pending = false;
     if (!on || n >= (int)(sizeof recs / sizeof recs[0])) return;
     Rec &r = recs[n];
     r.id = id;
     r.bytes = bytes;
     r.flops = flops;
-    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    if (hipEventCreate(&r.a) != hipSuccess) return;
+    if (hipEventCreate(&r.b) != hipSuccess) {
+        (void)hipEventDestroy(r.a);
+        return;
+    }
     (void)hipEventRecord(r.a, s);
+    pending = true;
 }
 void Prof::end(hipStream_t s) {
-    if (!on || n >= (int)(sizeof recs / sizeof recs[0])) return;
+    if (!pending) return;   // timing off, full, or the events could not be made
     (void)hipEventRecord(recs[n].b, s);
     ++n;
+    pending = false;
 }
 void Prof::flush() {
     std::lock_guard<std::mutex> lk(g_stats_mu);
@@ -243,10 +250,8 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         set_error("internal: a solve takes either data on the mask or a source off it");
         return HDI_ERR_ARG;
     }
-    hipEvent_t ev0, ev1;
-    HIP_TRY(hipEventCreate(&ev0));
-    HIP_TRY(hipEventCreate(&ev1));
-    HIP_TRY(hipEventRecord(ev0, s));
+    CallTimer tm;
+    HIP_TRY(tm.start(s));
     if (cfg.flags & HDI_FLAG_CG) {
         if (h.u_alt_moved) {
             set_error("internal: a CG solve after a multigrid solve handed over its buffer");
@@ -256,12 +261,8 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         double rel[3] = {0, 0, 0};
         int steps = 0;
         const int32_t st = solve_cg<TD>(h, W, H, C, mask, data, src, u, cfg, rel, steps, s, prof);
-        HIP_TRY(hipEventRecord(ev1, s));
-        HIP_TRY(hipEventSynchronize(ev1));
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
+        HIP_TRY(tm.stop(s, &ms));
         if (prof) prof->flush();
         if (rep) {
             for (int c = 0; c < 3; ++c) rep->rel_residual[c] = c < C ? rel[c] : 0.0;
@@ -331,12 +332,8 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         }
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(ev1, s));
-    HIP_TRY(hipEventSynchronize(ev1));
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
+    HIP_TRY(tm.stop(s, &ms));
     if (prof) prof->flush();
     if (rep) {
         for (int c = 0; c < 3; ++c) rep->rel_residual[c] = c < C ? rel[c] : 0.0;

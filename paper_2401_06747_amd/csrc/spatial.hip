@@ -220,10 +220,8 @@ int32_t spatial_optimize(hdi_image img, const float *f, const double *rand, cons
     Arena a{(char *)ws, ws_bytes, 0};
     plan_spatial(w, a, img, u == nullptr);
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    S_TRY(hipEventCreate(&e0));
-    S_TRY(hipEventCreate(&e1));
-    S_TRY(hipEventRecord(e0, s));
+    CallTimer tm;
+    S_TRY(tm.start(s));
 
     long long count = 0;
     int32_t st = init_mask(img.width, img.height, img.channels, f, rand, n0, mask, w.lap, w.sums, &count, s);
@@ -280,12 +278,8 @@ int32_t spatial_optimize(hdi_image img, const float *f, const double *rand, cons
         if (st) return st;
     }
     if (u && cur != u) S_TRY(hipMemcpyAsync(u, cur, sizeof(double) * Nz * img.channels, hipMemcpyDeviceToDevice, s));
-    S_TRY(hipEventRecord(e1, s));
-    S_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
-    S_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    S_TRY(tm.stop(s, &ms));
     if (report) {
         report->initial_count = c0;
         report->final_count = count;

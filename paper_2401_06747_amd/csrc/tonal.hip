@@ -483,10 +483,8 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
         return HDI_ERR_WORKSPACE;
     }
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    T_TRY(hipEventCreate(&e0));
-    T_TRY(hipEventCreate(&e1));
-    T_TRY(hipEventRecord(e0, s));
+    CallTimer tm;
+    T_TRY(tm.start(s));
     Arena a{(char *)ws, ws_bytes, 0};
     TonalWs t;
     plan_tonal(t, a, img.width, img.height, img.channels, ov_inner, mask, inner.small_from);
@@ -512,12 +510,8 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
         prof->flush();
         delete prof;
     }
-    T_TRY(hipEventRecord(e1, s));
-    T_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
-    T_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    T_TRY(tm.stop(s, &ms));
     if (report) report->ms = ms;
     return st;
 }

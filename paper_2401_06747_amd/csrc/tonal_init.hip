@@ -314,10 +314,8 @@ int32_t voronoi_init(hdi_image img, const uint8_t *mask, const float *f, double 
         return HDI_ERR_WORKSPACE;
     }
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    V_TRY(hipEventCreate(&e0));
-    V_TRY(hipEventCreate(&e1));
-    V_TRY(hipEventRecord(e0, s));
+    CallTimer tm;
+    V_TRY(tm.start(s));
     Arena a{(char *)ws, ws_bytes, 0};
     VinitWs v;
     plan_vinit(v, a, W, H, C, overlap, mask, cfg.small_from);
@@ -376,12 +374,8 @@ int32_t voronoi_init(hdi_image img, const uint8_t *mask, const float *f, double 
         if (u) V_TRY(hipMemcpyAsync(u, uc, bytes, hipMemcpyDeviceToDevice, s));
     }
     V_TRY(hipGetLastError());
-    V_TRY(hipEventRecord(e1, s));
-    V_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
-    V_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    V_TRY(tm.stop(s, &ms));
     if (report) {
         report->steps = steps;
         report->best = best;
