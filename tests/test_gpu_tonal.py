@@ -200,3 +200,14 @@ def test_mse_gain_out_of_range():
     mt = torch.tensor(m, dtype=torch.uint8, device=DEV).contiguous()
     with pytest.raises(hdi.HdiError):
         hdi.tonal_optimize(ft, mt, params=hdi.TonalParams(mse_gain=1.5))
+
+
+@pytest.mark.parametrize("density,C", [(0.005, 1), (0.15, 3)])
+def test_density_range_ends(density, C):
+    """The ends of the paper's density range (0.5% and 15%, Sec. 6.3) reach the
+    oracle's optimum with the default method."""
+    f = synth.textured_image(270, 480, C, 5, 33 + C)
+    m = synth.gradient_mask(f, density)
+    g, rep, u = _run(f, m, rel_tol=1e-7, max_outer=400)
+    _check(f, m, g, rep, u, tol=1e-7)
+    print("density", density, rep)
