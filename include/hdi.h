@@ -169,8 +169,9 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
  *                paper proposes with CGNR (Sec. 5.1) and uses in its
  *                comparisons with 1e-3 (Sec. 6.3). The MSE is the running
  *                estimate ||f - B g||^2 / (C N) of the Krylov modes (the
- *                evaluated one for stationary RAS); the report holds the final
- *                values recomputed with tight solves. 0: off (default)     */
+ *                evaluated one for stationary RAS, which undoes a last step
+ *                that raised it); the report holds the final values
+ *                recomputed with tight solves. 0: off (default)            */
 typedef struct {
     double rel_tol;
     int32_t max_outer, mode, overlap, local_outer, local_inner, flags;

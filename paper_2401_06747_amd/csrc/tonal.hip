@@ -283,6 +283,9 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             // Alg. 2: local corrections, then the global residual with warm starts
             T_ST(ras_sweep());
             const double one[3] = {1, 1, 1}, om[3] = {omega, omega, omega};
+            // with the MSE stop, keep the iterate before the step (uB is free in
+            // this mode): a step that raises the MSE is undone
+            if (tc.mse_gain > 0.0) T_TRY(hipMemcpyAsync(t.uB, t.gK, sizeof(double) * C * m, hipMemcpyDeviceToDevice, s));
             launch_axpby(m, C, om, one, t.zK, t.gK, s);
             ++it;
             T_ST(X.normal_residual(true, tol_in, sse));
@@ -374,6 +377,8 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             for (int c = 0; c < C; ++c) mse_now += ss[c];
             mse_now /= (double)C * X.N;
             if (mse_prev - mse_now < tc.mse_gain * mse_prev) {
+                if (tc.mode == HDI_TONAL_RAS && mse_now > mse_prev)
+                    T_TRY(hipMemcpyAsync(t.gK, t.uB, sizeof(double) * C * m, hipMemcpyDeviceToDevice, s));
                 mse_stop = true;
                 break;
             }

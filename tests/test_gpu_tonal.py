@@ -211,3 +211,20 @@ def test_density_range_ends(density, C):
     g, rep, u = _run(f, m, rel_tol=1e-7, max_outer=400)
     _check(f, m, g, rep, u, tol=1e-7)
     print("density", density, rep)
+
+
+def test_stationary_ras_mse_stop_never_returns_a_worse_iterate():
+    """On a 0.5% mask the damped stationary RAS can overshoot; with the MSE
+    stop, a last step that raised the MSE is undone, so the result is never
+    worse than the start and its reported MSE is that of the returned values."""
+    f = synth.textured_image(270, 480, 3, 5, 40)
+    m = synth.gradient_mask(f, 0.005)
+    g, rep, u = _run(f, m, mode=hdi.RAS, mse_gain=1e-3)
+    assert rep["status"] == 0
+    f64 = np.asarray(f, np.float64)
+    mse = ot.mse(g, f64, m)
+    assert abs(mse - rep["mse_final"]) <= 1e-6 * mse
+    # (the starting MSE comes from a solve at the outer tolerance, the final one
+    # from tight solves)
+    assert mse <= rep["mse_initial"] * (1 + 1e-5)
+    print("stationary RAS on 0.5%:", rep)
