@@ -372,7 +372,8 @@ def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=500, seed=5, tonal_wo
     return res
 
 
-def comparators_bench(torch, hdi, synth, dev, configs=((2160, 3840, 0.05), (2160, 3840, 0.01), (540, 960, 0.05))):
+def comparators_bench(torch, hdi, synth, dev, configs=((2160, 3840, 0.05), (2160, 3840, 0.01), (2160, 3840, 0.005),
+                                                      (2160, 3840, 0.15), (1080, 1920, 0.05), (540, 960, 0.05))):
     """The paper's comparisons on this GPU (Sec. 6.3), per configuration: a
     mask from spatial optimisation, then inpainting by plain CG against the
     multigrid method, the tonal initialisations (3x3 error balancing, Voronoi
@@ -395,7 +396,7 @@ def comparators_bench(torch, hdi, synth, dev, configs=((2160, 3840, 0.05), (2160
         f = torch.tensor(synth.textured_image(H, W, 3, 2, 7), dtype=torch.float32, device=dev)
         rand = torch.tensor(synth.rng_for(2, 7, 3000).random((H, W)), device=dev)
         mask, _, _ = hdi.spatial_optimize(f, rand, density, n_steps=20)
-        out = {"workload": f"{W}x{H}x3 RGB, {density:.0%} mask from spatial optimisation (20 Delaunay steps)"}
+        out = {"workload": f"{W}x{H}x3 RGB, {density * 100:g}% mask from spatial optimisation (20 Delaunay steps)"}
         cg = hdi.SolveParams(flags=hdi.FLAG_CG)
         for name, prm in (("multigrid", None), ("cg", cg)):
             hdi.inpaint_solve(f, mask, params=prm)
@@ -428,7 +429,7 @@ def comparators_bench(torch, hdi, synth, dev, configs=((2160, 3840, 0.05), (2160
             (_, rep), ms = timed(run)
             out[name] = {"ms": round(ms, 1), "outer_iters": rep["outer_iters"], "inner_solves": rep["inner_solves"],
                          "psnr_db": round(psnr(rep["mse_final"]), 3), "status": rep["status"]}
-            log(f"comparators {W}x{H} {density:.0%}: {name} {out[name]}")
+            log(f"comparators {W}x{H} {density * 100:g}%: {name} {out[name]}")
         b = out["cgnr_cg"]["ms"]
         out["speedup_cgnr_multigrid_vs_cgnr_cg"] = round(b / out["cgnr_multigrid"]["ms"], 2)
         out["speedup_ras_voronoi_vs_cgnr_cg"] = round(b / out["ras_voronoi"]["ms"], 2)
