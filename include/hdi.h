@@ -154,16 +154,21 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
  *                recomputed with tight inner solves (default 1e-6)
  *   max_outer    outer iteration cap (default 500)
  *   mode         HDI_TONAL_PCG_RAS / HDI_TONAL_RAS / HDI_TONAL_CGNR
- *   overlap      overlap of the 32x32 blocks of the RAS sweep (default 14;
- *                Sec. 5.2 uses 6 with 64x64 blocks: with 32x32 blocks a wider
- *                overlap buys fewer outer iterations than its sweep costs)
- *   local_outer  CG steps on each block's local normal equations (default 3)
- *   local_inner  CG steps of each local inpainting inside them (default 24;
- *                far fewer steps truncate the local echoes, which makes the
- *                stationary RAS iteration overshoot)
+ *   overlap      overlap of the blocks of the RAS sweep, even, 2..block/2
+ *                (default 16 for 64x64 blocks, 14 for 32x32; Sec. 5.2 uses 6
+ *                with 64x64 blocks: here a wider overlap buys fewer outer
+ *                iterations than its sweep costs)
+ *   local_outer  CG steps on each block's local normal equations (default 5
+ *                for 64x64 blocks, 3 for 32x32)
+ *   local_inner  CG steps of each local inpainting inside them (default 20
+ *                for 64x64 blocks, 24 for 32x32; far fewer steps truncate the
+ *                local echoes, which makes the stationary RAS iteration
+ *                overshoot)
  *   flags        HDI_TONAL_INIT_FROM_F
  *   inner        parameters of the global inpainting solves (rel_tol is set
  *                per solve by the outer method)
+ *   block        edge of the RAS blocks: 64 (Sec. 5.2's size, four wavefronts
+ *                per block, the default) or 32 (one wavefront per block)
  *   mse_gain     > 0: also stop once an outer iteration lowers the MSE by less
  *                than this fraction of its previous value, the criterion the
  *                paper proposes with CGNR (Sec. 5.1) and uses in its
@@ -177,6 +182,7 @@ typedef struct {
     int32_t max_outer, mode, overlap, local_outer, local_inner, flags;
     hdi_solve_params inner;
     double mse_gain;
+    int32_t block;
 } hdi_tonal_params;
 
 typedef struct {

@@ -50,16 +50,18 @@ class TonalParams:
     rel_tol: float = 0.0       # 0 -> 1e-6
     max_outer: int = 0         # 0 -> 500
     mode: int = 0              # PCG_RAS, RAS or CGNR
-    overlap: int = 0           # 0 -> 14
-    local_outer: int = 0       # 0 -> 3
-    local_inner: int = 0       # 0 -> 24
+    overlap: int = 0           # 0 -> 16 (64x64 blocks) or 14 (32x32)
+    local_outer: int = 0       # 0 -> 5 (64x64 blocks) or 3 (32x32)
+    local_inner: int = 0       # 0 -> 20 (64x64 blocks) or 24 (32x32)
     flags: int = 0
     inner: SolveParams | None = None
     mse_gain: float = 0.0      # > 0: also stop when an iteration lowers the MSE by less than this fraction
+    block: int = 0             # RAS block edge: 0 -> 64, or 32
 
     def c(self):
         return _lib.hdi_tonal_params(self.rel_tol, self.max_outer, self.mode, self.overlap, self.local_outer,
-                                     self.local_inner, self.flags, (self.inner or SolveParams()).c(), self.mse_gain)
+                                     self.local_inner, self.flags, (self.inner or SolveParams()).c(), self.mse_gain,
+                                     self.block)
 
 
 def _stream_ptr(dev) -> ctypes.c_void_p:

@@ -32,7 +32,8 @@ class hdi_job(ctypes.Structure):
 class hdi_tonal_params(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("local_outer", ctypes.c_int32), ("local_inner", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("inner", hdi_solve_params), ("mse_gain", ctypes.c_double)]
+                ("flags", ctypes.c_int32), ("inner", hdi_solve_params), ("mse_gain", ctypes.c_double),
+                ("block", ctypes.c_int32)]
 
 
 class hdi_tonal_report(ctypes.Structure):

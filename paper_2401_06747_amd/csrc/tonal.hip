@@ -34,8 +34,8 @@ void launch_image_residual(int N, int C, const float *f, const double *u, double
 void launch_dots(int m, int C, int np, const double *const *a, const double *const *b, double *partials,
                  double *sums, hipStream_t s);
 void launch_axpby(int m, int C, const double *a, const double *b, const double *x, double *y, hipStream_t s);
-void launch_ras_local(int W, int H, int C, int m, int overlap, int nc, int ni, const uint8_t *mask, const int *pos,
-                      const double *r, double *z, unsigned int *steps, hipStream_t s);
+void launch_ras_local(int W, int H, int C, int m, int block, int overlap, int nc, int ni, const uint8_t *mask,
+                      const int *pos, const double *r, double *z, unsigned int *steps, hipStream_t s);
 void launch_sum_steps(int n, const unsigned int *steps, unsigned long long *totals, hipStream_t s);
 bool check_image(const hdi_image &img);
 int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap);
@@ -187,6 +187,7 @@ struct TonalCfg {
     double rel_tol;
     int max_outer, mode, overlap, local_outer, local_inner, flags;
     double mse_gain;   // > 0: stop when an iteration improves the MSE by less than this fraction
+    int block;         // RAS block edge, 32 or 64
 };
 
 static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double *u_out, hdi_tonal_report *rep) {
@@ -256,12 +257,12 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
                 ? std::min(1e-4, std::max(tight, fac * rmin))
                 : std::min(1e-3, std::max(tight, fac * tc.rel_tol / std::max(rmin, 1e-300)));
 
-        const Blocks1D tbx = make_blocks(X.W, tc.overlap), tby = make_blocks(X.H, tc.overlap);
-        const double block_px = (double)std::min(32, X.W) * std::min(32, X.H);
+        const Blocks1D tbx = make_blocks(X.W, tc.overlap, tc.block), tby = make_blocks(X.H, tc.overlap, tc.block);
+        const double block_px = (double)std::min(tc.block, X.W) * std::min(tc.block, X.H);
         const double ras_bytes = (double)X.N * 5.0 + 16.0 * C * m;   // mask + pos, r in, z out
         auto ras_sweep = [&]() -> int32_t {
             if (!X.prof) {
-                launch_ras_local(X.W, X.H, C, m, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK,
+                launch_ras_local(X.W, X.H, C, m, tc.block, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK,
                                  t.zK, nullptr, s);
                 return HDI_OK;
             }
@@ -269,7 +270,8 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             // local CG stops early at its FP32 residual floor): 15 per block
             // pixel and local CG step, 20 per block pixel and local CGNR step
             X.prof->begin(6, ras_bytes, s, 0.0);
-            launch_ras_local(X.W, X.H, C, m, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK, t.zK,
+            launch_ras_local(X.W, X.H, C, m, tc.block, tc.overlap, tc.local_outer, tc.local_inner, X.mask, t.pos, t.rK,
+                             t.zK,
                              t.ras_steps, s);
             X.prof->end(s);
             launch_sum_steps(tbx.count * tby.count * C, t.ras_steps, t.ras_totals, s);
@@ -294,7 +296,8 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             if (worst() > prev_worst) omega = std::max(omega * 0.5, 1.0 / 64);
             prev_worst = worst();
             best_ever = std::min(best_ever, worst());
-            if (worst() > 10.0 * best_ever || (omega <= 1.0 / 64 && worst() > 1.05 * best_ever)) {
+            // (with the MSE stop, a step that raises the MSE ends the run instead)
+            if (tc.mse_gain <= 0.0 && (worst() > 10.0 * best_ever || (omega <= 1.0 / 64 && worst() > 1.05 * best_ever))) {
                 status = HDI_ERR_NO_CONVERGENCE;
                 set_error("tonal: stationary RAS diverges on this mask (relative normal residual %.3e); "
                           "the flexible-CG mode converges", worst());
@@ -468,14 +471,17 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
     tc.rel_tol = (params && params->rel_tol > 0) ? params->rel_tol : 1e-6;
     tc.max_outer = (params && params->max_outer > 0) ? params->max_outer : 500;
     tc.mode = params ? params->mode : HDI_TONAL_PCG_RAS;
-    tc.overlap = (params && params->overlap > 0) ? params->overlap : 14;
-    tc.local_outer = (params && params->local_outer > 0) ? params->local_outer : 3;
-    tc.local_inner = (params && params->local_inner > 0) ? params->local_inner : 24;
+    tc.block = (params && params->block > 0) ? params->block : 64;
+    tc.overlap = (params && params->overlap > 0) ? params->overlap : (tc.block == 64 ? 16 : 14);
+    tc.local_outer = (params && params->local_outer > 0) ? params->local_outer : (tc.block == 64 ? 5 : 3);
+    tc.local_inner = (params && params->local_inner > 0) ? params->local_inner : (tc.block == 64 ? 20 : 24);
     tc.flags = params ? params->flags : 0;
     tc.mse_gain = params ? params->mse_gain : 0.0;
-    if (tc.mode < 0 || tc.mode > 2 || !(tc.rel_tol < 1.0) || !(tc.mse_gain >= 0.0 && tc.mse_gain < 1.0) || tc.overlap < 2 || tc.overlap > 16 || (tc.overlap & 1) ||
+    if (tc.mode < 0 || tc.mode > 2 || !(tc.rel_tol < 1.0) || !(tc.mse_gain >= 0.0 && tc.mse_gain < 1.0) ||
+        (tc.block != 32 && tc.block != 64) || tc.overlap < 2 || tc.overlap > tc.block / 2 || (tc.overlap & 1) ||
         tc.local_outer > 64 || tc.local_inner > 256) {
-        set_error("tonal parameter out of range (mode 0..2, rel_tol < 1, 0 <= mse_gain < 1, even overlap 2..16)");
+        set_error("tonal parameter out of range (mode 0..2, rel_tol < 1, 0 <= mse_gain < 1, block 32 or 64, "
+                  "even overlap 2..block/2)");
         return HDI_ERR_ARG;
     }
     SolveCfg inner;

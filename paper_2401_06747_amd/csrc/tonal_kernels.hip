@@ -209,41 +209,47 @@ __global__ void k_axpby(int m, int C, Coef3 k, const double *__restrict__ x, dou
 
 // ------------------------------------------------------------------ RAS local normal equations
 
-// One RAS sweep of Alg. 2 step 2 on 32x32 blocks: each block solves its local
-// normal equations B_i^T B_i v_i = R_i r by `nc` steps of CG on the normal
-// equations (CGNR), where B_i = A_i^{-1} C_i is inpainting on the block's own
-// grid graph (homogeneous Neumann at the block boundary, Sec. 5.2) and each
-// local inpainting is `ni` steps of CG on L_UU of the block. The result is
-// written on the mask pixels the block owns (0/1 partition of unity, the middle
-// of each overlap splitting ownership). FP32 throughout (a preconditioner).
-// Layout as in the Schwarz smoother: one wave per block, 4x4 pixels per lane,
-// neighbour exchange through a zero-ringed LDS tile.
-constexpr int TT = 32;
-constexpr int TLDS_W = 40;
+// One RAS sweep of Alg. 2 step 2 on TB x TB blocks: each block solves its
+// local normal equations B_i^T B_i v_i = R_i r by `nc` steps of CG on the
+// normal equations (CGNR), where B_i = A_i^{-1} C_i is inpainting on the
+// block's own grid graph (homogeneous Neumann at the block boundary, Sec. 5.2)
+// and each local inpainting is `ni` steps of CG on L_UU of the block. The
+// result is written on the mask pixels the block owns (0/1 partition of unity,
+// the middle of each overlap splitting ownership). FP32 throughout (a
+// preconditioner). Each lane holds 4x4 pixels: TB = 32 is one wavefront per
+// block; TB = 64 (the paper's block size) is four wavefronts, one per 32x32
+// quadrant, which exchange their edges through the LDS tile and combine their
+// dot products through LDS, with workgroup barriers. Every loop bound and
+// branch below depends only on values that all threads of the block share,
+// so every thread reaches every barrier.
 constexpr int TCOL0 = 4;
 
+template <int TB>
 struct LocalTile {
-    float (*s_x)[TLDS_W];
-    int bx, by;
+    static constexpr int LW = TB + 8;   // LDS row: TCOL0 zero columns, TB pixels, zero columns
+    float (*s_x)[LW];
+    int ox, oy;                         // the lane's 4x4 pixels start at (ox, oy) in the block
+    float *s_red;                       // [2][4] partial sums of the four wavefronts (TB = 64)
+    int parity = 0;
     __device__ void publish(const float *v) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            *reinterpret_cast<float4 *>(&s_x[4 * by + j + 1][TCOL0 + 4 * bx]) =
+            *reinterpret_cast<float4 *>(&s_x[oy + j + 1][TCOL0 + ox]) =
                 make_float4(v[j * 4 + 0], v[j * 4 + 1], v[j * 4 + 2], v[j * 4 + 3]);
         __syncthreads();
     }
     // n[k] = sum of the 4 neighbours of pixel k of v (zero outside the block)
     __device__ void nbsum(const float *v, float *n) {
         publish(v);
-        const float4 up = *reinterpret_cast<const float4 *>(&s_x[4 * by][TCOL0 + 4 * bx]);
-        const float4 dn = *reinterpret_cast<const float4 *>(&s_x[4 * by + 5][TCOL0 + 4 * bx]);
+        const float4 up = *reinterpret_cast<const float4 *>(&s_x[oy][TCOL0 + ox]);
+        const float4 dn = *reinterpret_cast<const float4 *>(&s_x[oy + 5][TCOL0 + ox]);
         const float upv[4] = {up.x, up.y, up.z, up.w};
         const float dnv[4] = {dn.x, dn.y, dn.z, dn.w};
         float lf[4], rt[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            lf[j] = s_x[4 * by + j + 1][TCOL0 + 4 * bx - 1];
-            rt[j] = s_x[4 * by + j + 1][TCOL0 + 4 * bx + 4];
+            lf[j] = s_x[oy + j + 1][TCOL0 + ox - 1];
+            rt[j] = s_x[oy + j + 1][TCOL0 + ox + 4];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -255,12 +261,27 @@ struct LocalTile {
             }
         __syncthreads();
     }
+    // sum over the block: the wavefront's DPP sum, then (TB = 64) the four
+    // wavefront sums in a fixed order from double-buffered LDS slots (a slot is
+    // rewritten only after the next sum's barrier, when every wave has read it)
+    __device__ float sum(float v) {
+        v = wave_sum(v);
+        if constexpr (TB == 64) {
+            float *slot = s_red + 4 * parity;
+            if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = v;
+            __syncthreads();
+            v = (slot[0] + slot[1]) + (slot[2] + slot[3]);
+            parity ^= 1;
+        }
+        return v;
+    }
 };
 
 // x = (L_UU of the block)^{-1} b by `iters` CG steps from 0 (fewer once the
 // residual reaches the FP32 floor); b and x are zero off U. dg[k] = block-graph
 // degree on U pixels, 0 elsewhere. Returns the steps taken.
-__device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const float *b, float *x, int iters) {
+template <int TB>
+__device__ __forceinline__ int local_cg(LocalTile<TB> &T, const float *dg, const float *b, float *x, int iters) {
     float r[16], p[16], q[16];
     float rr = 0.f;
 #pragma unroll
@@ -270,7 +291,7 @@ __device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const flo
         p[k] = b[k];
         rr += b[k] * b[k];
     }
-    rr = wave_sum(rr);
+    rr = T.sum(rr);
     const float floor_rr = rr * 1e-14f;
     int it = 0;
     for (; it < iters && rr > floor_rr && rr >= FLT_MIN; ++it) {
@@ -281,7 +302,7 @@ __device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const flo
             q[k] = dg[k] > 0.f ? dg[k] * p[k] - q[k] : 0.f;
             pq += p[k] * q[k];
         }
-        pq = wave_sum(pq);
+        pq = T.sum(pq);
         if (!(pq >= FLT_MIN)) break;
         const float alpha = rr * __builtin_amdgcn_rcpf(pq);
         float rr2 = 0.f;
@@ -291,7 +312,7 @@ __device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const flo
             r[k] -= alpha * q[k];
             rr2 += r[k] * r[k];
         }
-        rr2 = wave_sum(rr2);
+        rr2 = T.sum(rr2);
         const float beta = rr2 * __builtin_amdgcn_rcpf(rr);
         rr = rr2;
 #pragma unroll
@@ -300,23 +321,27 @@ __device__ __forceinline__ int local_cg(LocalTile &T, const float *dg, const flo
     return it;
 }
 
-__global__ void __launch_bounds__(64)
+template <int TB>
+__global__ void __launch_bounds__(TB == 64 ? 256 : 64)
 k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int ni, const uint8_t *__restrict__ mask,
             const int *__restrict__ pos, const double *__restrict__ r, double *__restrict__ z,
             unsigned int *__restrict__ steps) {
-    __shared__ __attribute__((aligned(16))) float s_x[TT + 2][TLDS_W];
-    __shared__ __attribute__((aligned(16))) float s_t[TT][TT];   // t = B_i p between the two local solves
+    constexpr int NT = TB == 64 ? 256 : 64;
+    __shared__ __attribute__((aligned(16))) float s_x[TB + 2][LocalTile<TB>::LW];
+    __shared__ __attribute__((aligned(16))) float s_t[TB][TB];   // t = B_i p between the two local solves
+    __shared__ float s_red[8];
     const int ntiles = ntx * nty;
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int c = blockIdx.y;
     const int tx = t % ntx, ty = t / ntx;
-    const int Tx = min(TT, W), Ty = min(TT, H);
+    const int Tx = min(TB, W), Ty = min(TB, H);
     const int x0 = min(tx * sx, W - Tx), y0 = min(ty * sy, H - Ty);
-    const int lane = threadIdx.x;
-    for (int k = lane; k < (TT + 2) * TLDS_W; k += 64) (&s_x[0][0])[k] = 0.f;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < (TB + 2) * LocalTile<TB>::LW; k += NT) (&s_x[0][0])[k] = 0.f;
     __syncthreads();
-    LocalTile T{s_x, lane & 7, lane >> 3};
-    const int bx = lane & 7, by = lane >> 3;
+    // the lane's 4x4 pixels: wavefront w takes quadrant (w & 1, w >> 1) of a 64 block
+    const int ox = 32 * (w & 1) + 4 * (lane & 7), oy = 32 * (w >> 1) + 4 * (lane >> 3);
+    LocalTile<TB> T{s_x, ox, oy, s_red};
 
     // pixel classes and right-hand side (all loads first, clamped addresses)
     int pk[16];
@@ -325,12 +350,12 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int xx = min(x0 + 4 * bx + i, W - 1), yy = min(y0 + 4 * by + j, H - 1);
+            const int xx = min(x0 + ox + i, W - 1), yy = min(y0 + oy + j, H - 1);
             pk[j * 4 + i] = pos[yy * W + xx];
             mk[j * 4 + i] = mask[yy * W + xx];
         }
     // pixel class in one value: degree in the block graph on U (> 0), 0 on
-    // the mask, -1 outside the image (tiles narrower than 32)
+    // the mask, -1 outside the image (tiles narrower than TB)
     float dgU[16], s[16];
     float ss = 0.f;
 #pragma unroll
@@ -338,7 +363,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int k = j * 4 + i;
-            const int lx = 4 * bx + i, ly = 4 * by + j;
+            const int lx = ox + i, ly = oy + j;
             const bool act = lx < Tx && ly < Ty;
             const bool known = act && mk[k];
             const float d = (float)((lx > 0) + (lx < Tx - 1) + (ly > 0) + (ly < Ty - 1));
@@ -346,7 +371,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
             s[k] = known ? (float)r[(size_t)c * m + pk[k]] : 0.f;
             ss += s[k] * s[k];
         }
-    ss = wave_sum(ss);
+    ss = T.sum(ss);
 
     // local CGNR on the mask pixels of the block
     float v[16], p[16];
@@ -360,24 +385,24 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
         T.nbsum(p, tmp);
 #pragma unroll
         for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tmp[k] : 0.f;
-        n_local += local_cg(T, dgU, tmp, u, ni);
+        n_local += local_cg<TB>(T, dgU, tmp, u, ni);
         // t is parked in LDS (the lane's own 4x4) while the second solve runs
 #pragma unroll
         for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] == 0.f ? p[k] : u[k];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            *reinterpret_cast<float4 *>(&s_t[4 * by + j][4 * bx]) =
+            *reinterpret_cast<float4 *>(&s_t[oy + j][ox]) =
                 make_float4(tmp[j * 4 + 0], tmp[j * 4 + 1], tmp[j * 4 + 2], tmp[j * 4 + 3]);
         // q = B_i^T t = t_K + sum over unknown neighbours of (L_UU^{-1} t_U)
 #pragma unroll
         for (int k = 0; k < 16; ++k) tmp[k] = dgU[k] > 0.f ? tmp[k] : 0.f;
-        n_local += local_cg(T, dgU, tmp, u, ni);
+        n_local += local_cg<TB>(T, dgU, tmp, u, ni);
         ++n_outer;
         T.nbsum(u, tmp);
         float pq = 0.f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const float4 t4 = *reinterpret_cast<const float4 *>(&s_t[4 * by + j][4 * bx]);
+            const float4 t4 = *reinterpret_cast<const float4 *>(&s_t[oy + j][ox]);
             const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -386,7 +411,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
                 pq += p[k] * tmp[k];
             }
         }
-        pq = wave_sum(pq);
+        pq = T.sum(pq);
         if (!(pq >= FLT_MIN)) break;
         const float alpha = ss * __builtin_amdgcn_rcpf(pq);
         float ss2 = 0.f;
@@ -396,14 +421,14 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
             s[k] -= alpha * tmp[k];
             ss2 += s[k] * s[k];
         }
-        ss2 = wave_sum(ss2);
+        ss2 = T.sum(ss2);
         const float beta = ss2 * __builtin_amdgcn_rcpf(ss);
         ss = ss2;
 #pragma unroll
         for (int k = 0; k < 16; ++k) p[k] = s[k] + beta * p[k];
     }
 
-    if (steps && lane == 0) steps[blockIdx.y * gridDim.x + blockIdx.x] = ((unsigned)n_local << 8) | (unsigned)n_outer;
+    if (steps && threadIdx.x == 0) steps[blockIdx.y * gridDim.x + blockIdx.x] = ((unsigned)n_local << 8) | (unsigned)n_outer;
     // restricted write-back on owned mask pixels
     const int xlo = tx == 0 ? 0 : (min((tx - 1) * sx, W - Tx) + Tx + x0) / 2;
     const int xhi = tx == ntx - 1 ? W : (x0 + Tx + min((tx + 1) * sx, W - Tx)) / 2;
@@ -416,7 +441,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int k = j * 4 + i;
-            const int x = x0 + 4 * bx + i, y = y0 + 4 * by + j;
+            const int x = x0 + ox + i, y = y0 + oy + j;
             if (dgU[k] == 0.f && x >= xlo && x < xhi && y >= ylo && y < yhi)
                 z[(size_t)c * m + pos[y * W + x]] = (double)v[k];
         }
@@ -482,12 +507,16 @@ void launch_axpby(int m, int C, const double *a, const double *b, const double *
     hipLaunchKernelGGL(k_axpby, g1(m, 256), dim3(256), 0, s, m, C, k, x, y);
 }
 
-void launch_ras_local(int W, int H, int C, int m, int overlap, int nc, int ni, const uint8_t *mask, const int *pos,
-                      const double *r, double *z, unsigned int *steps, hipStream_t s) {
-    const Blocks1D bx = make_blocks(W, overlap), by = make_blocks(H, overlap);
+void launch_ras_local(int W, int H, int C, int m, int block, int overlap, int nc, int ni, const uint8_t *mask,
+                      const int *pos, const double *r, double *z, unsigned int *steps, hipStream_t s) {
+    const Blocks1D bx = make_blocks(W, overlap, block), by = make_blocks(H, overlap, block);
     dim3 g(bx.count * by.count, C);
-    hipLaunchKernelGGL(k_ras_local, g, dim3(64), 0, s, W, H, m, bx.count, by.count, bx.stride, by.stride, nc, ni,
-                       mask, pos, r, z, steps);
+    if (block == 64)
+        hipLaunchKernelGGL(k_ras_local<64>, g, dim3(256), 0, s, W, H, m, bx.count, by.count, bx.stride, by.stride, nc,
+                           ni, mask, pos, r, z, steps);
+    else
+        hipLaunchKernelGGL(k_ras_local<32>, g, dim3(64), 0, s, W, H, m, bx.count, by.count, bx.stride, by.stride, nc,
+                           ni, mask, pos, r, z, steps);
 }
 
 // totals[0] += local CG steps, totals[1] += local CGNR steps over the n

@@ -228,3 +228,19 @@ def test_stationary_ras_mse_stop_never_returns_a_worse_iterate():
     # from tight solves)
     assert mse <= rep["mse_initial"] * (1 + 1e-5)
     print("stationary RAS on 0.5%:", rep)
+
+
+@pytest.mark.parametrize("block", [64, 32])
+@pytest.mark.parametrize("mode", [hdi.PCG_RAS, hdi.RAS])
+@pytest.mark.parametrize("shape,density,overlap", [((1, 90, 150), 0.04, 6), ((3, 97, 161), 0.03, 14),
+                                                   ((3, 270, 480), 0.02, 10), ((1, 40, 50), 0.1, 6)])
+def test_both_block_sizes_reach_the_optimum(block, mode, shape, density, overlap):
+    """Sec. 5.2's 64x64 RAS blocks (four wavefronts per block, the default) and
+    32x32 blocks (one wavefront), including images narrower than a block and
+    ragged last blocks."""
+    C, H, W = shape
+    f = synth.textured_image(H, W, C, 5, 50 + H)
+    m = synth.gradient_mask(f, density)
+    g, rep, u = _run(f, m, mode=mode, block=block, overlap=overlap, rel_tol=1e-7, max_outer=400)
+    _check(f, m, g, rep, u, tol=1e-7)
+    print(block, mode, shape, rep)
