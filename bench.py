@@ -100,7 +100,19 @@ def cpu_baseline(inst, crop=(540, 960)):
                       f"to rel 1e-6 ({t2 - t1:.1f} s), single-threaded, scaled by pixel count to 3840x2160x3"}
 
 
-def roofline_of(ks):
+def lds_bytes(L):
+    import ctypes
+    out = {}
+    for k, name in enumerate(KERNEL_NAMES):
+        v = ctypes.c_double()
+        L.hdi_stats_get_lds(k, ctypes.byref(v))
+        out[name] = v.value
+    return out
+
+
+def roofline_of(ks, lds=None, lds_calibrated=None):
+    """The dominant kernel against its peak; for a block solver with LDS
+    traffic also its LDS rate against the measured LDS bandwidth."""
     dom = max(KERNEL_NAMES, key=lambda k: ks[k][1])
     n, ms, by, fl = ks[dom]
     if dom in ALU_BOUND:
@@ -109,6 +121,11 @@ def roofline_of(ks):
              "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dom), "kernel": dom,
              "avg_us": round(ms / n * 1e3, 2), "alg_flops_per_launch": round(fl / n),
              "alg_bytes_per_launch": round(by / n)}
+        if lds and lds.get(dom, 0.0) > 0 and lds_calibrated:
+            rate = lds[dom] / (ms * 1e-3) / 1e9
+            r["lds"] = {"achieved": round(rate, 1), "peak": round(lds_calibrated / 1e9, 1), "unit": "GB/s",
+                        "frac": round(rate * 1e9 / lds_calibrated, 4), "bytes_per_launch": round(lds[dom] / n),
+                        "peak_source": "measured (hdi_lds_calibrate)"}
     else:
         achieved = by / (ms * 1e-3) / 1e9
         r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -520,7 +537,9 @@ def main():
             log(f"  {k:18s} launches {n:6d}  total {ms:9.2f} ms  avg {ms / n * 1e3:8.1f} us  "
                 f"{(by / (ms * 1e-3) / 1e9 if ms > 0 and by > 0 else 0):7.0f} GB/s  "
                 f"{(fl / (ms * 1e-3) / 1e12 if ms > 0 else 0):6.2f} TFLOP/s")
-    roofline = roofline_of(ks)
+    lds_cal = hdi.lds_calibrate(dev)
+    log(f"LDS calibration: {lds_cal / 1e9:.0f} GB/s")
+    roofline = roofline_of(ks, lds_bytes(L), lds_cal)
 
     densify = None
     if not args.no_densify:

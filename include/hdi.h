@@ -485,6 +485,30 @@ void hdi_stats_reset(void);
 int32_t hdi_stats_get(int32_t kernel_id, int64_t *launches, double *total_ms, double *alg_bytes,
                       double *alg_flops);
 
+/* LDS bytes of the launches timed under the same switches (kernel id as above;
+ * counted for the tonal RAS sweep, 0 for the other ids). Every lane of a
+ * TB x TB tile issues the tile's LDS operations, so per tile pixel:
+ *   local CG step    8 bytes (the direction written to the tile, the halo of
+ *                    the lane's 4x4 pixels read back), plus 1 byte per block
+ *                    sum on 64x64 blocks (four wavefront slots read; two sums)
+ *   local CGNR step  24 bytes (two such exchanges, t parked in LDS and read
+ *                    back), plus 4 bytes of block sums on 64x64 blocks
+ *   once per block   the zeroed tile and, on 64x64 blocks, the first sum
+ * over the local steps the sweep takes (the slot writes, one lane per
+ * wavefront, are left out). ARG for an unknown id or a null output. */
+int32_t hdi_stats_get_lds(int32_t kernel_id, double *lds_bytes);
+
+/* Measured LDS bandwidth of the current device: a kernel that only writes and
+ * reads float4s through LDS (16 blocks of 256 threads per CU, 128 bytes per
+ * lane and iteration) is launched four times on `stream`; *bytes_per_s is the
+ * rate of the fastest of the last three. It is the ceiling against which the
+ * block solvers' LDS traffic is set.
+ *   iters        1..2^20 (4096 take a few milliseconds)
+ *   sink         device pointer to one float (caller-owned; never written in
+ *                practice, it keeps the compiler from removing the loop)
+ * Host-synchronous. ARG for bad arguments, HIP if a launch or event fails. */
+int32_t hdi_lds_calibrate(int32_t iters, float *sink, double *bytes_per_s, void *stream);
+
 const char *hdi_status_string(int32_t status);
 const char *hdi_last_error(void);   /* thread-local message of the last failure */
 

@@ -122,6 +122,14 @@ def hdi_block_count(width: int, height: int, overlap: int) -> int:
     return int(_lib.lib().hdi_block_count(width, height, overlap))
 
 
+def lds_calibrate(device="cuda:0", iters: int = 4096) -> float:
+    """Measured LDS bandwidth of `device` in bytes/s (hdi_lds_calibrate)."""
+    sink = torch.empty(1, dtype=torch.float32, device=device)
+    out = ctypes.c_double()
+    check(_lib.lib().hdi_lds_calibrate(iters, _ptr(sink), ctypes.byref(out), _stream_ptr(sink.device)))
+    return out.value
+
+
 def tonal_optimize(f: torch.Tensor, mask: torch.Tensor, g0: torch.Tensor | None = None,
                    params: TonalParams | None = None, ws: torch.Tensor | None = None,
                    want_u: bool = False, out: torch.Tensor | None = None):

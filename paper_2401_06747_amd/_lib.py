@@ -135,6 +135,9 @@ _SIGS = {
     "hdi_stats_reset": (None, []),
     "hdi_stats_get": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "hdi_stats_get_lds": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "hdi_lds_calibrate": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.c_void_p]),
     "hdi_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "hdi_last_error": (ctypes.c_char_p, []),
 }

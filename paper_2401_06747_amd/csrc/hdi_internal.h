@@ -122,16 +122,21 @@ struct CallTimer {
 // are resolved after the call's final synchronisation.
 struct Prof {
     bool on = false;
-    struct Rec { int id; double bytes, flops; hipEvent_t a, b; };
+    struct Rec { int id; double bytes, flops, lds; hipEvent_t a, b; };
     Rec recs[4096];
     int n = 0;
     bool pending = false;   // begin() made the events of recs[n]
+    bool ended = false;     // the last begin() was closed by end() as recs[n - 1]
     void begin(int id, double bytes, hipStream_t s, double flops = 0.0);
     void end(hipStream_t s);
     void flush();   // accumulate into the global counters and free the events
-    // FLOPs of the last ended record, when they are known only after the launch
-    void set_last_flops(double flops) {
-        if (on && n > 0) recs[n - 1].flops = flops;
+    // FLOPs and LDS bytes of the record the last begin()/end() pair made, when
+    // they are known only after the launch (nothing if that pair made none)
+    void set_last(double flops, double lds) {
+        if (on && ended) {
+            recs[n - 1].flops = flops;
+            recs[n - 1].lds = lds;
+        }
     }
 };
 Prof *prof_for_call();   // nullptr when timing is off

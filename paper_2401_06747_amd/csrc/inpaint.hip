@@ -21,18 +21,20 @@ namespace hdi {
 
 // ------------------------------------------------------------------ kernel timing
 
-struct KStats { int64_t launches; double ms, bytes, flops; };
+struct KStats { int64_t launches; double ms, bytes, flops, lds; };
 static std::mutex g_stats_mu;
 static KStats g_stats[HDI_NUM_KERNEL_IDS];
 static std::atomic<int> g_stats_on{0};
 
 void Prof::begin(int id, double bytes, hipStream_t s, double flops) {
     pending = false;
+    ended = false;
     if (!on || n >= (int)(sizeof recs / sizeof recs[0])) return;
     Rec &r = recs[n];
     r.id = id;
     r.bytes = bytes;
     r.flops = flops;
+    r.lds = 0.0;
     if (hipEventCreate(&r.a) != hipSuccess) return;
     if (hipEventCreate(&r.b) != hipSuccess) {
         (void)hipEventDestroy(r.a);
@@ -46,6 +48,7 @@ void Prof::end(hipStream_t s) {
     (void)hipEventRecord(recs[n].b, s);
     ++n;
     pending = false;
+    ended = true;
 }
 void Prof::flush() {
     std::lock_guard<std::mutex> lk(g_stats_mu);
@@ -56,11 +59,13 @@ void Prof::flush() {
             g_stats[recs[i].id].ms += ms;
             g_stats[recs[i].id].bytes += recs[i].bytes;
             g_stats[recs[i].id].flops += recs[i].flops;
+            g_stats[recs[i].id].lds += recs[i].lds;
         }
         (void)hipEventDestroy(recs[i].a);
         (void)hipEventDestroy(recs[i].b);
     }
     n = 0;
+    ended = false;
 }
 Prof *prof_for_call() {
     if (!g_stats_on.load()) return nullptr;
@@ -522,7 +527,7 @@ void hdi_stats_enable(int32_t on) { g_stats_on.store(on ? 1 : 0); }
 
 void hdi_stats_reset(void) {
     std::lock_guard<std::mutex> lk(g_stats_mu);
-    for (auto &k : g_stats) k = KStats{0, 0.0, 0.0, 0.0};
+    for (auto &k : g_stats) k = KStats{0, 0.0, 0.0, 0.0, 0.0};
 }
 
 int32_t hdi_stats_get(int32_t id, int64_t *launches, double *total_ms, double *alg_bytes, double *alg_flops) {
@@ -535,6 +540,16 @@ int32_t hdi_stats_get(int32_t id, int64_t *launches, double *total_ms, double *a
     if (total_ms) *total_ms = g_stats[id].ms;
     if (alg_bytes) *alg_bytes = g_stats[id].bytes;
     if (alg_flops) *alg_flops = g_stats[id].flops;
+    return HDI_OK;
+}
+
+int32_t hdi_stats_get_lds(int32_t id, double *lds_bytes) {
+    if (id < 0 || id >= HDI_NUM_KERNEL_IDS || !lds_bytes) {
+        set_error("kernel id %d outside 0..%d, or no output", id, HDI_NUM_KERNEL_IDS - 1);
+        return HDI_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_stats_mu);
+    *lds_bytes = g_stats[id].lds;
     return HDI_OK;
 }
 

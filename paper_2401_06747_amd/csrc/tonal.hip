@@ -278,7 +278,19 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             unsigned long long tot[2] = {0, 0};
             T_TRY(hipMemcpyAsync(tot, t.ras_totals, sizeof tot, hipMemcpyDeviceToHost, s));
             T_TRY(hipStreamSynchronize(s));
-            X.prof->set_last_flops(block_px * (15.0 * (double)tot[0] + 20.0 * (double)tot[1]));
+            // LDS bytes, every lane of a TB x TB tile issuing the tile's LDS
+            // operations: per pixel and local CG step the direction written to
+            // the tile (4) and the halo of the lane's 4x4 read back (4), plus
+            // the four wavefront slots read per block sum (1 each, two sums, 64
+            // blocks only); per pixel and local CGNR step two such exchanges,
+            // t parked and read back (8) and four block sums; once per block
+            // the zeroed tile and the first sum. (The slot writes, one lane per
+            // wavefront, are left out.)
+            const double tpx = (double)tc.block * tc.block, sb = tc.block == 64 ? 1.0 : 0.0;
+            const double nblk = (double)tbx.count * tby.count * C;
+            const double lds = nblk * ((tc.block + 2.0) * (tc.block + 8.0) * 4.0 + sb * tpx) +
+                               tpx * ((8.0 + 2.0 * sb) * (double)tot[0] + (24.0 + 4.0 * sb) * (double)tot[1]);
+            X.prof->set_last(block_px * (15.0 * (double)tot[0] + 20.0 * (double)tot[1]), lds);
             return HDI_OK;
         };
         if (tc.mode == HDI_TONAL_RAS) {

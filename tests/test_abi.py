@@ -118,3 +118,23 @@ def test_argument_errors_of_the_later_entry_points_need_no_gpu():
     tp = L.hdi_tonal_params(0.0, 0, 0, 0, 0, 0, 0, L.hdi_solve_params(), 1.5)   # mse_gain >= 1
     assert lib.tonal_optimize(img, dev, dev, dev, None, dev, 1 << 30, ctypes.byref(tp), ctypes.byref(trep),
                               None) == L.HDI_ERR_ARG
+
+
+def test_lds_calibration_and_statistics_arguments_need_no_gpu():
+    """The LDS calibration and the LDS statistics reject bad arguments before
+    any HIP call; the statistics are host-side and read 0 after a reset."""
+    import ctypes
+    L = _lib()
+    lib = L.lib()
+    bw = ctypes.c_double(-1.0)
+    sink = ctypes.c_void_p(16)   # never dereferenced: every call below fails first
+    assert lib.hdi_lds_calibrate(0, sink, ctypes.byref(bw), None) == L.HDI_ERR_ARG
+    assert lib.hdi_lds_calibrate((1 << 20) + 1, sink, ctypes.byref(bw), None) == L.HDI_ERR_ARG
+    assert lib.hdi_lds_calibrate(16, None, ctypes.byref(bw), None) == L.HDI_ERR_ARG
+    assert lib.hdi_lds_calibrate(16, sink, None, None) == L.HDI_ERR_ARG
+    v = ctypes.c_double(-1.0)
+    assert lib.hdi_stats_get_lds(8, ctypes.byref(v)) == L.HDI_ERR_ARG
+    assert lib.hdi_stats_get_lds(-1, ctypes.byref(v)) == L.HDI_ERR_ARG
+    assert lib.hdi_stats_get_lds(6, None) == L.HDI_ERR_ARG
+    lib.hdi_stats_reset()
+    assert lib.hdi_stats_get_lds(6, ctypes.byref(v)) == L.HDI_OK and v.value == 0.0

@@ -244,3 +244,58 @@ def test_both_block_sizes_reach_the_optimum(block, mode, shape, density, overlap
     g, rep, u = _run(f, m, mode=mode, block=block, overlap=overlap, rel_tol=1e-7, max_outer=400)
     _check(f, m, g, rep, u, tol=1e-7)
     print(block, mode, shape, rep)
+
+
+def _blocks(n, block, overlap):
+    """Blocks per dimension: ceil((n - block) / (block - overlap)) + 1, 1 if n <= block."""
+    return 1 if n <= block else -(-(n - block) // (block - overlap)) + 1
+
+
+@pytest.mark.parametrize("block,overlap,nc,ni", [(64, 16, 5, 20), (32, 14, 3, 24)])
+def test_ras_sweep_statistics_count_the_steps_taken(block, overlap, nc, ni):
+    """The RAS sweep's FLOP and LDS figures are linear in the local CG and
+    CGNR steps it takes (15 and 20 FLOPs, 8 + 2s and 24 + 4s LDS bytes per
+    tile pixel, s = 1 for 64x64 blocks, plus a fixed amount per block): solving
+    the two for the step counts gives whole, admissible numbers."""
+    from paper_2401_06747_amd import _lib
+    import ctypes
+    C, H, W = 3, 150, 230
+    f = synth.textured_image(H, W, C, 5, 77)
+    m = synth.gradient_mask(f, 0.04)
+    ft = torch.tensor(f, dtype=torch.float32, device=DEV).contiguous()
+    mt = torch.tensor(m, dtype=torch.uint8, device=DEV).contiguous()
+    L = _lib.lib()
+    L.hdi_stats_reset()
+    L.hdi_stats_enable(1)
+    try:
+        g, rep = hdi.tonal_optimize(ft, mt, params=hdi.TonalParams(block=block, overlap=overlap, local_outer=nc,
+                                                                   local_inner=ni))
+        torch.cuda.synchronize()
+    finally:
+        L.hdi_stats_enable(0)
+    assert rep["status"] == 0
+    n, ms, by, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lds = ctypes.c_double()
+    assert L.hdi_stats_get(6, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)) == 0
+    assert L.hdi_stats_get_lds(6, ctypes.byref(lds)) == 0
+    sweeps = n.value
+    assert sweeps >= 1 and ms.value > 0
+    nblk = _blocks(W, block, overlap) * _blocks(H, block, overlap) * C
+    tpx = block * block
+    s = 1 if block == 64 else 0
+    fixed = sweeps * nblk * ((block + 2) * (block + 8) * 4 + s * tpx)
+    # fl = tpx (15 a + 20 b), lds - fixed = tpx ((8 + 2 s) a + (24 + 4 s) b)
+    A = np.array([[15.0, 20.0], [8.0 + 2 * s, 24.0 + 4 * s]])
+    a, b = np.linalg.solve(A, np.array([fl.value, lds.value - fixed]) / tpx)
+    assert abs(a - round(a)) < 1e-3 and abs(b - round(b)) < 1e-3, (a, b)
+    a, b = round(a), round(b)
+    assert 0 < b <= sweeps * nblk * nc
+    assert 0 < a <= 2 * ni * b
+    print(f"block {block}: {sweeps} sweeps, {a} local CG steps, {b} local CGNR steps, "
+          f"{lds.value / n.value / 1e9:.3f} GB of LDS traffic per sweep")
+
+
+def test_lds_calibration_measures_a_plausible_bandwidth():
+    bw = hdi.lds_calibrate(DEV)
+    assert np.isfinite(bw) and 1e12 < bw < 1e15, bw
+    print(f"LDS bandwidth {bw / 1e12:.1f} TB/s")
