@@ -323,16 +323,18 @@ __device__ __forceinline__ int local_cg(LocalTile<TB> &T, const float *dg, const
 
 template <int TB>
 __global__ void __launch_bounds__(TB == 64 ? 256 : 64)
-k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int ni, const uint8_t *__restrict__ mask,
-            const int *__restrict__ pos, const double *__restrict__ r, double *__restrict__ z,
-            unsigned int *__restrict__ steps) {
+k_ras_local(int W, int H, int C, int m, int ntx, int nty, int sx, int sy, int nc, int ni,
+            const uint8_t *__restrict__ mask, const int *__restrict__ pos, const double *__restrict__ r,
+            double *__restrict__ z, unsigned int *__restrict__ steps) {
     constexpr int NT = TB == 64 ? 256 : 64;
     __shared__ __attribute__((aligned(16))) float s_x[TB + 2][LocalTile<TB>::LW];
     __shared__ __attribute__((aligned(16))) float s_t[TB][TB];   // t = B_i p between the two local solves
     __shared__ float s_red[8];
-    const int ntiles = ntx * nty;
-    const int t = xcd_remap(blockIdx.x, ntiles);
-    const int c = blockIdx.y;
+    // the C channel blocks of a tile are neighbours in the launch order and go
+    // to the same XCD, so the tile's mask and compact positions come from L2
+    // after the first of them
+    const int b = xcd_remap(blockIdx.x, ntx * nty * C);
+    const int c = b % C, t = b / C;
     const int tx = t % ntx, ty = t / ntx;
     const int Tx = min(TB, W), Ty = min(TB, H);
     const int x0 = min(tx * sx, W - Tx), y0 = min(ty * sy, H - Ty);
@@ -428,7 +430,7 @@ k_ras_local(int W, int H, int m, int ntx, int nty, int sx, int sy, int nc, int n
         for (int k = 0; k < 16; ++k) p[k] = s[k] + beta * p[k];
     }
 
-    if (steps && threadIdx.x == 0) steps[blockIdx.y * gridDim.x + blockIdx.x] = ((unsigned)n_local << 8) | (unsigned)n_outer;
+    if (steps && threadIdx.x == 0) steps[blockIdx.x] = ((unsigned)n_local << 8) | (unsigned)n_outer;
     // restricted write-back on owned mask pixels
     const int xlo = tx == 0 ? 0 : (min((tx - 1) * sx, W - Tx) + Tx + x0) / 2;
     const int xhi = tx == ntx - 1 ? W : (x0 + Tx + min((tx + 1) * sx, W - Tx)) / 2;
@@ -510,13 +512,13 @@ void launch_axpby(int m, int C, const double *a, const double *b, const double *
 void launch_ras_local(int W, int H, int C, int m, int block, int overlap, int nc, int ni, const uint8_t *mask,
                       const int *pos, const double *r, double *z, unsigned int *steps, hipStream_t s) {
     const Blocks1D bx = make_blocks(W, overlap, block), by = make_blocks(H, overlap, block);
-    dim3 g(bx.count * by.count, C);
+    const dim3 g(bx.count * by.count * C);
     if (block == 64)
-        hipLaunchKernelGGL(k_ras_local<64>, g, dim3(256), 0, s, W, H, m, bx.count, by.count, bx.stride, by.stride, nc,
-                           ni, mask, pos, r, z, steps);
+        hipLaunchKernelGGL(k_ras_local<64>, g, dim3(256), 0, s, W, H, C, m, bx.count, by.count, bx.stride, by.stride,
+                           nc, ni, mask, pos, r, z, steps);
     else
-        hipLaunchKernelGGL(k_ras_local<32>, g, dim3(64), 0, s, W, H, m, bx.count, by.count, bx.stride, by.stride, nc,
-                           ni, mask, pos, r, z, steps);
+        hipLaunchKernelGGL(k_ras_local<32>, g, dim3(64), 0, s, W, H, C, m, bx.count, by.count, bx.stride, by.stride,
+                           nc, ni, mask, pos, r, z, steps);
 }
 
 // totals[0] += local CG steps, totals[1] += local CGNR steps over the n
