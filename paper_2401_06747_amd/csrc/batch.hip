@@ -300,8 +300,7 @@ int32_t Engine::round(std::vector<EJob *> &ended, hipStream_t s) {
     for (int k = 0; k < 2; ++k) launch_b_residual(res[k], k == 0 ? 1 : 3, d_img_, d_flags_, d_lev_, s);
     launch_b_reduce(red, d_img_, s);
     B_TRY(hipGetLastError());
-    B_TRY(hipMemcpyAsync(h_norms_.data(), d_norms_, sizeof(double) * h_norms_.size(), hipMemcpyDeviceToHost, s));
-    B_TRY(hipStreamSynchronize(s));
+    B_TRY(read_to_host(h_norms_.data(), d_norms_, sizeof(double) * h_norms_.size(), s));
 
     // 2. per-job decision
     std::vector<EJob *> go;

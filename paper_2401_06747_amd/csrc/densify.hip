@@ -488,8 +488,7 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, 1, 0, d.total + 1);
     hipLaunchKernelGGL(k_check_err, gd(N), dim3(256), 0, s, N, err, emax, d.total + 1);
     int mb[2] = {0, 0};
-    D_TRY(hipMemcpyAsync(mb, d.total, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    D_TRY(hipStreamSynchronize(s));
+    D_TRY(read_to_host(mb, d.total, 2 * sizeof(int), s));
     const int m = mb[0];
     if (m == 0) {
         set_error("empty mask: densification needs at least one mask pixel");
@@ -505,8 +504,7 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
         // every later stage indexes by label: refuse unlabelled pixels
         launch_label_max_d2(W, H, d.labels, d.maxd2, s);
         unsigned long long r[2] = {0, 0};
-        D_TRY(hipMemcpyAsync(r, d.maxd2, sizeof r, hipMemcpyDeviceToHost, s));
-        D_TRY(hipStreamSynchronize(s));
+        D_TRY(read_to_host(r, d.maxd2, sizeof r, s));
         if (r[1]) {
             set_error("jump flooding from step %d left pixels without a label", jfa_k0);
             return HDI_ERR_ARG;
@@ -522,8 +520,7 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
         hipLaunchKernelGGL(k_quads, gd((long)(W - 1) * (H - 1)), dim3(256), 0, s, W, H, d.labels, d.count, d.ta, d.tb,
                            d.tc);
         unsigned int nt = 0;
-        D_TRY(hipMemcpyAsync(&nt, d.count, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-        D_TRY(hipStreamSynchronize(s));
+        D_TRY(read_to_host(&nt, d.count, sizeof(unsigned int), s));
         if (nt > 0) {
             const int n = (int)nt;
             hipLaunchKernelGGL(k_iota, gd(n), dim3(256), 0, s, n, d.ord0);
@@ -539,9 +536,8 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
             hipLaunchKernelGGL(k_uniq_scatter, gd(n), dim3(256), 0, s, n, d.ord0, d.flag, d.off, d.ta, d.tb, d.tc,
                                d.ua, d.ub, d.uc);
             int last_off = 0, last_flag = 0;
-            D_TRY(hipMemcpyAsync(&last_off, d.off + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-            D_TRY(hipMemcpyAsync(&last_flag, d.flag + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-            D_TRY(hipStreamSynchronize(s));
+            D_TRY(read_to_host(&last_off, d.off + n - 1, sizeof(int), s));
+            D_TRY(read_to_host(&last_flag, d.flag + n - 1, sizeof(int), s));
             T = last_off + last_flag;
         }
         // 3 ownership
@@ -569,8 +565,7 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
     // added pixels in ascending order: compaction of the new-pixel flags
     launch_compact(N, d.newpix, d.chunk_cnt, d.chunk_off, d.total, d.seed_idx, d.seed_pos, s);
     int na = 0;
-    D_TRY(hipMemcpyAsync(&na, d.total, sizeof(int), hipMemcpyDeviceToHost, s));
-    D_TRY(hipStreamSynchronize(s));
+    D_TRY(read_to_host(&na, d.total, sizeof(int), s));
     if (added && na > 0) hipLaunchKernelGGL(k_copy_i32, gd(na), dim3(256), 0, s, na, d.seed_idx, added);
     if (max_d2) D_TRY(hipMemcpyAsync(max_d2, d.maxd2, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     D_TRY(hipGetLastError());
@@ -685,8 +680,7 @@ int32_t hdi_voronoi_labels(int32_t width, int32_t height, const uint8_t *mask, i
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, 4, slot);
     hipLaunchKernelGGL(k_count_set, gd(N), dim3(256), 0, s, N, mask, slot + 2);
     unsigned long long cnt = 0;
-    D_TRY(hipMemcpyAsync(&cnt, slot + 2, sizeof cnt, hipMemcpyDeviceToHost, s));
-    D_TRY(hipStreamSynchronize(s));
+    D_TRY(read_to_host(&cnt, slot + 2, sizeof cnt, s));
     if (cnt == 0) {
         set_error("empty mask: no labels");
         return HDI_ERR_EMPTY_MASK;

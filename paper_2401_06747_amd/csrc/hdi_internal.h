@@ -16,6 +16,14 @@ constexpr int RED_THREADS = 256;  // threads of the reduction kernels
 
 void set_error(const char *fmt, ...);
 
+// A small device-to-host read that the host waits for (a convergence test, a
+// count): staged through a pinned per-thread buffer, so that the copy is
+// asynchronous, and waited for by polling the stream for up to 5 ms before a
+// blocking wait (a blocking wait adds tens of microseconds of wake-up to each
+// test). Larger reads take a plain copy and the same wait. Returns the first
+// HIP error.
+hipError_t read_to_host(void *dst, const void *src, size_t bytes, hipStream_t s);
+
 // Geometry of the overlapping tile x tile blocks along one dimension (Sec. 3.1, 3.3).
 struct Blocks1D {
     int n;       // pixels along the dimension

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <mutex>
 #include <vector>
 
@@ -67,6 +68,40 @@ void Prof::flush() {
     n = 0;
     ended = false;
 }
+// pinned staging for read_to_host: one buffer per host thread, kept for the
+// life of the process (freeing it at thread exit could run after the HIP
+// runtime has shut down)
+constexpr size_t STAGING_BYTES = 16384;
+static thread_local void *t_staging = nullptr;
+static thread_local bool t_staging_failed = false;
+
+static hipError_t wait_for(hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e != hipErrorNotReady) return e;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(5)) return hipStreamSynchronize(s);
+    }
+}
+
+hipError_t read_to_host(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes <= STAGING_BYTES && !t_staging && !t_staging_failed) {
+        if (hipHostMalloc(&t_staging, STAGING_BYTES, hipHostMallocPortable) != hipSuccess) {
+            t_staging = nullptr;
+            t_staging_failed = true;
+            (void)hipGetLastError();
+        }
+    }
+    if (bytes <= STAGING_BYTES && t_staging) {
+        hipError_t e = hipMemcpyAsync(t_staging, src, bytes, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = wait_for(s);
+        if (e == hipSuccess) std::memcpy(dst, t_staging, bytes);
+        return e;
+    }
+    const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? wait_for(s) : e;
+}
+
 Prof *prof_for_call() {
     if (!g_stats_on.load()) return nullptr;
     Prof *p = new Prof;
@@ -211,8 +246,7 @@ static int32_t solve_cg(Hierarchy &h, int W, int H, int C, const uint8_t *mask, 
     if (prof) prof->end(s);
     for (;;) {
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(sc, h.cg_scal, sizeof(double) * 8 * C, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(read_to_host(sc, h.cg_scal, sizeof(double) * 8 * C, s));
         double worst = 0.0;
         bool finite = true;
         for (int c = 0; c < C; ++c) {
@@ -302,8 +336,7 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         launch_residual<TD>(W, H, C, mask, cur, e, e ? oth : nullptr, data, src, h.lev[0].r, h.partials, h.norms, s);
         if (prof) prof->end(s);
         if (e) std::swap(cur, oth);
-        HIP_TRY(hipMemcpyAsync(norms, h.norms, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(read_to_host(norms, h.norms, sizeof(double) * 2 * C, s));
         double worst = 0.0;
         bool finite = true;
         for (int c = 0; c < C; ++c) {
@@ -403,8 +436,7 @@ int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap) {
 int32_t prepare_mask(Hierarchy &h, hipStream_t s) {
     launch_mask_pyramid(h, h.nlev_full, h.counts, s);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(h.known, h.counts, sizeof(unsigned int) * MAX_LEVELS, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(read_to_host(h.known, h.counts, sizeof(unsigned int) * MAX_LEVELS, s));
     if (h.known[0] == 0) {
         set_error("empty mask: the inpainting matrix is singular");
         return HDI_ERR_EMPTY_MASK;

@@ -92,14 +92,12 @@ static int32_t init_mask(int W, int H, int C, const float *f, const double *rnd,
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, 2, sums);
     hipLaunchKernelGGL(k_lapmag, g, b, 0, s, W, H, C, f, lap, sums);
     unsigned long long S = 0;
-    S_TRY(hipMemcpyAsync(&S, sums, sizeof S, hipMemcpyDeviceToHost, s));
-    S_TRY(hipStreamSynchronize(s));
+    S_TRY(read_to_host(&S, sums, sizeof S, s));
     const double alpha = S > 0 ? (double)n0 / ((double)S * std::ldexp(1.0, -LAP_SHIFT)) : 0.0;
     const double uniform_p = (double)n0 / N;
     hipLaunchKernelGGL(k_coins, g, b, 0, s, N, lap, rnd, alpha, uniform_p, mask, sums + 1);
     unsigned long long cnt = 0;
-    S_TRY(hipMemcpyAsync(&cnt, sums + 1, sizeof cnt, hipMemcpyDeviceToHost, s));
-    S_TRY(hipStreamSynchronize(s));
+    S_TRY(read_to_host(&cnt, sums + 1, sizeof cnt, s));
     *count = (long long)cnt;
     return HDI_OK;
 }
@@ -251,9 +249,8 @@ int32_t spatial_optimize(hdi_image img, const float *f, const double *rand, cons
             // host copies of what the step sees, for the caller's inspection
             h_mask.resize(Nz);
             h_err.resize(Nz);
-            S_TRY(hipMemcpyAsync(h_mask.data(), mask, Nz, hipMemcpyDeviceToHost, s));
-            S_TRY(hipMemcpyAsync(h_err.data(), w.err, Nz * 4, hipMemcpyDeviceToHost, s));
-            S_TRY(hipStreamSynchronize(s));
+            S_TRY(read_to_host(h_mask.data(), mask, Nz, s));
+            S_TRY(read_to_host(h_err.data(), w.err, Nz * 4, s));
         }
         int64_t n_added = 0;
         uint64_t max_d2 = 0;

@@ -138,15 +138,13 @@ struct TonalCtx {
     // rho = f - u, returns sum of squares per channel
     int32_t image_residual(double *ss, const double *u) {
         launch_image_residual(N, C, f, u, t.rho, t.partials, t.sums, s);
-        T_TRY(hipMemcpyAsync(ss, t.sums, sizeof(double) * C, hipMemcpyDeviceToHost, s));
-        T_TRY(hipStreamSynchronize(s));
+        T_TRY(read_to_host(ss, t.sums, sizeof(double) * C, s));
         return HDI_OK;
     }
     int32_t dots(int np, const double *const *a, const double *const *b, double out[4][3]) {
         launch_dots(m, C, np, a, b, t.partials, t.sums, s);
         double tmp[12];
-        T_TRY(hipMemcpyAsync(tmp, t.sums, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
-        T_TRY(hipStreamSynchronize(s));
+        T_TRY(read_to_host(tmp, t.sums, sizeof(double) * 3 * np, s));
         for (int q = 0; q < np; ++q)
             for (int c = 0; c < 3; ++c) out[q][c] = c < C ? tmp[q * 3 + c] : 0.0;
         return HDI_OK;
@@ -276,8 +274,7 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
             X.prof->end(s);
             launch_sum_steps(tbx.count * tby.count * C, t.ras_steps, t.ras_totals, s);
             unsigned long long tot[2] = {0, 0};
-            T_TRY(hipMemcpyAsync(tot, t.ras_totals, sizeof tot, hipMemcpyDeviceToHost, s));
-            T_TRY(hipStreamSynchronize(s));
+            T_TRY(read_to_host(tot, t.ras_totals, sizeof tot, s));
             // LDS bytes, every lane of a TB x TB tile issuing the tile's LDS
             // operations: per pixel and local CG step the direction written to
             // the tile (4) and the halo of the lane's 4x4 read back (4), plus
@@ -516,8 +513,7 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
     const int N = img.width * img.height, C = img.channels;
     launch_compact(N, mask, t.chunk_cnt, t.chunk_off, t.total, t.idx, t.pos, s);
     int m = 0;
-    T_TRY(hipMemcpyAsync(&m, t.total, sizeof(int), hipMemcpyDeviceToHost, s));
-    T_TRY(hipStreamSynchronize(s));
+    T_TRY(read_to_host(&m, t.total, sizeof(int), s));
     if (tc.flags & HDI_TONAL_INIT_FROM_F)
         launch_gather_f(m, C, N, t.idx, f, t.gK, s);
     else

@@ -261,8 +261,7 @@ struct Vinit {
         double sums[3];
         int flag = 0;
         V_TRY(hipMemcpyAsync(sums, v.sums, sizeof(double) * C, hipMemcpyDeviceToHost, s));
-        V_TRY(hipMemcpyAsync(&flag, v.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-        V_TRY(hipStreamSynchronize(s));
+        V_TRY(read_to_host(&flag, v.flag, sizeof(int), s));
         if (flag) {
             set_error("|f - B g| reached 2^30 or is not finite: the Richardson steps diverge (step size too large)");
             return HDI_ERR_ARG;
