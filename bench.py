@@ -527,11 +527,24 @@ def main():
     # kernels run on), for the roofline entry
     L.hdi_stats_reset()
     L.hdi_stats_enable(1)
-    for _ in range(max(1, args.steps // 2)):
+    n_stat_steps = max(1, args.steps // 2)
+    for _ in range(n_stat_steps):
         step()
     torch.cuda.synchronize()
     L.hdi_stats_enable(0)
     ks = kernel_stats(L)
+    # every timed kernel class against the HBM peak (algorithmic bytes over its
+    # event time), and the whole step's algorithmic bytes over its wall time
+    per_kernel = {}
+    for k, (n, ms, by, fl) in ks.items():
+        if n and ms > 0:
+            per_kernel[k] = {"launches_per_step": round(n / n_stat_steps, 1), "ms_per_step": round(ms / n_stat_steps, 3),
+                             "avg_us": round(ms / n * 1e3, 1), "alg_GBps": round(by / (ms * 1e-3) / 1e9, 1),
+                             "hbm_frac": round(by / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                             "TFLOPs": round(fl / (ms * 1e-3) / 1e12, 2)}
+    step_bytes = sum(v[2] for v in ks.values()) / n_stat_steps
+    step_hbm = {"alg_bytes_per_step": round(step_bytes), "alg_GBps_over_wall": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+                "hbm_frac_over_wall": round(step_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     for k, (n, ms, by, fl) in ks.items():
         if n:
             log(f"  {k:18s} launches {n:6d}  total {ms:9.2f} ms  avg {ms / n * 1e3:8.1f} us  "
@@ -579,7 +592,8 @@ def main():
                    "tonal_ms": round(ms_tonal, 3), "inpaint_rounds": ri["outer_iters"],
                    "tonal_outer_iters": rt["outer_iters"], "tonal_inner_solves": rt["inner_solves"],
                    "mse_initial": round(rt["mse_initial"], 4), "mse_final": round(rt["mse_final"], 4)},
-        "roofline": roofline, "cpu_baseline": cpu, "copy_calibration": copy,
+        "roofline": roofline, "kernels": per_kernel, "step_hbm": step_hbm, "cpu_baseline": cpu,
+        "copy_calibration": copy,
         "densify": densify, "spatial": spatial, "comparators": comparators, "batch": batch, "serving": serving,
     }
     print(json.dumps(out), flush=True)
