@@ -478,7 +478,10 @@ int64_t hdi_block_count(int32_t width, int32_t height, int32_t overlap);
  * local CG step: stencil 5, two dot products 4, three vector updates 6; 20 per
  * pixel and local CGNR step of the tonal sweep). The tonal RAS sweep counts the
  * local steps it actually takes (a local CG stops at its FP32 residual floor);
- * the Schwarz smoother's figure assumes every configured step (an upper bound). */
+ * the Schwarz smoother's figure assumes every configured step (an upper bound).
+ * Id 5 counts the coarse recursion of each V-cycle by the finest level's
+ * per-launch bytes and FLOPs applied level by level; the launches of the FMG
+ * start, timed under the same id, carry no byte or FLOP count. */
 #define HDI_NUM_KERNEL_IDS 8
 void hdi_stats_enable(int32_t on);
 void hdi_stats_reset(void);

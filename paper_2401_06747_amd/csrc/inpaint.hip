@@ -182,6 +182,29 @@ bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, co
     return a.base == nullptr || a.used <= a.size;
 }
 
+// Algorithmic bytes and FLOPs of a V-cycle from level l down, with the
+// per-launch counts of the finest level applied to every level: pre-smoothing
+// N(1 + 8C) bytes, residual restriction N(1 + 8C) + Nc(1 + 4C), post-smoothing
+// N(1 + 12C) + 4C Nc, the coarsest level's smoothing N(1 + 8C); 15 FLOPs per
+// block pixel and local CG step.
+static void vcycle_cost(const Hierarchy &h, int l, const SolveCfg &cfg, double &bytes, double &flops) {
+    bytes = flops = 0.0;
+    const int C = h.C;
+    for (int k = l; k < h.nlev; ++k) {
+        const Level &L = h.lev[k];
+        const double N = (double)L.W * L.H;
+        const double blk_px = (double)L.bx.count * L.by.count * std::min(L.tile, L.W) * std::min(L.tile, L.H) * C;
+        if (k == h.nlev - 1) {
+            bytes += N * (1 + 8.0 * C);
+            flops += 15.0 * blk_px * cfg.coarse_iters;
+        } else {
+            const double Nc = (double)h.lev[k + 1].W * h.lev[k + 1].H;
+            bytes += 2.0 * N * (1 + 8.0 * C) + Nc * (1 + 4.0 * C) + N * (1 + 12.0 * C) + 4.0 * C * Nc;
+            flops += 2.0 * 15.0 * blk_px * cfg.local_iters;
+        }
+    }
+}
+
 // One V-cycle for A e = r on level l (r in lev[l].r); returns the buffer with e.
 // With `prof`, the finest level's launches are timed one by one and the whole
 // coarse recursion as one record.
@@ -200,7 +223,12 @@ static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Pr
     launch_smooth_pre(L, C, cfg.local_iters, L.ea, s);
     if (prof) { prof->end(s); prof->begin(3, N * (1 + 8.0 * C) + Nc * (1 + 4.0 * C), s); }
     launch_restrict_residual(L, Lc, C, L.ea, s);
-    if (prof) { prof->end(s); prof->begin(5, 0.0, s); }
+    if (prof) {
+        prof->end(s);
+        double cb = 0.0, cf = 0.0;
+        vcycle_cost(h, l + 1, cfg, cb, cf);
+        prof->begin(5, cb, s, cf);
+    }
     const float *ec = vcycle(h, l + 1, cfg, s);
     if (prof) { prof->end(s); prof->begin(2, N * (1 + 12.0 * C) + 4.0 * C * Nc, s, cg_flops); }
     launch_smooth_post(L, Lc, C, cfg.local_iters, L.ea, ec, L.eb, s);
