@@ -166,3 +166,27 @@ def test_small_tile_coarse_levels(shape, small_from):
     ref = oi.inpaint(inst.f, inst.mask)
     assert oi.rel_l2(u, ref).max() <= 1e-5
     assert oi.relres(u, inst.f, inst.mask).max() <= 1e-6 * 1.0001
+
+
+def test_side_stream_gives_identical_results():
+    """The library works on the caller's current stream, also one other than
+    the default: its host reads (convergence tests) poll that stream. Results
+    on a created stream equal those on the default stream bit for bit, for
+    inpainting and for the tonal optimisation."""
+    C, H, W = 3, 150, 210
+    f = synth.textured_image(H, W, C, 6, 31)
+    m = synth.gradient_mask(f, 0.04)
+    ft = torch.tensor(f, dtype=torch.float32, device=DEV).contiguous()
+    mt = torch.tensor(m, dtype=torch.uint8, device=DEV).contiguous()
+    u0, r0 = hdi.inpaint_solve(ft, mt)
+    g0, t0 = hdi.tonal_optimize(ft, mt)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        u1, r1 = hdi.inpaint_solve(ft, mt)
+        g1, t1 = hdi.tonal_optimize(ft, mt)
+    torch.cuda.synchronize()
+    assert r0["status"] == r1["status"] == 0 and t0["status"] == t1["status"] == 0
+    assert torch.equal(u0, u1) and r0["outer_iters"] == r1["outer_iters"]
+    assert torch.equal(g0, g1) and t0["outer_iters"] == t1["outer_iters"]
