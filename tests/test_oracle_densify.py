@@ -133,3 +133,65 @@ def test_schedule():
     assert g[-1] == 1000 and np.all(np.diff([100] + g) > 0)
     d = np.diff([100] + g)
     assert np.all(d[1:] >= d[:-1])
+
+
+def test_four_label_quad_splits_along_the_l0_l2_diagonal():
+    """S2: a quad q0=(x,y), q1=(x+1,y), q2=(x+1,y+1), q3=(x,y+1) with four distinct
+    labels gives the triangles {l0,l1,l2} and {l0,l2,l3}, never the other diagonal
+    ({l0,l1,l3}, {l1,l2,l3}). Labels are hand-placed, with seeds far from the quad."""
+    W, H = 12, 10
+    a, b, c, d = 1 * W + 1, 1 * W + 10, 8 * W + 9, 9 * W + 2      # four non-collinear seeds
+    for l0, l1, l2, l3 in [(a, b, c, d), (b, c, d, a), (d, a, b, c)]:
+        lab = np.full((H, W), a, np.int64)
+        lab[:, 6:] = b
+        lab[5:, 6:] = c
+        lab[5:, :6] = d
+        # the only quad with four labels is the one at (x, y) = (5, 4); put the
+        # requested labels on its corners
+        lab[4, 5], lab[4, 6], lab[5, 6], lab[5, 5] = l0, l1, l2, l3
+        tris = {tuple(t) for t in od.triangles(lab)}
+        four = {tuple(sorted((l0, l1, l2))), tuple(sorted((l0, l2, l3)))}
+        assert four <= tris
+        other = {tuple(sorted((l0, l1, l3))), tuple(sorted((l1, l2, l3)))}
+        # a triangle of the other diagonal may only appear if a 3-label quad made it
+        q = np.stack([lab[:-1, :-1].ravel(), lab[:-1, 1:].ravel(), lab[1:, 1:].ravel(), lab[1:, :-1].ravel()], 1)
+        from_three = {tuple(sorted(set(r))) for r in q if len(set(r)) == 3}
+        assert not ((other & tris) - from_three)
+
+
+def test_pixel_on_a_shared_edge_belongs_to_the_smaller_key():
+    """S3/S4: triangles are closed, so a pixel centre on the edge two triangles
+    share is covered by both, and the triangle with the smaller key owns it.
+    Seeds at the corners of a 5x5 image; the triangles (0, 4, 24) and (0, 20, 24)
+    share the diagonal from (0,0) to (4,4)."""
+    W = H = 5
+    a, b, c, d = 0, 4, 24, 20                 # (0,0), (4,0), (4,4), (0,4)
+    tris = np.array([[a, b, c], [a, d, c]], np.int64)
+    tris = np.sort(tris, axis=1)
+    assert tuple(tris[0]) < tuple(tris[1])
+    lab = np.full((H, W), a, np.int64)        # labels only matter for uncovered pixels
+    owner, ncells = od.ownership(lab, tris)
+    assert ncells == 2 + 1
+    for k in range(5):
+        assert owner[k, k] == 0               # on the shared diagonal: smaller key
+    assert owner[1, 3] == 0 and owner[3, 1] == 1      # strictly inside each triangle
+    assert owner[4, 0] == 1 and owner[0, 4] == 0      # corners d and b
+    # mirrored (x -> 4 - x): the triangles (0, 4, 20) and (4, 20, 24) share the
+    # anti-diagonal, which goes to the smaller key (0, 4, 20), the upper-left one
+    tris2 = np.array([[0, 4, 20], [4, 20, 24]], np.int64)
+    owner2, _ = od.ownership(np.zeros((H, W), np.int64), tris2)
+    for k in range(5):
+        assert owner2[k, 4 - k] == 0
+    assert owner2[1, 1] == 0 and owner2[3, 3] == 1
+
+
+def test_negative_zero_error_ties_with_zero():
+    """An error of -0.0 is a valid e >= 0 and equals 0: in a cell whose free
+    pixels all have zero error, the smallest index wins, whatever the sign bit."""
+    m = np.zeros((6, 6), np.uint8)
+    m[0, 0] = 1
+    err = np.zeros((6, 6), np.float32)
+    err[3, 3] = np.float32(-0.0)
+    err[5, 5] = np.float32(-0.0)
+    _, added, _ = od.densify_step(m, err, 1, "voronoi")
+    assert list(added) == [1]

@@ -181,3 +181,41 @@ def test_fs_dither_c_matches_python():
     rng = np.random.default_rng(11)
     p = rng.random((37, 53)) * 0.2
     np.testing.assert_array_equal(synth.fs_dither(p), synth._fs_python(p))
+
+
+def test_relres_of_zero_is_one_per_channel():
+    """The stopping measure is ||C f - A u|| / ||C f|| per channel (the relative
+    residual of eq. inp-discrete-lsi): at u = 0 the residual is C f itself, so
+    every channel gives exactly 1, whatever its scale."""
+    rng = np.random.default_rng(12)
+    m = _rand_mask(rng, 17, 23, 0.08)
+    f = np.stack([rng.uniform(0, 255, (17, 23)), 1e-3 * rng.uniform(0, 1, (17, 23)), rng.uniform(50, 60, (17, 23))])
+    assert np.array_equal(oi.relres(np.zeros_like(f), f, m), np.ones(3))
+
+
+def test_relres_of_one_pixel_perturbation_by_hand():
+    """u* + delta e_p at an unknown pixel p: A e_p has deg(p) in row p, -1 in the
+    rows of p's unknown 4-neighbours and nothing on the mask rows (they are
+    identity rows). So the residual norm is delta sqrt(deg(p)^2 + #unknown
+    neighbours), divided by ||C f|| of that channel only; the other channels
+    keep their (rounding-level) residual. A denominator of ||f||, or norms taken
+    over all channels together, fail this."""
+    H, W = 9, 11
+    m = np.zeros((H, W), np.uint8)
+    m[0, 0] = m[4, 8] = m[7, 2] = m[5, 5] = 1
+    rng = np.random.default_rng(13)
+    f = np.stack([rng.uniform(0, 255, (H, W)), rng.uniform(0, 255, (H, W))])
+    u = oi.inpaint(f, m)
+    delta = 0.5
+    cases = [((5, 4), 4, 3),    # interior, right neighbour (5,5) known
+             ((0, 1), 3, 2),    # top border, left neighbour (0,0) known
+             ((8, 10), 2, 2)]   # corner
+    for (y, x), deg, n_unknown in cases:
+        assert m[y, x] == 0
+        v = u.copy()
+        v[1, y, x] += delta
+        rr = oi.relres(v, f, m)
+        cf = np.linalg.norm(f[1][m != 0])
+        expect = delta * np.sqrt(deg * deg + n_unknown) / cf
+        assert abs(rr[1] - expect) <= 1e-9 * expect
+        assert rr[0] < 1e-12

@@ -143,3 +143,35 @@ def test_psnr_closed_form():
     in Sec. 6.3): an MSE of 255^2 / 100 is 20 dB, each 10x smaller MSE adds 10 dB."""
     assert abs(ot.psnr(255.0 ** 2 / 100) - 20.0) < 1e-12
     assert abs(ot.psnr(255.0 ** 2 / 1000) - 30.0) < 1e-12
+
+
+def test_normal_residual_of_zero_is_one():
+    """At g = 0 the normal residual B^T (f - B g) is B^T f itself, so the relative
+    measure is exactly 1 per channel."""
+    rng = np.random.default_rng(20)
+    m = _rand_mask(rng, 13, 17, 0.1)
+    f = np.stack([rng.uniform(0, 255, (13, 17)), 1e-2 * rng.uniform(0, 1, (13, 17))])
+    nr = ot.normal_residual(np.zeros_like(f), f, m)
+    np.testing.assert_allclose(nr, 1.0, rtol=1e-14)
+
+
+def test_normal_residual_closed_forms():
+    """Two masks where B is known in closed form (Sec. 5):
+    - full mask: B = I, so B^T (f - B g) = f - g and the measure is ||f - g|| / ||f||;
+    - one mask pixel k: B g is the constant image g_k and B^T y is the sum of y
+      placed at k, so the measure is |mean f - g_k| / |mean f|.
+    A residual taken before applying B^T (||f - B g|| / ||f||) fails the second."""
+    rng = np.random.default_rng(21)
+    f = rng.uniform(0, 255, (6, 8))
+    full = np.ones((6, 8), np.uint8)
+    g = f + rng.standard_normal(f.shape)
+    expect = np.linalg.norm(f - g) / np.linalg.norm(f)
+    np.testing.assert_allclose(ot.normal_residual(g, f, full), [expect], rtol=1e-12)
+    one = np.zeros((6, 8), np.uint8)
+    one[2, 5] = 1
+    g = np.zeros_like(f)
+    g[2, 5] = 17.0
+    expect = abs(f.mean() - 17.0) / abs(f.mean())
+    np.testing.assert_allclose(ot.normal_residual(g, f, one), [expect], rtol=1e-10)
+    # and the error bound there is N |mean f - g_k| (||B^T y|| = |sum y|)
+    np.testing.assert_allclose(ot.error_bound(g, f, one), [f.size * abs(f.mean() - 17.0)], rtol=1e-10)
