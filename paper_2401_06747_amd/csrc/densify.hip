@@ -316,8 +316,10 @@ __global__ void k_cells(int N, int T, const int *__restrict__ owner, const int *
     const unsigned long long q = (unsigned long long)rint(ldexp((double)e, 20));
     if (q) atomicAdd(&E[cell], q);
     if (!mask[i]) {
-        // larger error first, then smaller index; e >= 0 so its bits order like its value
-        const unsigned long long key = ((unsigned long long)__float_as_uint(e) << 32) | (0xFFFFFFFFu - (unsigned)i);
+        // larger error first, then smaller index; e >= 0 so its bits order like its value,
+        // once -0 (accepted as e >= 0, but with the sign bit set) is made +0
+        const unsigned eb = e == 0.f ? 0u : __float_as_uint(e);
+        const unsigned long long key = ((unsigned long long)eb << 32) | (0xFFFFFFFFu - (unsigned)i);
         atomicMax(&best[cell], key);
     }
 }

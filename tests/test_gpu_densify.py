@@ -82,6 +82,23 @@ def test_densification_loop_matches_oracle_at_every_step():
     assert int(mask.sum()) == sched[-1]
 
 
+def test_negative_zero_errors_tie_with_zero():
+    """-0.0 is an accepted error value equal to 0: cells whose free pixels all
+    carry zero error pick their smallest free index, whatever the sign bit."""
+    H, W = 40, 52
+    rng = np.random.default_rng(5)
+    m = np.zeros(H * W, np.uint8)
+    m[rng.choice(H * W, 30, replace=False)] = 1
+    m = m.reshape(H, W)
+    err = np.zeros((H, W), np.float32)
+    err[rng.random((H, W)) < 0.3] = np.float32(-0.0)
+    # a few cells with positive errors so the ranking has something to order
+    err[rng.random((H, W)) < 0.02] = 3.0
+    err[m != 0] = 0
+    for partition in (hdi.DELAUNAY, hdi.VORONOI):
+        _compare(m, err, 25, partition)
+
+
 def test_errors():
     m = torch.zeros((8, 8), dtype=torch.uint8, device=DEV)
     e = torch.zeros((8, 8), dtype=torch.float32, device=DEV)
