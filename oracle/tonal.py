@@ -13,10 +13,14 @@ mask (Sec. 1) and every method converges to the same values (Sec. 6.3).
 
 B g and B^T y are applied by their definitions, B g = A^{-1}(C g) and
 B^T y = C A^{-T} y, with one SuperLU factorisation of A reused for both.
-For grids too large for a direct factorisation the symmetric reduced form is
-used instead (Sec. 5.1, symmetrised system): B g equals g on K and solves
+For grids too large for that factorisation the symmetric reduced form is used
+instead (Sec. 5.1, symmetrised system): B g equals g on K and solves
 L_UU u_U = -L_UK g_K on U, and B^T y equals y_K - L_KU z_U on K with
-L_UU z_U = y_U, solved by conjugate gradients to a tight tolerance.
+L_UU z_U = y_U, solved with one factorisation of L_UU (or, on request, by
+conjugate gradients to a tight tolerance).
+
+The operators take one channel as a length-N vector or several channels as the
+columns of an N x C array; the channels never mix.
 """
 from __future__ import annotations
 
@@ -27,7 +31,9 @@ from .inpaint import DIRECT_LIMIT, ReducedSystem, _as_chw, _check_mask, system_m
 
 
 class TonalOperator:
-    """B and B^T for one mask, acting on flat length-N vectors."""
+    """B and B^T for one mask, acting on flat length-N vectors or N x C arrays.
+    method: "direct" (factor A itself), "reduced" (factor L_UU), "cg" (reduced
+    form with conjugate gradients), "auto" (direct up to DIRECT_LIMIT pixels)."""
 
     def __init__(self, mask: np.ndarray, method: str = "auto"):
         self.shape = mask.shape
@@ -35,52 +41,67 @@ class TonalOperator:
         self.c = self.K.astype(np.float64)
         N = mask.size
         if method == "auto":
-            method = "direct" if N <= DIRECT_LIMIT else "cg"
+            method = "direct" if N <= DIRECT_LIMIT else "reduced"
         self.method = method
         if method == "direct":
             self.lu = spla.splu(system_matrix(mask).tocsc())
         else:
-            self.rs = ReducedSystem(mask, "cg")
+            self.rs = ReducedSystem(mask, "cg" if method == "cg" else "direct")
+
+    def _cols(self, fn, x):
+        # the CG fallback solves one right-hand side at a time
+        if x.ndim == 1 or self.method != "cg":
+            return fn(x)
+        return np.stack([fn(x[:, j]) for j in range(x.shape[1])], axis=1)
 
     def B(self, g: np.ndarray) -> np.ndarray:
         """u = A^{-1} C g."""
         if self.method == "direct":
-            return self.lu.solve(self.c * g)
-        return self.rs.solve(g)
+            cg = self.c * g if g.ndim == 1 else self.c[:, None] * g
+            return self.lu.solve(np.ascontiguousarray(cg))
+        rs = self.rs
+        u = np.zeros_like(g, dtype=np.float64)
+        u[rs.K] = g[rs.K]
+        u[rs.U] = self._cols(rs.solve_UU, -(rs.LUK @ g[rs.K]))
+        return u
 
     def Bt(self, y: np.ndarray) -> np.ndarray:
         """C A^{-T} y (zero off the mask)."""
         if self.method == "direct":
-            return self.c * self.lu.solve(np.ascontiguousarray(y, dtype=np.float64), trans="T")
+            z = self.lu.solve(np.ascontiguousarray(y, dtype=np.float64), trans="T")
+            return self.c * z if z.ndim == 1 else self.c[:, None] * z
         rs = self.rs
-        z = np.zeros_like(y)
-        zU = rs.solve_UU(y[rs.U])
+        z = np.zeros_like(y, dtype=np.float64)
+        zU = self._cols(rs.solve_UU, np.ascontiguousarray(y[rs.U], dtype=np.float64))
         z[rs.K] = y[rs.K] - rs.LKU @ zU
         return z
 
     def normal(self, gK: np.ndarray) -> np.ndarray:
         """(B^T B) restricted to the mask entries."""
-        g = np.zeros(self.K.size)
+        g = np.zeros((self.K.size,) + gK.shape[1:])
         g[self.K] = gK
         return self.Bt(self.B(g))[self.K]
 
 
 def _cg(matvec, rhs, x0, rtol, maxiter):
-    """Textbook conjugate gradients for a symmetric positive definite operator."""
+    """Textbook conjugate gradients for a symmetric positive definite operator.
+    rhs and x0 may hold several independent systems as columns: each column
+    keeps its own step sizes and stops on its own residual."""
     x = x0.copy()
     r = rhs - matvec(x)
     p = r.copy()
-    rr = r @ r
-    stop = (rtol * np.linalg.norm(rhs)) ** 2
+    rr = (r * r).sum(axis=0)
+    stop = (rtol * np.sqrt((rhs * rhs).sum(axis=0))) ** 2
     it = 0
-    while rr > stop and it < maxiter:
+    while np.any(rr > stop) and it < maxiter:
+        act = rr > stop                       # columns still iterating
         q = matvec(p)
-        a = rr / (p @ q)
+        a = np.where(act, rr / np.where(act, (p * q).sum(axis=0), 1.0), 0.0)
         x += a * p
         r -= a * q
-        rr_new = r @ r
-        p = r + (rr_new / rr) * p
-        rr = rr_new
+        rr_new = (r * r).sum(axis=0)
+        p = r + np.where(act, rr_new / np.where(act, rr, 1.0), 0.0) * p
+        rr = np.where(act, rr_new, rr)
         it += 1
     return x, it
 
@@ -88,18 +109,16 @@ def _cg(matvec, rhs, x0, rtol, maxiter):
 def tonal_optimize(f: np.ndarray, mask: np.ndarray, rtol: float = 1e-12, maxiter: int = 5000,
                    method: str = "auto") -> np.ndarray:
     """g* per channel by CG on the normal equations restricted to K, started at
-    g = f on K (the usual start, Sec. 5.3). Returns (C,H,W) with zeros off K."""
+    g = f on K (the usual start, Sec. 5.3). The channels are independent
+    systems, iterated side by side. Returns (C,H,W) with zeros off K."""
     f = _as_chw(f)
     op = TonalOperator(mask, method)
-    out = []
-    for fc in f:
-        fl = fc.ravel()
-        rhs = op.Bt(fl)[op.K]
-        gK, _ = _cg(op.normal, rhs, fl[op.K].copy(), rtol, maxiter)
-        g = np.zeros(fl.size)
-        g[op.K] = gK
-        out.append(g.reshape(mask.shape))
-    return np.stack(out)
+    F = np.stack([fc.ravel() for fc in f], axis=1)          # N x C
+    rhs = op.Bt(F)[op.K]
+    gK, _ = _cg(op.normal, rhs, F[op.K].copy(), rtol, maxiter)
+    g = np.zeros_like(F)
+    g[op.K] = gK
+    return np.stack([g[:, c].reshape(mask.shape) for c in range(f.shape[0])])
 
 
 def tonal_dense(f: np.ndarray, mask: np.ndarray) -> np.ndarray:
@@ -124,7 +143,8 @@ def reconstruct(g: np.ndarray, mask: np.ndarray, method: str = "auto") -> np.nda
     """B g per channel, (C,H,W)."""
     g = _as_chw(g)
     op = TonalOperator(mask, method)
-    return np.stack([op.B(gc.ravel()).reshape(mask.shape) for gc in g])
+    u = op.B(np.stack([gc.ravel() for gc in g], axis=1))
+    return np.stack([u[:, c].reshape(mask.shape) for c in range(g.shape[0])])
 
 
 def mse(g: np.ndarray, f: np.ndarray, mask: np.ndarray, method: str = "auto") -> float:
@@ -139,21 +159,23 @@ def psnr(m: float) -> float:
     return float(10.0 * np.log10(255.0 ** 2 / m))
 
 
-def normal_residual(g: np.ndarray, f: np.ndarray, mask: np.ndarray, method: str = "auto") -> np.ndarray:
-    """||B^T (f - B g)|| / ||B^T f|| per channel (relative normal-equation residual)."""
+def _normal_parts(g, f, mask, method):
     g, f = _as_chw(g), _as_chw(f)
     op = TonalOperator(mask, method)
-    out = []
-    for gc, fc in zip(g, f):
-        fl = fc.ravel()
-        r = op.Bt(fl - op.B(gc.ravel()))
-        out.append(np.linalg.norm(r) / max(np.linalg.norm(op.Bt(fl)), 1e-300))
-    return np.array(out)
+    G = np.stack([gc.ravel() for gc in g], axis=1)
+    F = np.stack([fc.ravel() for fc in f], axis=1)
+    return op, G, F
+
+
+def normal_residual(g: np.ndarray, f: np.ndarray, mask: np.ndarray, method: str = "auto") -> np.ndarray:
+    """||B^T (f - B g)|| / ||B^T f|| per channel (relative normal-equation residual)."""
+    op, G, F = _normal_parts(g, f, mask, method)
+    r = np.linalg.norm(op.Bt(F - op.B(G)), axis=0)
+    return r / np.maximum(np.linalg.norm(op.Bt(F), axis=0), 1e-300)
 
 
 def error_bound(g: np.ndarray, f: np.ndarray, mask: np.ndarray, method: str = "auto") -> np.ndarray:
     """Certificate: on K, B^T B = I + (positive semi-definite), so its smallest
     eigenvalue is at least 1 and ||g - g*|| <= ||B^T (f - B g)|| per channel."""
-    g, f = _as_chw(g), _as_chw(f)
-    op = TonalOperator(mask, method)
-    return np.array([np.linalg.norm(op.Bt(fc.ravel() - op.B(gc.ravel()))) for gc, fc in zip(g, f)])
+    op, G, F = _normal_parts(g, f, mask, method)
+    return np.linalg.norm(op.Bt(F - op.B(G)), axis=0)

@@ -219,3 +219,19 @@ def test_relres_of_one_pixel_perturbation_by_hand():
         expect = delta * np.sqrt(deg * deg + n_unknown) / cf
         assert abs(rr[1] - expect) <= 1e-9 * expect
         assert rr[0] < 1e-12
+
+
+def test_nested_dissection_is_a_permutation_and_solves_match():
+    """The direct solver's fill-reducing order is a permutation of the pixels, and
+    the solution does not depend on it (compared with SuperLU's own column order)."""
+    import scipy.sparse.linalg as spla
+    for H, W in [(1, 1), (1, 37), (29, 1), (17, 23), (64, 65)]:
+        p = oi.nested_dissection(H, W)
+        assert np.array_equal(np.sort(p), np.arange(H * W))
+    rng = np.random.default_rng(14)
+    m = _rand_mask(rng, 41, 53, 0.04)
+    f = rng.uniform(0, 255, (41, 53))
+    rs = oi.ReducedSystem(m)
+    b = -(rs.LUK @ f.ravel()[rs.K])
+    ref = spla.splu(rs.LUU.tocsc()).solve(b)
+    np.testing.assert_allclose(rs.solve_UU(b), ref, rtol=0, atol=1e-10 * np.abs(ref).max())

@@ -98,6 +98,13 @@ def test_bt_definition_matches_reduced_gather():
     direct = ot.TonalOperator(m, "direct").Bt(y)
     reduced = ot.TonalOperator(m, "cg").Bt(y)
     np.testing.assert_allclose(direct, reduced, atol=1e-9)
+    np.testing.assert_allclose(direct, ot.TonalOperator(m, "reduced").Bt(y), atol=1e-11)
+    g = rng.standard_normal(m.size) * (m.ravel() != 0)
+    np.testing.assert_allclose(ot.TonalOperator(m, "direct").B(g), ot.TonalOperator(m, "reduced").B(g), atol=1e-11)
+    # several channels as columns give the same as one at a time
+    Y = rng.standard_normal((m.size, 3))
+    op = ot.TonalOperator(m, "reduced")
+    np.testing.assert_allclose(op.Bt(Y), np.stack([op.Bt(Y[:, j]) for j in range(3)], 1), atol=1e-12)
     # gather written out by neighbours
     rs = oi.ReducedSystem(m)
     z = np.zeros(m.size)
