@@ -35,11 +35,18 @@ class TonalOperator:
     method: "direct" (factor A itself), "reduced" (factor L_UU), "cg" (reduced
     form with conjugate gradients), "auto" (direct up to DIRECT_LIMIT pixels)."""
 
-    def __init__(self, mask: np.ndarray, method: str = "auto"):
+    def __init__(self, mask: np.ndarray, method: str = "auto", system: ReducedSystem | None = None):
         self.shape = mask.shape
         self.K = _check_mask(mask)
         self.c = self.K.astype(np.float64)
         N = mask.size
+        if system is not None:
+            # reuse a factorised reduced system of this same mask
+            if system.H * system.W != N or not np.array_equal(system.K, self.K):
+                raise ValueError("the given reduced system belongs to another mask")
+            self.method = "cg" if system.lu is None else "reduced"
+            self.rs = system
+            return
         if method == "auto":
             method = "direct" if N <= DIRECT_LIMIT else "reduced"
         self.method = method
@@ -179,3 +186,35 @@ def error_bound(g: np.ndarray, f: np.ndarray, mask: np.ndarray, method: str = "a
     eigenvalue is at least 1 and ||g - g*|| <= ||B^T (f - B g)|| per channel."""
     op, G, F = _normal_parts(g, f, mask, method)
     return np.linalg.norm(op.Bt(F - op.B(G)), axis=0)
+
+
+def certificate(g: np.ndarray, f: np.ndarray, mask: np.ndarray, steps: int = 0,
+                op: TonalOperator | None = None) -> dict:
+    """Rigorous bounds on the distance of g from the optimum g*, per channel.
+
+    With M = B^T B restricted to K (smallest eigenvalue at least 1) and the
+    normal residual r = B^T (f - B g) on K, the error e = g - g* solves
+    M e = -r. For any estimate e_h of e, ||e - e_h|| <= ||M (e - e_h)||
+    = ||-r - M e_h||, hence ||e|| <= ||e_h|| + ||r + M e_h||. With steps = 0
+    (e_h = 0) this is the plain bound ||e|| <= ||r||; steps > 0 takes e_h from
+    that many conjugate-gradient steps on M e_h = -r started at zero, which
+    tightens the bound when r is dominated by large eigenvalues of M.
+
+    The MSE excess follows from e^T M e = r^T M^{-1} r <= ||r|| ||e||:
+    MSE(g) - MSE(g*) <= sum_c ||r_c|| E_c / (C N), with E_c the error bound.
+
+    Returns per-channel arrays 'normal_residual' (||r||), 'error_bound' (E),
+    'g_norm' (||g_K||) and the scalar 'mse_excess_bound'."""
+    f, g = _as_chw(f), _as_chw(g)
+    if op is None:
+        op = TonalOperator(mask)
+    G = np.stack([gc.ravel() for gc in g], axis=1)
+    F = np.stack([fc.ravel() for fc in f], axis=1)
+    r = op.Bt(F - op.B(G))[op.K]
+    rn = np.linalg.norm(r, axis=0)
+    E = rn.copy()
+    if steps > 0:
+        eh, _ = _cg(op.normal, -r, np.zeros_like(r), 0.0, steps)
+        E = np.minimum(E, np.linalg.norm(eh, axis=0) + np.linalg.norm(r + op.normal(eh), axis=0))
+    return {"normal_residual": rn, "error_bound": E, "g_norm": np.linalg.norm(G[op.K], axis=0),
+            "mse_excess_bound": float((rn * E).sum() / F.size)}

@@ -182,3 +182,71 @@ def test_normal_residual_closed_forms():
     np.testing.assert_allclose(ot.normal_residual(g, f, one), [expect], rtol=1e-10)
     # and the error bound there is N |mean f - g_k| (||B^T y|| = |sum y|)
     np.testing.assert_allclose(ot.error_bound(g, f, one), [f.size * abs(f.mean() - 17.0)], rtol=1e-10)
+
+
+def test_certificate_bounds_the_true_error_of_perturbed_optima():
+    """certificate(): against the brute-force optimum (dense lstsq) of a small
+    RGB image, for g = g* + d with d on the mask:
+    - steps = 0 gives ||r|| with r = B^T (f - B g), and it bounds ||d||;
+    - more CG steps tighten the bound but never below ||d||;
+    - with as many steps as mask pixels the bound is ||d|| itself;
+    - the MSE excess d^T (B^T B) d / (C N) (computed densely) stays below its bound.
+    A bound that dropped the residual term of the estimate, or used B instead of
+    B^T B, falls below ||d|| for some of these perturbations."""
+    rng = np.random.default_rng(31)
+    H, W = 14, 17
+    m = _rand_mask(rng, H, W, 0.08)
+    f = rng.uniform(0, 255, (3, H, W))
+    gs = ot.tonal_dense(f, m)
+    K = m.ravel() != 0
+    A = oi.system_matrix(m).toarray()
+    Bd = np.linalg.solve(A, np.eye(m.size)[:, K])
+    M = Bd.T @ Bd
+    for scale, kind in [(1e-3, "smooth"), (1e-1, "rough")]:
+        d = np.zeros_like(gs)
+        for c in range(3):
+            v = rng.standard_normal(int(K.sum()))
+            if kind == "smooth":   # along the smallest eigenvectors of M (slow to resolve)
+                w, V = np.linalg.eigh(M)
+                v = V[:, :3] @ rng.standard_normal(3)
+            d[c].ravel()[K] = scale * v
+        g = gs + d
+        dn = np.array([np.linalg.norm(d[c].ravel()[K]) for c in range(3)])
+        c0 = ot.certificate(g, f, m)
+        rK = np.stack([Bd.T @ (f[c].ravel() - Bd @ g[c].ravel()[K]) for c in range(3)], axis=1)
+        np.testing.assert_allclose(c0["normal_residual"], np.linalg.norm(rK, axis=0), rtol=1e-8)
+        np.testing.assert_allclose(c0["error_bound"], c0["normal_residual"], rtol=0)
+        assert np.all(c0["error_bound"] >= dn * (1 - 1e-9))
+        prev = c0["error_bound"]
+        for steps in (1, 3, 8):
+            ck = ot.certificate(g, f, m, steps=steps)
+            assert np.all(ck["error_bound"] >= dn * (1 - 1e-9)), (steps, ck["error_bound"], dn)
+            assert np.all(ck["error_bound"] <= prev * (1 + 1e-12))
+        full = ot.certificate(g, f, m, steps=int(K.sum()) + 5)
+        np.testing.assert_allclose(full["error_bound"], dn, rtol=1e-6)
+        excess = sum(d[c].ravel()[K] @ M @ d[c].ravel()[K] for c in range(3)) / f.size
+        assert excess <= full["mse_excess_bound"] * (1 + 1e-9)
+        assert excess <= c0["mse_excess_bound"] * (1 + 1e-9)
+        # (a difference of two MSEs near 1e3: absolute rounding about 1e-12)
+        np.testing.assert_allclose(ot.mse(g, f, m) - ot.mse(gs, f, m), excess, rtol=1e-6, atol=1e-10)
+
+
+def test_tonal_operator_reuses_a_factored_system():
+    """A TonalOperator built on a given ReducedSystem applies the same B and B^T
+    as one that factors its own; a system of another mask is refused."""
+    rng = np.random.default_rng(32)
+    m = _rand_mask(rng, 30, 41, 0.05)
+    rs = oi.ReducedSystem(m)
+    a = ot.TonalOperator(m, system=rs)
+    b = ot.TonalOperator(m, method="direct")
+    y = rng.standard_normal((m.size, 3))
+    np.testing.assert_allclose(a.B(y), b.B(y), rtol=1e-10, atol=1e-9)
+    np.testing.assert_allclose(a.Bt(y), b.Bt(y), rtol=1e-10, atol=1e-9)
+    other = m.copy()
+    other[0, 0] ^= 1
+    try:
+        ot.TonalOperator(other, system=rs)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("a system of another mask was accepted")
