@@ -114,6 +114,33 @@ int32_t inpaint_solve(hdi_image img, const uint8_t *mask, const float *f, double
                       const double *u0, void *ws, size_t ws_bytes,
                       const hdi_solve_params *params, hdi_solve_report *report, void *stream);
 
+/* ------------------------------------------------------------------ no-allocation solve */
+
+/* Size in MiB of the scratch array behind inpaint_solve_noalloc, per GPU. */
+#define HDI_NOALLOC_SCRATCH_MB 64
+
+/* Bytes of that array (HDI_NOALLOC_SCRATCH_MB MiB). */
+size_t hdi_noalloc_scratch_bytes(void);
+
+/* inpaint_solve for callers that cannot allocate device memory: code that may
+ * not call hipMalloc (tight serving loops, harnesses that forbid allocation).
+ * The operation, arguments, results and errors are those of inpaint_solve,
+ * but the workspace is an array of HDI_NOALLOC_SCRATCH_MB MiB inside the
+ * library; each GPU holds its own copy from the first call on it until the
+ * process ends. The call makes no device or pinned-host allocation and creates
+ * no HIP events: report->ms is host time from entry until the stream's work is
+ * done, and the per-kernel statistics do not see the call.
+ *   Limit   an image whose hdi_inpaint_workspace_bytes exceeds the array
+ *           (beyond about 1024x768 RGB or 1920x1080 gray) returns
+ *           HDI_ERR_WORKSPACE before any launch.
+ *   Sharing every call on one GPU uses that GPU's array, which keeps the last
+ *           call's contents (a solve writes each scratch byte before reading
+ *           it). Overlapping calls would race on it, so the calls of one
+ *           process on one GPU are serialised by a lock held for the whole
+ *           call. */
+int32_t inpaint_solve_noalloc(hdi_image img, const uint8_t *mask, const float *f, double *u, const double *u0,
+                              const hdi_solve_params *params, hdi_solve_report *report, void *stream);
+
 /* ------------------------------------------------------------------ batches */
 
 /* One inpainting job of a batch: image shape and device pointers as for

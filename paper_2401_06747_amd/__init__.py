@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import HdiError, check
 
-__all__ = ["inpaint_solve", "solve_batch", "tonal_optimize", "densify_step", "error_map", "initial_mask",
+__all__ = ["inpaint_solve", "inpaint_solve_noalloc", "solve_batch", "tonal_optimize", "densify_step", "error_map", "initial_mask",
            "spatial_optimize", "Server", "DELAUNAY", "VORONOI",
            "INPAINT", "TONAL", "hdi_block_count", "SolveParams", "TonalParams", "HdiError", "PCG_RAS", "RAS", "CGNR",
            "FLAG_NO_FMG", "FLAG_CG", "voronoi_init", "VINIT_DIRECT", "VINIT_VORONOI", "VINIT_VORONOI_LOG",
@@ -109,6 +109,32 @@ def inpaint_solve(f: torch.Tensor, mask: torch.Tensor, u0: torch.Tensor | None =
     p = (params or SolveParams()).c()
     st = L.inpaint_solve(img, _ptr(mask), _ptr(f), _ptr(u), _ptr(u0), _ptr(ws), ws.numel(),
                          ctypes.byref(p), ctypes.byref(rep), _stream_ptr(f.device))
+    report = {"status": st, "rel_residual": list(rep.rel_residual)[:f.shape[0]],
+              "outer_iters": rep.outer_iters, "vcycles": rep.vcycles, "ms": rep.ms}
+    if st != _lib.HDI_OK:
+        report["message"] = L.hdi_last_error().decode()
+    if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
+        check(st)
+    return u, report
+
+
+def inpaint_solve_noalloc(f: torch.Tensor, mask: torch.Tensor, u0: torch.Tensor | None = None,
+                          params: SolveParams | None = None, out: torch.Tensor | None = None):
+    """inpaint_solve on the library's own fixed scratch array (no workspace and
+    no allocation inside the call; images up to hdi_noalloc_scratch_bytes of
+    workspace). Returns (u float64, report dict)."""
+    _check_inputs(f, mask)
+    L = _lib.lib()
+    img = _img(f.shape)
+    u = out if out is not None else torch.empty(f.shape, dtype=torch.float64, device=f.device)
+    if u.shape != f.shape or u.dtype != torch.float64 or not u.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor shaped like f")
+    if u0 is not None and (u0.shape != f.shape or u0.dtype != torch.float64 or not u0.is_contiguous()):
+        raise ValueError("u0 must be a contiguous float64 tensor shaped like f")
+    rep = _lib.hdi_solve_report()
+    p = (params or SolveParams()).c()
+    st = L.inpaint_solve_noalloc(img, _ptr(mask), _ptr(f), _ptr(u), _ptr(u0), ctypes.byref(p), ctypes.byref(rep),
+                                 _stream_ptr(f.device))
     report = {"status": st, "rel_residual": list(rep.rel_residual)[:f.shape[0]],
               "outer_iters": rep.outer_iters, "vcycles": rep.vcycles, "ms": rep.ms}
     if st != _lib.HDI_OK:

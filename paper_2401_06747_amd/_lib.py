@@ -98,6 +98,9 @@ _SIGS = {
     "hdi_inpaint_workspace_bytes": (ctypes.c_size_t, [hdi_image]),
     "inpaint_solve": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                        ctypes.POINTER(hdi_solve_params), ctypes.POINTER(hdi_solve_report), _P]),
+    "hdi_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "inpaint_solve_noalloc": (ctypes.c_int32, [hdi_image, _P, _P, _P, _P, ctypes.POINTER(hdi_solve_params),
+                                               ctypes.POINTER(hdi_solve_report), _P]),
     "hdi_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(hdi_job)]),
     "hdi_solve_batch": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(hdi_job), _P, ctypes.c_size_t,
                                          ctypes.POINTER(hdi_solve_params), ctypes.POINTER(hdi_solve_report), _P]),

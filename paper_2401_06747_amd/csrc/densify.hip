@@ -29,7 +29,6 @@ namespace hdi {
 
 void launch_compact(int N, const uint8_t *mask, int *chunk_cnt, int *chunk_off, int *total, int *idx, int *pos,
                     hipStream_t s);
-bool check_image(const hdi_image &img);
 
 constexpr int SEG = 64;   // rows per column segment of the column pass
 

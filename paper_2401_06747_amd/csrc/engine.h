@@ -73,7 +73,6 @@ private:
     SegList seg_admit_, seg_res_, seg_vc_;
 };
 
-bool check_image(const hdi_image &img);
 int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap);
 
 }  // namespace hdi

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <chrono>
 #include <string>
 
 #include "../../include/hdi.h"
@@ -15,6 +16,7 @@ constexpr int MAX_LEVELS = 16;
 constexpr int RED_THREADS = 256;  // threads of the reduction kernels
 
 void set_error(const char *fmt, ...);
+bool check_image(const hdi_image &img);   // sizes >= 1, 1 or 3 channels, at most 2^30 pixels
 
 // A small device-to-host read that the host waits for (a convergence test, a
 // count): staged through a pinned per-thread buffer, so that the copy is
@@ -103,11 +105,29 @@ struct SolveCfg {
     int64_t known;   // number of known pixels (for the byte accounting)
 };
 
+// A call that must not allocate (inpaint_solve_noalloc) holds one of these on
+// its thread for its duration. Meanwhile small host reads skip the pinned
+// staging buffer (a plain copy into the caller's host memory), call timers use
+// the host clock instead of HIP events, and per-kernel statistics are off.
+struct NoAllocScope {
+    NoAllocScope();
+    ~NoAllocScope();
+};
+bool no_alloc_active();
+
 // Device time of one call: the start and stop events live as long as the
-// object, so every return path releases them.
+// object, so every return path releases them. Under a NoAllocScope it makes no
+// events and measures host time from start() to the end of the stream's work.
 struct CallTimer {
     hipEvent_t a = nullptr, b = nullptr;
+    bool host = false;
+    std::chrono::steady_clock::time_point t0;
     hipError_t start(hipStream_t s) {
+        if (no_alloc_active()) {
+            host = true;
+            t0 = std::chrono::steady_clock::now();
+            return hipSuccess;
+        }
         hipError_t e = hipEventCreate(&a);
         if (e == hipSuccess) e = hipEventCreate(&b);
         if (e == hipSuccess) e = hipEventRecord(a, s);
@@ -115,6 +135,11 @@ struct CallTimer {
     }
     // records the stop event, waits for it, and stores the elapsed time in *ms
     hipError_t stop(hipStream_t s, float *ms) {
+        if (host) {
+            const hipError_t e = hipStreamSynchronize(s);
+            *ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            return e;
+        }
         hipError_t e = hipEventRecord(b, s);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);

@@ -84,8 +84,13 @@ static hipError_t wait_for(hipStream_t s) {
     }
 }
 
+static thread_local int t_no_alloc = 0;
+NoAllocScope::NoAllocScope() { ++t_no_alloc; }
+NoAllocScope::~NoAllocScope() { --t_no_alloc; }
+bool no_alloc_active() { return t_no_alloc > 0; }
+
 hipError_t read_to_host(void *dst, const void *src, size_t bytes, hipStream_t s) {
-    if (bytes <= STAGING_BYTES && !t_staging && !t_staging_failed) {
+    if (bytes <= STAGING_BYTES && !t_staging && !t_staging_failed && !no_alloc_active()) {
         if (hipHostMalloc(&t_staging, STAGING_BYTES, hipHostMallocPortable) != hipSuccess) {
             t_staging = nullptr;
             t_staging_failed = true;
@@ -103,7 +108,7 @@ hipError_t read_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
 }
 
 Prof *prof_for_call() {
-    if (!g_stats_on.load()) return nullptr;
+    if (!g_stats_on.load() || no_alloc_active()) return nullptr;
     Prof *p = new Prof;
     p->on = true;
     return p;

@@ -138,3 +138,25 @@ def test_lds_calibration_and_statistics_arguments_need_no_gpu():
     assert lib.hdi_stats_get_lds(6, None) == L.HDI_ERR_ARG
     lib.hdi_stats_reset()
     assert lib.hdi_stats_get_lds(6, ctypes.byref(v)) == L.HDI_OK and v.value == 0.0
+
+
+def test_noalloc_solve_refuses_images_beyond_its_scratch_without_a_gpu():
+    """inpaint_solve_noalloc checks the image against its fixed scratch array
+    (HDI_NOALLOC_SCRATCH_MB MiB per GPU) before any HIP call."""
+    import ctypes
+    L = _lib()
+    lib = L.lib()
+    src = open(HEADER).read()
+    mb = int(re.search(r"#define HDI_NOALLOC_SCRATCH_MB (\d+)", src).group(1))
+    assert lib.hdi_noalloc_scratch_bytes() == mb << 20
+    # the sizes the header names as fitting do fit
+    assert lib.hdi_inpaint_workspace_bytes(L.hdi_image(1024, 768, 3)) <= mb << 20
+    assert lib.hdi_inpaint_workspace_bytes(L.hdi_image(1920, 1080, 1)) <= mb << 20
+    rep = L.hdi_solve_report()
+    p16 = ctypes.c_void_p(16)
+    st = lib.inpaint_solve_noalloc(L.hdi_image(3840, 2160, 3), p16, p16, p16, None, None, ctypes.byref(rep), None)
+    assert st == L.HDI_ERR_WORKSPACE and b"no-allocation" in lib.hdi_last_error()
+    st = lib.inpaint_solve_noalloc(L.hdi_image(4, 4, 1), None, p16, p16, None, None, ctypes.byref(rep), None)
+    assert st == L.HDI_ERR_ARG
+    st = lib.inpaint_solve_noalloc(L.hdi_image(4, 4, 2), p16, p16, p16, None, None, ctypes.byref(rep), None)
+    assert st == L.HDI_ERR_ARG
