@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/hdi.h"
+#include "arena.h"
 
 namespace hdi {
 
@@ -26,25 +27,8 @@ bool check_image(const hdi_image &img);   // sizes >= 1, 1 or 3 channels, at mos
 // HIP error.
 hipError_t read_to_host(void *dst, const void *src, size_t bytes, hipStream_t s);
 
-// Geometry of the overlapping tile x tile blocks along one dimension (Sec. 3.1, 3.3).
-struct Blocks1D {
-    int n;       // pixels along the dimension
-    int count;   // number of blocks
-    int stride;  // start of block i is min(i*stride, n-tile)
-};
-
-inline Blocks1D make_blocks(int n, int overlap, int tile = TILE) {
-    Blocks1D b;
-    b.n = n;
-    if (n <= tile) {
-        b.count = 1;
-        b.stride = tile;
-    } else {
-        b.stride = tile - overlap;
-        b.count = (n - tile + b.stride - 1) / b.stride + 1;
-    }
-    return b;
-}
+// Blocks of the fine-level TILE x TILE smoother along one dimension.
+inline Blocks1D make_blocks(int n, int overlap) { return make_blocks(n, overlap, TILE); }
 
 struct Level {
     int W, H;
@@ -54,19 +38,6 @@ struct Level {
     float *r;        // right-hand side of the correction equation, C x H x W
     float *ea, *eb;  // correction ping-pong buffers, C x H x W
     float *aux;      // FMG: restricted data on this level, C x H x W
-};
-
-// Bump allocator over the caller's workspace.
-struct Arena {
-    char *base;
-    size_t size, used;
-    void *take(size_t bytes) {
-        size_t off = (used + 255) & ~size_t(255);
-        if (!base) { used = off + bytes; return nullptr; }
-        if (off + bytes > size) return nullptr;
-        used = off + bytes;
-        return base + off;
-    }
 };
 
 // A laid-out multigrid hierarchy for one image shape.

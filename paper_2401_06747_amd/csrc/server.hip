@@ -24,54 +24,6 @@
 
 namespace hdi {
 
-static size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
-
-// First-fit allocator over the caller's arena; blocks are 256-byte aligned and
-// neighbouring free blocks merge on release.
-class ArenaAlloc {
-public:
-    void init(char *base, size_t size) {
-        base_ = base;
-        size_ = size;
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    size_t capacity() const { return size_; }
-    char *alloc(size_t n) {
-        n = up256(n);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n) continue;
-            const size_t off = it->first, len = it->second;
-            free_.erase(it);
-            if (len > n) free_[off + n] = len - n;
-            return base_ + off;
-        }
-        return nullptr;
-    }
-    void release(char *p, size_t n) {
-        n = up256(n);
-        size_t off = (size_t)(p - base_);
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + n == next->first) {
-            n += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += n;
-                return;
-            }
-        }
-        free_[off] = n;
-    }
-
-private:
-    char *base_ = nullptr;
-    size_t size_ = 0;
-    std::map<size_t, size_t> free_;   // offset -> bytes
-};
-
 struct Ticket {
     uint64_t id = 0;
     hdi_request req{};
@@ -175,6 +127,14 @@ struct hdi_server {
         return HDI_OK;
     }
 
+    // Before a failed request's arena block goes back to the allocator: wait
+    // for whatever its stream (and, with host I/O, the copy stream) may still
+    // do with that memory, such as a staging copy or a solve's last copy.
+    void quiesce(Ticket *t, hipStream_t s) {
+        (void)hipStreamSynchronize(s);
+        if (t->req.flags & HDI_REQ_HOST_IO) (void)hipStreamSynchronize(copy);
+    }
+
     void finish(Ticket *t, int32_t status, const char *msg) {
         std::lock_guard<std::mutex> lk(mu);
         t->rep.status = status;
@@ -195,9 +155,12 @@ struct hdi_server {
             st = tonal_optimize(t->req.img, t->mask, t->f, t->out, nullptr, t->ws, t->ws_bytes, &t->tonal, &tr, s);
         }
         const std::string msg = st ? hdi_last_error() : "";
+        bool sealed = false;
         if (st == HDI_OK || st == HDI_ERR_NO_CONVERGENCE) {
             if (seal(t, s) || hipEventSynchronize(t->ev) != hipSuccess) st = HDI_ERR_HIP;
+            else sealed = true;
         }
+        if (!sealed) quiesce(t, s);
         t->rep.outer_iters = tr.outer_iters;
         t->rep.inner_solves = tr.inner_solves;
         t->rep.rel_residual[0] = tr.rel_normal_residual;
@@ -211,9 +174,12 @@ struct hdi_server {
         hdi_solve_report sr{};
         if (!st) st = inpaint_solve(t->req.img, t->mask, t->f, t->out, nullptr, t->ws, t->ws_bytes, &t->req.solve, &sr, s);
         const std::string msg = st ? hdi_last_error() : "";
+        bool sealed = false;
         if (st == HDI_OK || st == HDI_ERR_NO_CONVERGENCE) {
             if (seal(t, s) || hipEventSynchronize(t->ev) != hipSuccess) st = HDI_ERR_HIP;
+            else sealed = true;
         }
+        if (!sealed) quiesce(t, s);
         t->rep.outer_iters = sr.outer_iters;
         t->rep.max_running = 1;
         for (int c = 0; c < 3; ++c) t->rep.rel_residual[c] = sr.rel_residual[c];
@@ -286,7 +252,9 @@ struct hdi_server {
             for (Ticket *t : admitted) {
                 int32_t st = place(t, compute);
                 if (st) {
-                    finish(t, st, hdi_last_error());
+                    const std::string msg = hdi_last_error();
+                    quiesce(t, compute);
+                    finish(t, st, msg.c_str());
                     continue;
                 }
                 EJob &j = t->ej;
@@ -306,7 +274,7 @@ struct hdi_server {
                 live.clear();
                 for (EJob *j : ended) {
                     Ticket *t = (Ticket *)j->user;
-                    (void)hipStreamSynchronize(compute);
+                    quiesce(t, compute);
                     finish(t, st, msg.c_str());
                 }
                 continue;
@@ -321,10 +289,12 @@ struct hdi_server {
                 t->rep.outer_iters = j->rounds;
                 for (int c = 0; c < 3; ++c) t->rep.rel_residual[c] = c < j->h.C ? j->rel[c] : 0.0;
                 if (j->status == HDI_ERR_EMPTY_MASK) {
+                    quiesce(t, compute);
                     finish(t, j->status, "empty mask (the inpainting matrix is singular)");
                     continue;
                 }
                 if (seal(t, compute)) {
+                    quiesce(t, compute);
                     finish(t, HDI_ERR_HIP, "recording the request's completion failed");
                     continue;
                 }
