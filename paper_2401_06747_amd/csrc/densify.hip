@@ -17,7 +17,8 @@
 //   6 selection  in ranked order, each cell with a free pixel adds its free
 //                pixel of largest error (ties to the smaller index), until
 //                n_add pixels are added (Alg. 1: at most one per triangle)
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -417,15 +418,21 @@ struct DensWs {
     size_t tmp_bytes;
 };
 
-static size_t cub_tmp_bytes(int maxn) {
-    size_t a = 0, b = 0, c = 0, d = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, a, (unsigned int *)nullptr, (unsigned int *)nullptr,
-                                             (int *)nullptr, (int *)nullptr, maxn);
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
-                                             (int *)nullptr, (int *)nullptr, maxn);
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, c, (int *)nullptr, (int *)nullptr, maxn);
-    d = std::max(std::max(a, b), c);
-    return d;
+// Temporary storage of the rocPRIM radix sorts (32- and 64-bit keys with int
+// values) and the exclusive int scan for up to maxn items.
+static size_t sort_tmp_bytes(int maxn) {
+    size_t a = 0, b = 0, c = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, a, (unsigned int *)nullptr, (unsigned int *)nullptr, (int *)nullptr,
+                                    (int *)nullptr, maxn);
+    (void)rocprim::radix_sort_pairs(nullptr, b, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
+                                    (int *)nullptr, (int *)nullptr, maxn);
+    (void)rocprim::exclusive_scan(nullptr, c, (int *)nullptr, (int *)nullptr, 0, (size_t)maxn, rocprim::plus<int>());
+    return std::max(std::max(a, b), c);
+}
+
+// Exclusive prefix sum of n ints on the stream.
+static hipError_t scan_exclusive(void *tmp, size_t tmp_bytes, const int *in, int *out, int n, hipStream_t s) {
+    return rocprim::exclusive_scan(tmp, tmp_bytes, in, out, 0, (size_t)n, rocprim::plus<int>(), s);
 }
 
 static bool plan_densify(DensWs &d, Arena &a, int W, int H) {
@@ -457,7 +464,7 @@ static bool plan_densify(DensWs &d, Arena &a, int W, int H) {
     d.rk0 = (unsigned long long *)a.take(maxC * 8);
     d.rk1 = (unsigned long long *)a.take(maxC * 8);
     d.newpix = (uint8_t *)a.take((N + 3) & ~(size_t)3);   // zeroed in 4-byte words
-    d.tmp_bytes = cub_tmp_bytes((int)maxC);
+    d.tmp_bytes = sort_tmp_bytes((int)maxC);
     d.tmp = a.take(d.tmp_bytes);
     return a.base == nullptr || a.used <= a.size;
 }
@@ -527,13 +534,13 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
             hipLaunchKernelGGL(k_iota, gd(n), dim3(256), 0, s, n, d.ord0);
             hipLaunchKernelGGL(k_key_c, gd(n), dim3(256), 0, s, n, d.tc, d.keyc0);
             size_t tb = d.tmp_bytes;
-            D_TRY(hipcub::DeviceRadixSort::SortPairs(d.tmp, tb, d.keyc0, d.keyc1, d.ord0, d.ord1, n, 0, 32, s));
+            D_TRY(rocprim::radix_sort_pairs(d.tmp, tb, d.keyc0, d.keyc1, d.ord0, d.ord1, n, 0u, 32u, s));
             hipLaunchKernelGGL(k_key_ab, gd(n), dim3(256), 0, s, n, d.ord1, d.ta, d.tb, d.keyab0);
             tb = d.tmp_bytes;
-            D_TRY(hipcub::DeviceRadixSort::SortPairs(d.tmp, tb, d.keyab0, d.keyab1, d.ord1, d.ord0, n, 0, 64, s));
+            D_TRY(rocprim::radix_sort_pairs(d.tmp, tb, d.keyab0, d.keyab1, d.ord1, d.ord0, n, 0u, 64u, s));
             hipLaunchKernelGGL(k_uniq_flags, gd(n), dim3(256), 0, s, n, d.ord0, d.ta, d.tb, d.tc, d.flag);
             tb = d.tmp_bytes;
-            D_TRY(hipcub::DeviceScan::ExclusiveSum(d.tmp, tb, d.flag, d.off, n, s));
+            D_TRY(scan_exclusive(d.tmp, tb, d.flag, d.off, n, s));
             hipLaunchKernelGGL(k_uniq_scatter, gd(n), dim3(256), 0, s, n, d.ord0, d.flag, d.off, d.ta, d.tb, d.tc,
                                d.ua, d.ub, d.uc);
             int last_off = 0, last_flag = 0;
@@ -555,11 +562,11 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
     hipLaunchKernelGGL(k_rank_keys, gd(ncell), dim3(256), 0, s, ncell, d.E, d.rk0);
     hipLaunchKernelGGL(k_iota, gd(ncell), dim3(256), 0, s, ncell, d.ord0);
     size_t tb = d.tmp_bytes;
-    D_TRY(hipcub::DeviceRadixSort::SortPairs(d.tmp, tb, d.rk0, d.rk1, d.ord0, d.ord1, ncell, 0, 64, s));
+    D_TRY(rocprim::radix_sort_pairs(d.tmp, tb, d.rk0, d.rk1, d.ord0, d.ord1, ncell, 0u, 64u, s));
     // 6 selection
     hipLaunchKernelGGL(k_nonempty, gd(ncell), dim3(256), 0, s, ncell, d.ord1, d.best, d.flag);
     tb = d.tmp_bytes;
-    D_TRY(hipcub::DeviceScan::ExclusiveSum(d.tmp, tb, d.flag, d.off, ncell, s));
+    D_TRY(scan_exclusive(d.tmp, tb, d.flag, d.off, ncell, s));
     hipLaunchKernelGGL(k_fill_i32, gd((N + 3) / 4), dim3(256), 0, s, (N + 3) / 4, 0, (int *)d.newpix);
     hipLaunchKernelGGL(k_select, gd(ncell), dim3(256), 0, s, ncell, n_add, d.ord1, d.best, d.flag, d.off, d.newpix);
     hipLaunchKernelGGL(k_apply, gd(N), dim3(256), 0, s, N, d.newpix, mask);
