@@ -77,27 +77,91 @@ def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
     return {"bytes_per_launch": 2 * nbytes, "avg_us": round(ms * 1e3, 1), "GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
-def cpu_baseline(inst, crop=(540, 960)):
-    """The oracle (FP64 SciPy: SuperLU inpainting, CG on the tonal normal
-    equations with exact B and B^T) on a bounded crop of the same image and
-    mask, one channel, scaled to 4K RGB steps/s by pixel count (linear scaling,
-    which flatters the direct solver)."""
+def _oracle_channel(f, mask, u_gpu=None, g_gpu=None):
+    """One channel in a worker process: the oracle's inpainting (SuperLU) and
+    tonal optimisation (CG on the normal equations to rel 1e-6) as they stand,
+    timed; then, untimed, the GPU's results on the same channel against them:
+    rel-L2 of u, and the oracle's normal residual and error bound of g."""
     from oracle import inpaint as oi
     from oracle import tonal as ot
-    h, w = crop
-    f = inst.f[0, :h, :w]
-    m = inst.mask[:h, :w].copy()
-    if m.sum() == 0:
-        m[0, 0] = 1
-    t = time.perf_counter()
-    oi.inpaint(f, m)
+    t0 = time.perf_counter()
+    u = oi.inpaint(f, mask)
     t1 = time.perf_counter()
-    ot.tonal_optimize(f, m, rtol=1e-6)
+    # the reduced (nested-dissection) operator at every size, as at 4K
+    ot.tonal_optimize(f, mask, rtol=1e-6, method="reduced")
     t2 = time.perf_counter()
-    scale = (h * w) / (inst.f.shape[1] * inst.f.shape[2] * inst.f.shape[0])
-    return {"value": round(scale / (t2 - t), 8), "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one {w}x{h} channel crop of the 4K workload: SuperLU inpainting ({t1 - t:.1f} s) + tonal CG "
-                      f"to rel 1e-6 ({t2 - t1:.1f} s), single-threaded, scaled by pixel count to 3840x2160x3"}
+    out = {"inpaint_s": t1 - t0, "tonal_s": t2 - t1}
+    if u_gpu is not None:
+        out["inpaint_rel_l2"] = float(oi.rel_l2(u_gpu, u)[0])
+    if g_gpu is not None:
+        op = ot.TonalOperator(mask, method="reduced")
+        c = ot.certificate(g_gpu, f, mask, steps=8, op=op)
+        btf = float(np.linalg.norm(op.Bt(np.asarray(f, np.float64).ravel())[op.K]))
+        out["tonal_rel_normal_residual"] = float(c["normal_residual"][0]) / btf
+        out["tonal_error_bound"] = float(c["error_bound"][0] / c["g_norm"][0])
+    return out
+
+
+def oracle_pool():
+    """Three worker processes (one per colour channel), started before the GPU
+    is touched; each runs the single-threaded oracle with one BLAS thread."""
+    import concurrent.futures
+    import multiprocessing
+    os.environ["OMP_NUM_THREADS"] = os.environ["OPENBLAS_NUM_THREADS"] = os.environ["MKL_NUM_THREADS"] = "1"
+    pool = concurrent.futures.ProcessPoolExecutor(max_workers=3, mp_context=multiprocessing.get_context("spawn"))
+    list(pool.map(_warm, range(3)))
+    return pool
+
+
+def _warm(_):
+    import oracle.tonal  # noqa: F401  (imports SciPy in the worker)
+    return os.getpid()
+
+
+def cpu_baseline(pool, inst, gpu_crop, crops=((540, 960), (1080, 1920))):
+    """The oracle on two crops of the 4K RGB workload, each channel in its own
+    worker (3 cores): wall time of inpainting + tonal optimisation per crop, an
+    exponent t ~ N^b fitted to the two, and the 4K RGB step time extrapolated
+    from the larger crop with it. Also config 1 (256x256 gray) in full, and the
+    GPU's errors on each crop against the oracle."""
+    from workloads import synth
+    measured = {}
+    for h, w in crops:
+        f = inst.f[:, :h, :w]
+        m = inst.mask[:h, :w].copy()
+        u_gpu, g_gpu = gpu_crop(f, m)
+        t = time.perf_counter()
+        futs = [pool.submit(_oracle_channel, f[c], m, u_gpu[c], g_gpu[c]) for c in range(f.shape[0])]
+        res = [x.result() for x in futs]
+        checks = time.perf_counter() - t
+        wall = max(r["inpaint_s"] + r["tonal_s"] for r in res)
+        measured[f"{w}x{h}x3"] = {
+            "step_s": round(wall, 2), "inpaint_s": round(max(r["inpaint_s"] for r in res), 2),
+            "tonal_s": round(max(r["tonal_s"] for r in res), 2), "known_pixels": int(m.sum()),
+            "gpu_inpaint_rel_l2": max(r["inpaint_rel_l2"] for r in res),
+            "gpu_tonal_rel_normal_residual": max(r["tonal_rel_normal_residual"] for r in res),
+            "gpu_tonal_error_bound": max(r["tonal_error_bound"] for r in res),   # certified, 8 CG steps
+            "wall_with_checks_s": round(checks, 1)}
+        log(f"oracle {w}x{h}x3: {measured[f'{w}x{h}x3']}")
+    (h0, w0), (h1, w1) = crops
+    small, big = measured[f"{w0}x{h0}x3"], measured[f"{w1}x{h1}x3"]
+    N4k = inst.f.shape[1] * inst.f.shape[2]
+    expo, t_4k = {}, 0.0
+    for part in ("inpaint_s", "tonal_s"):
+        # each part's own exponent t ~ N^b from the two crops, then 4K from the larger
+        b = float(np.log(big[part] / small[part]) / np.log((h1 * w1) / (h0 * w0)))
+        expo[part[:-2]] = round(b, 3)
+        t_4k += big[part] * (N4k / (h1 * w1)) ** b
+    c1 = synth.config1()
+    r1 = pool.submit(_oracle_channel, c1.f[0], c1.mask).result()
+    return {"value": round(1.0 / t_4k, 6), "unit": "steps/s", "cores": 3, "kind": "oracle",
+            "sample": f"crops {w0}x{h0}x3 and {w1}x{h1}x3 of the 4K RGB workload, each channel in its own "
+                      f"process (3 cores, 1 thread each): SuperLU inpainting + tonal CG to rel 1e-6 measured in full; "
+                      f"the 4K RGB step time ({t_4k:.0f} s) is an extrapolation, inpainting ~ N^{expo['inpaint']:.2f} "
+                      f"and tonal ~ N^{expo['tonal']:.2f} fitted to the two crops",
+            "measured": measured, "exponents": expo, "extrapolated_4k_step_s": round(t_4k, 1),
+            "config1_256x256_gray_s": round(r1["inpaint_s"] + r1["tonal_s"], 2),
+            "host_cores": len(os.sched_getaffinity(0)), "threads_per_worker": 1}
 
 
 def lds_bytes(L):
@@ -265,7 +329,8 @@ def batch_bench(torch, hdi, synth, dev, n_images=64, reps=3):
     from paper_2401_06747_amd import _lib
     L = _lib.lib()
     ws_single = hdi.workspace(max(L.hdi_inpaint_workspace_bytes(hdi._img(f.shape)) for f in fs), dev)
-    jobs = (_lib.hdi_job * len(fs))(*[_lib.hdi_job(hdi._img(f.shape), m.data_ptr(), f.data_ptr(), u.data_ptr())
+    jobs = (_lib.hdi_job * len(fs))(*[_lib.hdi_job(_lib.HDI_JOB_INPAINT, hdi._img(f.shape), m.data_ptr(), f.data_ptr(),
+                                                   u.data_ptr())
                                       for f, m, u in zip(fs, ms, outs_b)])
     ws_batch = hdi.workspace(L.hdi_batch_workspace_bytes(len(fs), jobs), dev)
     mpx = sum(f.numel() for f in fs) / 1e6
@@ -314,45 +379,75 @@ def batch_bench(torch, hdi, synth, dev, n_images=64, reps=3):
     return res
 
 
-def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=500, seed=5, tonal_workers=3):
-    """Serving stream: Poisson arrivals of inpaint and tonal requests over sizes
-    {256^2, 1024x768, 1920x1080, 3840x2160}, gray or RGB, 1-8% masks, at 0.8x
-    and 1.5x the plain path's capacity; latency from submission to result."""
+def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=1000, seed=5, tonal_workers=3, per_class=3,
+                n_calibration=100):
+    """Serving stream: Poisson arrivals of inpaint and tonal requests (50/50),
+    each with its own size from {256^2, 1024x768, 1920x1080, 3840x2160}, gray
+    or RGB (50/50) and mask density U(0.01, 0.08), at 0.8x and 1.5x the plain
+    path's capacity (measured on a calibration sample of requests); latency
+    from submission to result. Images come from a pool of `per_class` textured
+    images per size and channel count; each request's mask is its own: the
+    d N pixels of smallest u / |grad f| (u uniform), a random dithering of the
+    gradient magnitude with exactly floor(d N) pixels."""
     from concurrent.futures import ThreadPoolExecutor
     sizes = [(256, 256), (768, 1024), (1080, 1920), (2160, 3840)]
     rng = np.random.default_rng(seed)
     classes = [(H, W, C) for (H, W) in sizes for C in (1, 3)]
-    dens = {c: float(rng.uniform(0.01, 0.08)) for c in classes}
 
-    def make(k, c):
-        H, W, C = c
-        if (H, W, C) == (2160, 3840, 3):
-            return inst4k.f, inst4k.mask
-        f = synth.textured_image(H, W, C, 5, 100 + k)
-        return f, synth.gradient_mask(f, dens[c])
+    def make(k):
+        ci, j = divmod(k, per_class)
+        H, W, C = classes[ci]
+        if (H, W, C) == (2160, 3840, 3) and j == 0:
+            return inst4k.f
+        return synth.textured_image(H, W, C, 5, 100 + k)
 
     t0 = time.perf_counter()
     with ThreadPoolExecutor(8) as ex:
-        pool = list(ex.map(lambda kc: make(*kc), enumerate(classes)))
+        imgs = list(ex.map(make, range(len(classes) * per_class)))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    pool = []
+    for f in imgs:
+        ft = torch.tensor(f, dtype=torch.float32, device=dev)
+        g = ft.mean(0)
+        gx = torch.zeros_like(g)
+        gy = torch.zeros_like(g)
+        if g.shape[1] > 2:
+            gx[:, 1:-1] = 0.5 * (g[:, 2:] - g[:, :-2])
+        if g.shape[0] > 2:
+            gy[1:-1, :] = 0.5 * (g[2:, :] - g[:-2, :])
+        prio = torch.rand(g.shape, generator=gen, device=dev) / (torch.sqrt(gx * gx + gy * gy) + 1e-3)
+        pool.append((ft, prio, torch.sort(prio.flatten())[0]))
+    torch.cuda.synchronize()
     log(f"serving pool generated in {time.perf_counter() - t0:.1f} s")
-    pool = [(torch.tensor(f, dtype=torch.float32, device=dev), torch.tensor(m, device=dev)) for f, m in pool]
     kinds = (hdi.INPAINT, hdi.TONAL)
-    # plain service time per (class, kind), after one warm run each
-    svc = {}
-    for ci, (f, m) in enumerate(pool):
-        for kind in kinds:
-            fn = (lambda: hdi.inpaint_solve(f, m)) if kind == hdi.INPAINT else (lambda: hdi.tonal_optimize(f, m))
-            fn()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            svc[(ci, kind)] = time.perf_counter() - t
-    mu_plain = 1.0 / float(np.mean(list(svc.values())))
-    req_class = rng.integers(0, len(pool), n_requests)
-    req_kind = rng.integers(0, 2, n_requests)
+
+    def draw(n):
+        cls = rng.integers(0, len(classes), n)
+        img = cls * per_class + rng.integers(0, per_class, n)
+        return img, rng.integers(0, 2, n), rng.uniform(0.01, 0.08, n)
+
+    def mask_of(i, d):
+        _, prio, srt = pool[i]
+        k = max(1, int(d * prio.numel()))
+        return (prio <= srt[k - 1]).to(torch.uint8).contiguous()
+
+    # plain capacity from a calibration sample of requests, one at a time
+    c_img, c_kind, c_den = draw(n_calibration)
+    cal = [(pool[i][0], mask_of(i, d), kinds[k]) for i, k, d in zip(c_img, c_kind, c_den)]
+    for f, m, kind in cal[:8]:
+        (hdi.inpaint_solve if kind == hdi.INPAINT else hdi.tonal_optimize)(f, m)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for f, m, kind in cal:
+        (hdi.inpaint_solve if kind == hdi.INPAINT else hdi.tonal_optimize)(f, m)
+    torch.cuda.synchronize()
+    mu_plain = n_calibration / (time.perf_counter() - t)
+    del cal
+    r_img, r_kind, r_den = draw(n_requests)
+    masks = [mask_of(i, d) for i, d in zip(r_img, r_den)]
+    outs = [torch.empty(pool[i][0].shape, dtype=torch.float64, device=dev) for i in r_img]
     gaps = rng.exponential(1.0, n_requests)
-    outs = [torch.empty(pool[c][0].shape, dtype=torch.float64, device=dev) for c in req_class]
     torch.cuda.synchronize()
 
     def run(load, plain):
@@ -366,8 +461,7 @@ def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=500, seed=5, tonal_wo
                 wait = arrive[i] - (time.perf_counter() - t0)
                 if wait > 0:
                     time.sleep(wait)
-                f, m = pool[req_class[i]]
-                tickets.append(srv.submit(kinds[req_kind[i]], f, m, out=outs[i]))
+                tickets.append(srv.submit(kinds[r_kind[i]], pool[r_img[i]][0], masks[i], out=outs[i]))
             srv.drain()
             reps_ = [srv.poll(t)[1] for t in tickets]
         finally:
@@ -375,13 +469,19 @@ def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=500, seed=5, tonal_wo
         assert all(r["status"] == 0 for r in reps_), [r for r in reps_ if r["status"]][:3]
         lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in reps_])
         span = max(r["t_done_ms"] for r in reps_) - min(r["t_submit_ms"] for r in reps_)
-        return {"p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-                "solves_per_s": round(n_requests / (span * 1e-3), 2),
-                "max_batch": int(max(r["max_running"] for r in reps_))}
+        out = {"p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+               "solves_per_s": round(n_requests / (span * 1e-3), 2),
+               "max_batch": int(max(r["max_running"] for r in reps_))}
+        for k, name in enumerate(("inpaint", "tonal")):
+            sel = r_kind == k
+            out[f"{name}_p99_ms"] = round(float(np.percentile(lat[sel], 99)), 2)
+            out[f"{name}_max_running"] = int(max(r["max_running"] for r, q in zip(reps_, sel) if q))
+        return out
 
-    res = {"workload": f"{n_requests} Poisson arrivals, inpaint/tonal 50/50, sizes 256^2..3840x2160, gray/RGB, "
-                       f"1-8% FS-gradient masks (one image per size and channel count)",
-           "mu_plain_per_s": round(mu_plain, 2), "tonal_workers": tonal_workers}
+    res = {"workload": f"{n_requests} Poisson arrivals, inpaint/tonal 50/50, per-request size from 256^2..3840x2160, "
+                       f"gray/RGB 50/50, density U(0.01, 0.08) (own mask per request: random dithering of the "
+                       f"gradient magnitude); {per_class} images per size and channel count",
+           "mu_plain_per_s": round(mu_plain, 2), "calibration_requests": n_calibration, "tonal_workers": tonal_workers}
     for load in (0.8, 1.5):
         res[f"load_{load}"] = {"lambda_per_s": round(load * mu_plain, 2), "served": run(load, False),
                                "plain": run(load, True)}
@@ -471,12 +571,15 @@ def main():
     ap.add_argument("--no-spatial", action="store_true", help="skip the full data-optimisation measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-comparators", action="store_true", help="skip the paper-comparator measurement")
-    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
               "not built", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's worker processes start before anything touches the GPU
+    pool = None if args.no_cpu_baseline else oracle_pool()
 
     import torch
     import paper_2401_06747_amd as hdi
@@ -578,8 +681,17 @@ def main():
         copy = copy_calibration(torch, dev)
         log(f"copy calibration: {copy}")
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(inst)
+    if pool is not None:
+        def gpu_crop(fc, mc):
+            ft = torch.tensor(fc, dtype=torch.float32, device=dev).contiguous()
+            mt = torch.tensor(mc, device=dev).contiguous()
+            uc, r1 = hdi.inpaint_solve(ft, mt)
+            gc, r2 = hdi.tonal_optimize(ft, mt, params=tonal_params)
+            if r1["status"] or r2["status"]:
+                raise RuntimeError(f"crop solves failed: {r1} {r2}")
+            return uc.cpu().numpy(), gc.cpu().numpy()
+        cpu = cpu_baseline(pool, inst, gpu_crop)
+        pool.shutdown()
         log(f"cpu baseline: {cpu}")
     out = {
         "metric": "4K RGB inpaint+tonal solves/s at rel-res 1e-6; batched vs plain; p99 latency",

@@ -61,9 +61,9 @@ typedef struct {
  *                (FP64 residual; default 1e-6)
  *   max_outer    cap on refinement rounds (default 40)
  *   overlap      overlap of the 32x32 subdomain blocks of the Schwarz smoother
- *                (Sec. 3.1, 3.3; default 4, valid 2..16, even)
+ *                (Sec. 3.1, 3.3; default 6 as in Sec. 3.3, valid 2..16, even)
  *   local_iters  conjugate-gradient iterations per block and smoothing step
- *                (Sec. 3.3; default 8)
+ *                on the finest level (Sec. 3.3; default 8)
  *   coarse_iters CG iterations on the coarsest level, which is a single block
  *                (Sec. 3.3; default 64)
  *   flags        HDI_FLAG_* bits
@@ -71,11 +71,31 @@ typedef struct {
  *                0 automatic (from level 1, the first level with fewer than
  *                4096 blocks of 32x32 over all channels, where the smoother is
  *                bound by the latency of its steps), -1 none, k >= 1 level k
+ *   robin        weight w in (0, 0.9] of the Robin transmission condition on
+ *                the inner block boundaries of the smoother (the optimised
+ *                Schwarz method of Sec. 3.1): in a block's local operator each
+ *                edge to a pixel outside the block adds 1 - w to the pixel's
+ *                diagonal, which is du/dn + p u = 0 on the edge's midpoint
+ *                with p = 2 (1 - w) / (1 + w); w -> 1 tends to a Neumann
+ *                condition. 0 selects the default 0.6; a negative value gives
+ *                w = 0, a zero Dirichlet value on the outside pixel (plain
+ *                restricted additive Schwarz).
+ *   local_stop   fraction in [0, 1) for the finest level's smoothing: a
+ *                block's local CG also stops once its squared residual is at
+ *                most local_stop times the channel's global squared residual
+ *                of the refinement round (Sec. 3.3); 0 (the default) runs
+ *                local_iters steps (fewer only at the FP32 rounding floor).
+ *                Coarse levels always run their fixed step counts.
+ *   mid_iters    conjugate-gradient iterations per block and smoothing step on
+ *                the levels between the finest and the coarsest, and in the
+ *                full-multigrid start (default: local_iters)
  * Each refinement round applies one V-cycle with one pre- and one
  * post-smoothing step (Sec. 3.3).                                            */
 typedef struct {
     double rel_tol;
     int32_t max_outer, overlap, local_iters, coarse_iters, flags, small_from;
+    float robin, local_stop;
+    int32_t mid_iters;
 } hdi_solve_params;
 
 #define HDI_FLAG_NO_FMG 1   /* cold start from u = C f instead of the reduced
@@ -140,33 +160,6 @@ size_t hdi_noalloc_scratch_bytes(void);
  *           call. */
 int32_t inpaint_solve_noalloc(hdi_image img, const uint8_t *mask, const float *f, double *u, const double *u0,
                               const hdi_solve_params *params, hdi_solve_report *report, void *stream);
-
-/* ------------------------------------------------------------------ batches */
-
-/* One inpainting job of a batch: image shape and device pointers as for
- * inpaint_solve (mask H x W uint8, f C x H x W float32, u C x H x W float64). */
-typedef struct {
-    hdi_image img;
-    const uint8_t *mask;
-    const float *f;
-    double *u;
-} hdi_job;
-
-/* Bytes of workspace hdi_solve_batch needs for these jobs. 0 on bad input. */
-size_t hdi_batch_workspace_bytes(int32_t n, const hdi_job *jobs);
-
-/* Inpainting (eq. inp-discrete-lsi) of n images of any sizes in shared
- * launches: every phase of the solve is one kernel launch over the work items
- * (image, level, block) of all images taking part, and each image refines
- * until its own tolerance. An image's result is bit-for-bit what inpaint_solve
- * returns for it with the same parameters, whatever else is in the batch.
- *   params   nullable array of n per-job parameter sets (each image its own)
- *   reports  nullable host array of n reports (ms: the whole batch)
- * Returns the first failing job's status (HDI_ERR_EMPTY_MASK for a job with
- * an empty mask, which ends at once while the others are solved;
- * HDI_ERR_NO_CONVERGENCE with the last iterates). */
-int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_bytes,
-                        const hdi_solve_params *params, hdi_solve_report *reports, void *stream);
 
 /* ------------------------------------------------------------------ tonal */
 
@@ -240,6 +233,51 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
                        void *ws, size_t ws_bytes, const hdi_tonal_params *params,
                        hdi_tonal_report *report, void *stream);
 
+/* ------------------------------------------------------------------ batches */
+
+#define HDI_JOB_INPAINT 0
+#define HDI_JOB_TONAL 1
+
+/* One job of a batch, with device pointers as for inpaint_solve and
+ * tonal_optimize (mask H x W uint8, f C x H x W float32, out C x H x W
+ * float64: u for an inpainting job, g for a tonal job, 0 off the mask).
+ *   kind          HDI_JOB_INPAINT or HDI_JOB_TONAL
+ *   tonal         tonal jobs: nullable parameters (defaults); the job starts
+ *                 from g = f on the mask and its inner parameters must not set
+ *                 HDI_FLAG_CG
+ *   tonal_report  tonal jobs: nullable host report                          */
+typedef struct {
+    int32_t kind;
+    hdi_image img;
+    const uint8_t *mask;
+    const float *f;
+    double *out;
+    const hdi_tonal_params *tonal;
+    hdi_tonal_report *tonal_report;
+} hdi_job;
+
+/* Bytes of workspace hdi_solve_batch needs for these jobs. 0 on bad input. */
+size_t hdi_batch_workspace_bytes(int32_t n, const hdi_job *jobs);
+
+/* n inpainting (eq. inp-discrete-lsi) and tonal optimisation (Sec. 5) jobs of
+ * any sizes in shared launches: every phase of an inpainting solve is one
+ * kernel launch over the work items (image, level, block) of all solves taking
+ * part, and each solve refines until its own tolerance. A tonal job's inner
+ * solves (B g and the symmetrised solve behind B^T, Sec. 5.1) are solves of
+ * these shared launches too, while its own kernels run on a stream of its own.
+ * Every result is bit-for-bit what inpaint_solve or tonal_optimize returns for
+ * it with the same parameters, whatever else is in the batch.
+ *   params   nullable array of n per-job parameter sets (each image its own;
+ *            the inpainting parameters of inpainting jobs)
+ *   reports  nullable host array of n reports; for a tonal job outer_iters is
+ *            its outer iterations and rel_residual[0] its relative normal
+ *            residual (ms: the whole batch)
+ * Returns the first failing job's status (HDI_ERR_EMPTY_MASK for a job with
+ * an empty mask, which ends at once while the others are solved;
+ * HDI_ERR_NO_CONVERGENCE with the last iterates). */
+int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_bytes,
+                        const hdi_solve_params *params, hdi_solve_report *reports, void *stream);
+
 /* ------------------------------------------------------------------ Voronoi initialisation */
 
 /* Starting values for tonal optimisation, Sec. 5.3: make the inpainting match
@@ -296,13 +334,18 @@ int32_t voronoi_init(hdi_image img, const uint8_t *mask, const float *f, double 
 /* ------------------------------------------------------------------ serving */
 
 /* A request loop over one device: inpainting and tonal requests of any sizes
- * are submitted as they arrive and run with continuous batching. Inpainting
- * requests join the shared launches of the batch engine between refinement
- * rounds (each keeps its own rounds and tolerance, and its result is bit-for-bit
- * what inpaint_solve gives); tonal requests run on worker threads with streams
- * of their own, so their kernels overlap the batch on the device. Every request
- * is admitted when a slot and its memory in the caller's arena are free, in
- * arrival order per kind, and its state stays in device memory until it ends. */
+ * are submitted as they arrive and run with continuous batching. Every
+ * inpainting solve joins the shared launches of the batch engine between
+ * refinement rounds: the inpainting requests, and the inner solves of the
+ * tonal requests (B g, and the symmetrised solve behind B^T, Sec. 5.1). Each
+ * solve keeps its own rounds and tolerance. A tonal request's outer iteration
+ * runs on a worker thread with a stream of its own (its gathers, RAS sweeps and
+ * vector updates overlap the engine's rounds), waits for its inner solves in
+ * the engine, and gives bit for bit what tonal_optimize gives; an inpainting
+ * request gives what inpaint_solve gives. Every request is admitted when its
+ * memory in the caller's arena is free (inpainting requests also need an
+ * engine slot), in arrival order per kind, and its state stays in device
+ * memory until it ends. */
 #define HDI_REQ_INPAINT 0
 #define HDI_REQ_TONAL 1
 #define HDI_REQ_HOST_IO 1   /* request flags: mask, f and out are pinned host memory
@@ -312,7 +355,8 @@ int32_t voronoi_init(hdi_image img, const uint8_t *mask, const float *f, double 
 
 /* One request. Without HDI_REQ_HOST_IO the pointers are device memory that
  * must stay valid and unchanged until the request is done. Tonal requests
- * start from g = f on the mask.
+ * start from g = f on the mask; their inner parameters must not set
+ * HDI_FLAG_CG (the engine runs the multigrid solver).
  *   out   u (inpaint, C x H x W float64) or g (tonal, 0 off the mask)      */
 typedef struct {
     int32_t kind, flags;
@@ -328,7 +372,8 @@ typedef struct {
     int32_t status, kind;
     int32_t outer_iters;       /* refinement rounds (inpaint) or outer iterations (tonal) */
     int32_t inner_solves;      /* tonal: inpainting solves */
-    int32_t max_running;       /* inpaint: most requests sharing one round with it */
+    int32_t max_running;       /* most solves sharing one engine round with it (tonal:
+                                  with any of its inner solves) */
     double rel_residual[3];    /* inpaint: per channel; tonal: [0] relative normal residual */
     double mse_initial, mse_final;
     double t_submit_ms, t_start_ms, t_done_ms;   /* host clock, ms since hdi_server_create */
@@ -341,8 +386,9 @@ size_t hdi_request_bytes(const hdi_request *req);
 
 /* Start a server on the current device. The arena (caller-owned device memory,
  * not freed by the server) holds the engine tables and every running request's
- * state; max_slots bounds the inpainting requests in one batch, tonal_workers
- * the tonal requests running at once. Returns NULL on bad arguments or HIP
+ * state; max_slots bounds the solves in one engine round (inpainting
+ * requests and tonal inner solves), tonal_workers the tonal requests running
+ * at once. Returns NULL on bad arguments or HIP
  * failure (hdi_last_error says which). */
 hdi_server *hdi_server_create(void *arena, size_t arena_bytes, int32_t max_slots, int32_t tonal_workers,
                               int32_t flags);

@@ -34,15 +34,19 @@ VINIT_DIRECT, VINIT_VORONOI, VINIT_VORONOI_LOG = (_lib.HDI_VINIT_DIRECT, _lib.HD
 class SolveParams:
     rel_tol: float = 0.0       # 0 -> 1e-6
     max_outer: int = 0         # 0 -> 40
-    overlap: int = 0           # 0 -> 4
+    overlap: int = 0           # 0 -> 6
     local_iters: int = 0       # 0 -> 8
     coarse_iters: int = 0      # 0 -> 64
     flags: int = 0
     small_from: int = 0        # first level with 16x16 blocks: 0 automatic, -1 none, k level k
+    robin: float = 0.0         # Robin weight at inner block boundaries (0 -> 0.6, < 0: Dirichlet), up to 0.9
+    local_stop: float = 0.0    # > 0: finest-level local CG stops at this fraction of the global squared residual
+    mid_iters: int = 0         # local CG steps on the levels between finest and coarsest (0 -> local_iters)
 
     def c(self):
         return _lib.hdi_solve_params(self.rel_tol, self.max_outer, self.overlap, self.local_iters,
-                                     self.coarse_iters, self.flags, self.small_from)
+                                     self.coarse_iters, self.flags, self.small_from, self.robin, self.local_stop,
+                                     self.mid_iters)
 
 
 @dataclass
@@ -322,18 +326,33 @@ def voronoi_labels(mask: torch.Tensor, jfa_step: int = 0, ws: torch.Tensor | Non
     return labels, int(d2.value)
 
 
-def solve_batch(fs, masks, params=None, ws: torch.Tensor | None = None, outs=None):
-    """Inpaint a list of images in shared launches (hdi_solve_batch). Returns
-    (list of u float64, list of report dicts)."""
+INPAINT, TONAL = _lib.HDI_REQ_INPAINT, _lib.HDI_REQ_TONAL
+
+
+def solve_batch(fs, masks, params=None, ws: torch.Tensor | None = None, outs=None, kinds=None, tonal_params=None):
+    """Inpainting and tonal jobs in shared launches (hdi_solve_batch). kinds:
+    None (all INPAINT) or a list of INPAINT / TONAL; params: inpainting
+    parameters (one or per job); tonal_params: TonalParams for the tonal jobs
+    (one or per job). Returns (list of outputs float64: u or g, list of report
+    dicts)."""
     n = len(fs)
     if n == 0 or len(masks) != n:
         raise ValueError("need equally many images and masks")
     for f, m in zip(fs, masks):
         _check_inputs(f, m)
+    kinds = list(kinds) if kinds is not None else [INPAINT] * n
+    if len(kinds) != n or any(k not in (INPAINT, TONAL) for k in kinds):
+        raise ValueError("kinds must list INPAINT or TONAL for every job")
     L = _lib.lib()
     us = outs if outs is not None else [torch.empty(f.shape, dtype=torch.float64, device=f.device) for f in fs]
-    jobs = (_lib.hdi_job * n)(*[_lib.hdi_job(_img(f.shape), m.data_ptr(), f.data_ptr(), u.data_ptr())
-                                for f, m, u in zip(fs, masks, us)])
+    tlist = tonal_params if isinstance(tonal_params, (list, tuple)) else [tonal_params] * n
+    tps = [t.c() if (k == TONAL and t is not None) else None for k, t in zip(kinds, tlist)]
+    treps = [_lib.hdi_tonal_report() if k == TONAL else None for k in kinds]
+    jobs = (_lib.hdi_job * n)(*[
+        _lib.hdi_job(k, _img(f.shape), m.data_ptr(), f.data_ptr(), u.data_ptr(),
+                     ctypes.pointer(tp) if tp is not None else None,
+                     ctypes.pointer(tr) if tr is not None else None)
+        for k, f, m, u, tp, tr in zip(kinds, fs, masks, us, tps, treps)])
     need = L.hdi_batch_workspace_bytes(n, jobs)
     if ws is None or ws.numel() < need:
         ws = workspace(need, fs[0].device)
@@ -344,14 +363,17 @@ def solve_batch(fs, masks, params=None, ws: torch.Tensor | None = None, outs=Non
         pc = (_lib.hdi_solve_params * n)(*[p.c() for p in plist])
     reps = (_lib.hdi_solve_report * n)()
     st = L.hdi_solve_batch(n, jobs, _ptr(ws), ws.numel(), pc, reps, _stream_ptr(fs[0].device))
-    reports = [{"status": st, "rel_residual": list(r.rel_residual)[:f.shape[0]], "outer_iters": r.outer_iters,
-                "vcycles": r.vcycles, "ms": r.ms} for r, f in zip(reps, fs)]
+    reports = []
+    for r, f, k, tr in zip(reps, fs, kinds, treps):
+        d = {"status": st, "kind": k, "rel_residual": list(r.rel_residual)[:f.shape[0]],
+             "outer_iters": r.outer_iters, "vcycles": r.vcycles, "ms": r.ms}
+        if tr is not None:
+            d.update(mse_initial=tr.mse_initial, mse_final=tr.mse_final, rel_normal_residual=tr.rel_normal_residual,
+                     inner_solves=tr.inner_solves, inner_vcycles=tr.inner_vcycles)
+        reports.append(d)
     if st not in (_lib.HDI_OK, _lib.HDI_ERR_NO_CONVERGENCE):
         check(st)
     return us, reports
-
-
-INPAINT, TONAL = _lib.HDI_REQ_INPAINT, _lib.HDI_REQ_TONAL
 
 
 class Server:

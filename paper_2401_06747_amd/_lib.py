@@ -17,16 +17,13 @@ class hdi_image(ctypes.Structure):
 class hdi_solve_params(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("overlap", ctypes.c_int32),
                 ("local_iters", ctypes.c_int32), ("coarse_iters", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("small_from", ctypes.c_int32)]
+                ("small_from", ctypes.c_int32), ("robin", ctypes.c_float),
+                ("local_stop", ctypes.c_float), ("mid_iters", ctypes.c_int32)]
 
 
 class hdi_solve_report(ctypes.Structure):
     _fields_ = [("rel_residual", ctypes.c_double * 3), ("outer_iters", ctypes.c_int32),
                 ("vcycles", ctypes.c_int32), ("ms", ctypes.c_float)]
-
-
-class hdi_job(ctypes.Structure):
-    _fields_ = [("img", hdi_image), ("mask", ctypes.c_void_p), ("f", ctypes.c_void_p), ("u", ctypes.c_void_p)]
 
 
 class hdi_tonal_params(ctypes.Structure):
@@ -40,6 +37,15 @@ class hdi_tonal_report(ctypes.Structure):
     _fields_ = [("mse_initial", ctypes.c_double), ("mse_final", ctypes.c_double),
                 ("rel_normal_residual", ctypes.c_double), ("outer_iters", ctypes.c_int32),
                 ("inner_solves", ctypes.c_int32), ("inner_vcycles", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+HDI_JOB_INPAINT, HDI_JOB_TONAL = 0, 1
+
+
+class hdi_job(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("img", hdi_image), ("mask", ctypes.c_void_p), ("f", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("tonal", ctypes.POINTER(hdi_tonal_params)),
+                ("tonal_report", ctypes.POINTER(hdi_tonal_report))]
 
 
 class hdi_request(ctypes.Structure):

@@ -19,15 +19,18 @@ from . import _lib
 from . import SolveParams, _check_inputs, _img, _ptr, _stream_ptr, workspace
 from ._lib import check
 
-OVERLAPS = (2, 4, 6)
-LOCAL_ITERS = (4, 6, 8, 12)
+OVERLAPS = (4, 6)
+LOCAL_ITERS = (6, 8, 10, 12)
 COARSE_ITERS = (32, 64)
 SMALL_FROM = (0, -1)          # 16x16 blocks on the coarse levels: automatic rule, or none
+ROBIN = (-1.0, 0.6)           # Dirichlet block boundaries, or the Robin condition with weight 0.6
+LOCAL_STOP = (0.0, 1e-7)      # fixed local CG steps, or the global-relative stop
 
 
 def candidates():
-    return [SolveParams(overlap=o, local_iters=k, coarse_iters=c, small_from=t)
-            for o in OVERLAPS for k in LOCAL_ITERS for c in COARSE_ITERS for t in SMALL_FROM]
+    return [SolveParams(overlap=o, local_iters=k, coarse_iters=c, small_from=t, robin=w, local_stop=q)
+            for o in OVERLAPS for k in LOCAL_ITERS for c in COARSE_ITERS for t in SMALL_FROM for w in ROBIN
+            for q in LOCAL_STOP]
 
 
 def bucket(shape, density: float) -> str:
@@ -71,5 +74,5 @@ class Autotuner:
         check(st)
         p = cands[best.value]
         return {"params": {"overlap": p.overlap, "local_iters": p.local_iters, "coarse_iters": p.coarse_iters,
-                           "small_from": p.small_from},
+                           "small_from": p.small_from, "robin": p.robin, "local_stop": p.local_stop},
                 "ms": float(ms.value)}

@@ -128,13 +128,20 @@ void Engine::describe(const EJob &j) {
     m.C = j.job.img.channels;
     m.nlev = h.nlev;
     m.local_iters = j.cfg.local_iters;
+    m.mid_iters = j.cfg.mid_iters;
     m.coarse_iters = j.cfg.coarse_iters;
+    m.robin = j.cfg.robin;
+    m.local_stop = j.cfg.local_stop;
+    m.kind = j.kind;
+    m.warm = j.warm ? 1 : 0;
+    m.data_d = j.data_d;
+    m.src = j.src;
     const dim3 g = residual_grid(m.W, m.H);
     m.gx = (int)g.x;
     m.nblk = h.nblk;
     m.mask = j.job.mask;
     m.f = j.job.f;
-    m.u = j.job.u;
+    m.u = j.job.out;
     m.u_alt = h.u_alt;
     m.partials = h.partials;
     m.norms = d_norms_ + (size_t)i * 6;
@@ -215,9 +222,13 @@ int32_t Engine::admit(const std::vector<EJob *> &news, std::vector<EJob *> &ende
     }
     if (go.empty()) return HDI_OK;
 
-    // 3. starting iterate: u = f on the mask, reduced FMG elsewhere (Sec. 3.2)
+    // 3. starting iterate: the data on the mask, and elsewhere the reduced FMG
+    // (Sec. 3.2) for cold data problems, the caller's start for warm ones, 0
+    // otherwise
     seg_admit_.v.clear();
-    auto fmg = [](const EJob *j) { return !(j->cfg.flags & HDI_FLAG_NO_FMG); };
+    auto fmg = [](const EJob *j) {
+        return !(j->cfg.flags & HDI_FLAG_NO_FMG) && !j->warm && j->kind != EK_SRC_F64;
+    };
     auto chunks = [](const Level &L) { return ((long)L.W * L.H + 255) / 256; };
     auto tiles = [](const Level &L) { return (long)L.bx.count * L.by.count; };
     BPhase init_u = seg_admit_.begin(d_seg_admit_);
@@ -332,7 +343,7 @@ int32_t Engine::round(std::vector<EJob *> &ended, hipStream_t s) {
         }
         // iterates that ended in the workspace copy go back to the caller's u
         if (j->where == 1)
-            B_TRY(hipMemcpyAsync(j->job.u, j->h.u_alt,
+            B_TRY(hipMemcpyAsync(j->job.out, j->h.u_alt,
                                  sizeof(double) * j->h.C * j->job.img.width * j->job.img.height,
                                  hipMemcpyDeviceToDevice, s));
         slot_[j->slot] = nullptr;
@@ -405,11 +416,15 @@ extern "C" {
 size_t hdi_batch_workspace_bytes(int32_t n, const hdi_job *jobs) {
     if (n < 1 || !jobs) return 0;
     std::vector<EJob> ej(n);
+    bool tonal = false;
     for (int i = 0; i < n; ++i) {
         if (jobs[i].img.width < 1 || jobs[i].img.height < 1 || (jobs[i].img.channels != 1 && jobs[i].img.channels != 3))
             return 0;
+        if (jobs[i].kind != HDI_JOB_INPAINT && jobs[i].kind != HDI_JOB_TONAL) return 0;
+        tonal = tonal || jobs[i].kind == HDI_JOB_TONAL;
         ej[i].job = jobs[i];
     }
+    if (tonal) return batch_served_bytes(n, jobs);
     Engine e;
     Arena a{nullptr, 0, 0};
     plan_batch(e, ej, a);
@@ -423,10 +438,15 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
         return HDI_ERR_ARG;
     }
     std::vector<EJob> ej(n);
+    bool tonal = false;
     for (int i = 0; i < n; ++i) {
         if (!check_image(jobs[i].img)) return HDI_ERR_ARG;
-        if (!jobs[i].mask || !jobs[i].f || !jobs[i].u) {
-            set_error("job %d: mask, f and u must be non-null device pointers", i);
+        if (jobs[i].kind != HDI_JOB_INPAINT && jobs[i].kind != HDI_JOB_TONAL) {
+            set_error("job %d: kind %d is neither HDI_JOB_INPAINT nor HDI_JOB_TONAL", i, jobs[i].kind);
+            return HDI_ERR_ARG;
+        }
+        if (!jobs[i].mask || !jobs[i].f || !jobs[i].out) {
+            set_error("job %d: mask, f and out must be non-null device pointers", i);
             return HDI_ERR_ARG;
         }
         int32_t st = fill_cfg(params ? &params[i] : nullptr, ej[i].cfg, ej[i].overlap);
@@ -434,6 +454,18 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
         if (ej[i].cfg.flags & HDI_FLAG_CG) {
             set_error("job %d: batches run the multigrid solver only (HDI_FLAG_CG is for single solves)", i);
             return HDI_ERR_ARG;
+        }
+        if (jobs[i].kind == HDI_JOB_TONAL) {
+            TonalCfg tc;
+            SolveCfg inner;
+            int ov = 0;
+            st = fill_tonal_cfg(jobs[i].tonal, tc, inner, ov);
+            if (st) return st;
+            if (inner.flags & HDI_FLAG_CG) {
+                set_error("job %d: batches run the multigrid solver only (HDI_FLAG_CG is for single solves)", i);
+                return HDI_ERR_ARG;
+            }
+            tonal = true;
         }
         ej[i].job = jobs[i];
         ej[i].slot = i;
@@ -444,6 +476,7 @@ int32_t hdi_solve_batch(int32_t n, const hdi_job *jobs, void *ws, size_t ws_byte
         return HDI_ERR_WORKSPACE;
     }
     hipStream_t s = (hipStream_t)stream;
+    if (tonal) return solve_batch_served(n, jobs, ws, ws_bytes, params, reports, s);
     Arena a{(char *)ws, ws_bytes, 0};
     Engine e;
     plan_batch(e, ej, a);

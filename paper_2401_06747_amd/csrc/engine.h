@@ -15,8 +15,14 @@
 namespace hdi {
 
 // One image in the engine. The caller owns it and its hierarchy memory.
+// job.out receives the solution; kind says whether the right-hand side is the
+// FP32 image job.f on the mask, an FP64 image data_d on the mask, or an FP64
+// source src off it (EK_*); warm: job.out holds the start on unknown pixels.
 struct EJob {
     hdi_job job{};
+    int kind = EK_DATA_F32;
+    const double *data_d = nullptr, *src = nullptr;
+    bool warm = false;
     SolveCfg cfg{};
     int overlap = 4;
     Hierarchy h{};
@@ -41,7 +47,7 @@ public:
     int32_t admit(const std::vector<EJob *> &news, std::vector<EJob *> &ended, hipStream_t s);
     // One refinement round over every running job. Jobs that met their
     // tolerance, ran out of rounds or went non-finite are returned in `ended`
-    // with their final iterate copied to job.u (enqueued on s, not waited for)
+    // with their final iterate copied to job.out (enqueued on s, not waited for)
     // and their slots freed.
     int32_t round(std::vector<EJob *> &ended, hipStream_t s);
     // After a HIP failure: every running job leaves (returned in `ended`).
@@ -74,5 +80,12 @@ private:
 };
 
 int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap);
+
+// Batches with tonal jobs run as the requests of a server over the batch
+// workspace (server.hip): the workspace they need, and the run (arguments
+// already checked; host-synchronous, after the work enqueued on s).
+size_t batch_served_bytes(int n, const hdi_job *jobs);
+int32_t solve_batch_served(int n, const hdi_job *jobs, void *ws, size_t ws_bytes, const hdi_solve_params *params,
+                           hdi_solve_report *reports, hipStream_t s);
 
 }  // namespace hdi

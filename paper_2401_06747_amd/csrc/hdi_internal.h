@@ -72,6 +72,9 @@ inline int small_overlap(int overlap) { return overlap / 2 >= 2 ? (overlap / 2) 
 struct SolveCfg {
     double rel_tol;
     int max_outer, local_iters, coarse_iters, vcycles, flags;
+    int mid_iters;     // local CG steps on the levels between the finest and the coarsest
+    float robin;       // Robin weight of the Schwarz smoother (hdi_solve_params::robin)
+    float local_stop;  // global-relative local stop (hdi_solve_params::local_stop)
     int small_from;  // hdi_solve_params::small_from (0 automatic, -1 none)
     int64_t known;   // number of known pixels (for the byte accounting)
 };
@@ -157,9 +160,15 @@ template <typename TD>
 void launch_residual(int W, int H, int C, const uint8_t *mask, const double *u_in, const float *e, double *u_out,
                      const TD *data, const double *src, float *r, double *partials, double *norms, hipStream_t s);
 void launch_update(int W, int H, int C, const uint8_t *mask, const float *e, double *u, hipStream_t s);
-void launch_smooth_pre(const Level &L, int C, int iters, float *e_out, hipStream_t s);
-void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, const float *e_in,
-                        const float *ec, float *e_out, hipStream_t s);
+// Schwarz smoothing steps. robin: weight of the Robin transmission condition
+// at inner block boundaries (0: zero Dirichlet values outside the block).
+// gnorm, frac: a block's local CG also stops once its squared residual is at
+// most frac times the channel's global squared residual gnorm[2 c] (nullptr or
+// 0: fixed step count).
+void launch_smooth_pre(const Level &L, int C, int iters, float robin, const double *gnorm, float frac, float *e_out,
+                       hipStream_t s);
+void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, float robin, const double *gnorm,
+                        float frac, const float *e_in, const float *ec, float *e_out, hipStream_t s);
 void launch_restrict_residual(const Level &L, const Level &Lc, int C, const float *e, hipStream_t s);
 // FMG helpers
 template <typename TD>
@@ -167,7 +176,8 @@ void launch_data_restrict0(int W, int H, int C, const uint8_t *mask, const TD *d
 void launch_data_restrict(const Level &L, const Level &Lc, int C, hipStream_t s);
 void launch_fmg_prolong(const Level &L, const Level &Lc, int C, const float *ec, float *out, hipStream_t s);
 void launch_fmg_prolong0(int W, int H, int C, const uint8_t *mask, const Level &Lc, const float *ec, double *u, hipStream_t s);
-void launch_smooth_fmg(const Level &L, int C, int iters, const float *e_in, float *e_out, hipStream_t s);
+void launch_smooth_fmg(const Level &L, int C, int iters, float robin, const float *e_in, float *e_out,
+                       hipStream_t s);
 
 // Build the coarse masks of levels 1..nlev-1 and count known pixels per level
 // into counts[0..nlev) (counts must hold MAX_LEVELS entries).
@@ -184,11 +194,22 @@ struct BLev {
     float *r_c, *aux_c;         // next level's right-hand side and FMG data
     const float *ec;            // next level's final correction (post-smoothing input)
 };
+// What a batched solve's right-hand side is: A x = C d + (I - C) s with d the
+// FP32 image (inpainting), d an FP64 image (tonal: x = B g), or s an FP64
+// source off the mask and d = 0 (tonal: the symmetrised solve of B^T).
+enum { EK_DATA_F32 = 0, EK_DATA_F64 = 1, EK_SRC_F64 = 2 };
+
 // Descriptor of one image in a batch.
 struct BImg {
     int W, H, C, nlev, local_iters, coarse_iters, gx, nblk;
+    int mid_iters;
+    float robin, local_stop;
+    int kind;                 // EK_*
+    int warm;                 // 1: u holds the start on unknown pixels (no FMG)
     const uint8_t *mask;
-    const float *f;
+    const float *f;           // EK_DATA_F32
+    const double *data_d;     // EK_DATA_F64
+    const double *src;        // EK_SRC_F64
     double *u, *u_alt, *partials, *norms;
     unsigned int *counts;
 };
@@ -232,6 +253,35 @@ int32_t densify_step_ex(int W, int H, uint8_t *mask, const float *err, long long
 
 // Coarse masks, known counts and the number of levels for a new mask.
 int32_t prepare_mask(Hierarchy &h, hipStream_t s);
+
+// An executor of inner solves for tonal optimisation (the server's batch
+// engine): A x = C data + (I - C) src on the hierarchy h (planned for `mask`
+// with blocks of `overlap`), with exactly one of data and src given, x the
+// start on unknown pixels when warm. The solve is ordered after the work
+// enqueued on s before the call, later work on s after the solve; x holds the
+// solution when later work on s runs. Returns the status (with the message set
+// on failure) and fills rep's residuals, rounds and V-cycles.
+struct SolveHook {
+    virtual ~SolveHook() = default;
+    virtual int32_t solve(Hierarchy &h, int overlap, int W, int H, int C, const uint8_t *mask, const double *data,
+                          const double *src, double *x, bool warm, const SolveCfg &cfg, hdi_solve_report *rep,
+                          hipStream_t s) = 0;
+};
+
+// tonal_optimize with its inner solves run by `hook` (nullptr: on the calling
+// thread, as tonal_optimize does); the results are the same bit for bit.
+int32_t tonal_optimize_hooked(hdi_image img, const uint8_t *mask, const float *f, double *g, double *u, void *ws,
+                              size_t ws_bytes, const hdi_tonal_params *params, hdi_tonal_report *report, void *stream,
+                              SolveHook *hook);
+// Checks tonal parameters and fills the outer configuration and the inner
+// solves' configuration (HDI_ERR_ARG on a bad value).
+struct TonalCfg {
+    double rel_tol;
+    int max_outer, mode, overlap, local_outer, local_inner, flags;
+    double mse_gain;   // > 0: stop when an iteration improves the MSE by less than this fraction
+    int block;         // RAS block edge, 32 or 64
+};
+int32_t fill_tonal_cfg(const hdi_tonal_params *params, TonalCfg &tc, SolveCfg &inner, int &ov_inner);
 
 // Host driver: solve A x = C data + (I - C) src on the caller's buffers.
 // swap: optional address of the caller's pointer to u. When the refinement ends

@@ -205,7 +205,7 @@ static void vcycle_cost(const Hierarchy &h, int l, const SolveCfg &cfg, double &
         } else {
             const double Nc = (double)h.lev[k + 1].W * h.lev[k + 1].H;
             bytes += 2.0 * N * (1 + 8.0 * C) + Nc * (1 + 4.0 * C) + N * (1 + 12.0 * C) + 4.0 * C * Nc;
-            flops += 2.0 * 15.0 * blk_px * cfg.local_iters;
+            flops += 2.0 * 15.0 * blk_px * (k == 0 ? cfg.local_iters : cfg.mid_iters);
         }
     }
 }
@@ -217,15 +217,19 @@ static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Pr
     Level &L = h.lev[l];
     const int C = h.C;
     if (l == h.nlev - 1) {
-        launch_smooth_pre(L, C, cfg.coarse_iters, L.ea, s);
+        launch_smooth_pre(L, C, cfg.coarse_iters, cfg.robin, nullptr, 0.f, L.ea, s);
         return L.ea;
     }
     Level &Lc = h.lev[l + 1];
     const double N = (double)L.W * L.H, Nc = (double)Lc.W * Lc.H;
     const double blk_px = (double)L.bx.count * L.by.count * std::min(L.tile, L.W) * std::min(L.tile, L.H) * C;
-    const double cg_flops = 15.0 * blk_px * cfg.local_iters;
+    const int iters = l == 0 ? cfg.local_iters : cfg.mid_iters;
+    const double cg_flops = 15.0 * blk_px * iters;
     if (prof) prof->begin(1, N * (1 + 8.0 * C), s, cg_flops);
-    launch_smooth_pre(L, C, cfg.local_iters, L.ea, s);
+    // the global-relative local stop on the finest level, against the norms
+    // of the residual sweep that precedes the V-cycle
+    const double *gnorm = l == 0 ? h.norms : nullptr;
+    launch_smooth_pre(L, C, iters, cfg.robin, gnorm, cfg.local_stop, L.ea, s);
     if (prof) { prof->end(s); prof->begin(3, N * (1 + 8.0 * C) + Nc * (1 + 4.0 * C), s); }
     launch_restrict_residual(L, Lc, C, L.ea, s);
     if (prof) {
@@ -236,7 +240,7 @@ static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Pr
     }
     const float *ec = vcycle(h, l + 1, cfg, s);
     if (prof) { prof->end(s); prof->begin(2, N * (1 + 12.0 * C) + 4.0 * C * Nc, s, cg_flops); }
-    launch_smooth_post(L, Lc, C, cfg.local_iters, L.ea, ec, L.eb, s);
+    launch_smooth_post(L, Lc, C, iters, cfg.robin, gnorm, cfg.local_stop, L.ea, ec, L.eb, s);
     if (prof) prof->end(s);
     return L.eb;
 }
@@ -248,12 +252,12 @@ static void fmg_init(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     launch_data_restrict0<TD>(W, H, C, mask, data, h.lev[1], s);
     for (int l = 2; l < h.nlev; ++l) launch_data_restrict(h.lev[l - 1], h.lev[l], C, s);
     Level &Lc = h.lev[h.nlev - 1];
-    launch_smooth_fmg(Lc, C, cfg.coarse_iters, Lc.aux, Lc.ea, s);
+    launch_smooth_fmg(Lc, C, cfg.coarse_iters, cfg.robin, Lc.aux, Lc.ea, s);
     const float *cur = Lc.ea;
     for (int l = h.nlev - 2; l >= 1; --l) {
         Level &L = h.lev[l];
         launch_fmg_prolong(L, h.lev[l + 1], C, cur, L.eb, s);
-        launch_smooth_fmg(L, C, cfg.local_iters, L.eb, L.ea, s);
+        launch_smooth_fmg(L, C, cfg.mid_iters, cfg.robin, L.eb, L.ea, s);
         cur = L.ea;
     }
     launch_fmg_prolong0(W, H, C, mask, h.lev[1], cur, u, s);
@@ -439,11 +443,15 @@ int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap) {
     cfg.rel_tol = (p && p->rel_tol > 0) ? p->rel_tol : 1e-6;
     cfg.max_outer = (p && p->max_outer > 0) ? p->max_outer : 40;
     cfg.local_iters = (p && p->local_iters > 0) ? p->local_iters : 8;
+    cfg.mid_iters = (p && p->mid_iters > 0) ? p->mid_iters : cfg.local_iters;
     cfg.coarse_iters = (p && p->coarse_iters > 0) ? p->coarse_iters : 64;
     cfg.vcycles = 1;
     cfg.flags = p ? p->flags : 0;
     cfg.small_from = p ? p->small_from : 0;
-    overlap = (p && p->overlap > 0) ? p->overlap : 4;
+    // Robin weight: 0 selects the default 0.6, a negative value Dirichlet (0)
+    cfg.robin = (p && p->robin != 0.f) ? std::max(p->robin, 0.f) : 0.6f;
+    cfg.local_stop = p ? p->local_stop : 0.f;
+    overlap = (p && p->overlap > 0) ? p->overlap : 6;
     if (cfg.flags & ~(HDI_FLAG_NO_FMG | HDI_FLAG_CG)) {
         set_error("unknown solve flags 0x%x", cfg.flags);
         return HDI_ERR_ARG;
@@ -452,10 +460,12 @@ int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap) {
         set_error("overlap %d outside 2..16 or odd", overlap);
         return HDI_ERR_ARG;
     }
-    if (!(cfg.rel_tol < 1.0) || cfg.local_iters > 256 || cfg.coarse_iters > 4096 || cfg.max_outer > 100000 ||
-        cfg.small_from < -1 || cfg.small_from >= MAX_LEVELS) {
-        set_error("parameter out of range (rel_tol < 1, local_iters <= 256, coarse_iters <= 4096, "
-                  "small_from -1..%d)", MAX_LEVELS - 1);
+    if (!(cfg.rel_tol < 1.0) || cfg.local_iters > 256 || cfg.mid_iters > 256 || cfg.coarse_iters > 4096 ||
+        cfg.max_outer > 100000 ||
+        cfg.small_from < -1 || cfg.small_from >= MAX_LEVELS || !(cfg.robin >= 0.f && cfg.robin <= 0.9f) ||
+        !(cfg.local_stop >= 0.f && cfg.local_stop < 1.f)) {
+        set_error("parameter out of range (rel_tol < 1, local_iters and mid_iters <= 256, coarse_iters <= 4096, "
+                  "small_from -1..%d, robin 0..0.9, local_stop 0..1)", MAX_LEVELS - 1);
         return HDI_ERR_ARG;
     }
     return HDI_OK;

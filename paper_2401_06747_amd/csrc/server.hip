@@ -1,12 +1,15 @@
 // Request loop with continuous batching over one device.
 //
-// Inpainting requests go through the batch engine: a worker thread admits
-// waiting requests between refinement rounds (as slots and arena memory free
-// up), runs one round over every running request, and hands back the ones that
-// met their tolerance. Tonal requests run on their own worker threads and
-// streams (each tonal solve is a chain of host-synchronous inner solves), so
-// their kernels overlap the batch rounds on the device. With HDI_SERVER_PLAIN
-// one worker runs the requests one at a time through inpaint_solve and
+// All inpainting solves go through the batch engine: an engine thread admits
+// waiting work between refinement rounds (as slots and arena memory free up),
+// runs one round over everything running, and hands back the solves that met
+// their tolerance. Work comes from inpainting requests and from tonal
+// requests: each tonal request's outer iteration (Sec. 5) runs on a tonal
+// worker thread and stream, and its inner solves (x = B g and the symmetrised
+// solve of B^T) join the engine's shared rounds like inpainting requests do,
+// while its own kernels (gathers, the RAS sweep, vector updates) run on the
+// worker's stream. Events order the two streams. With HDI_SERVER_PLAIN one
+// worker runs the requests one at a time through inpaint_solve and
 // tonal_optimize: the one-request-per-launch control.
 #include <algorithm>
 #include <chrono>
@@ -29,6 +32,7 @@ struct Ticket {
     hdi_request req{};
     hdi_tonal_params tonal{};
     hdi_request_report rep{};
+    hdi_tonal_report tonal_rep{};   // tonal requests: the full report
     std::string message;
     bool done = false;
     char *mem = nullptr;
@@ -41,6 +45,18 @@ struct Ticket {
     size_t ws_bytes = 0;
     EJob ej;
     hipEvent_t ev = nullptr;
+};
+
+// An inner solve of a tonal request, waiting for or running in the engine.
+// It lives on the tonal worker's stack until the engine thread marks it
+// finished; the engine thread does not touch it afterwards.
+struct EngineSolve {
+    EJob ej;
+    hipEvent_t ready = nullptr;   // recorded on the worker's stream: the inputs are written
+    hipEvent_t done = nullptr;    // recorded on the compute stream when the solution is in place
+    int max_running = 0;          // most solves sharing one round with it
+    bool finished = false;
+    int32_t status = HDI_OK;      // HDI_ERR_HIP if the engine failed
 };
 
 static size_t image_px(const hdi_image &img) { return (size_t)img.width * img.height; }
@@ -70,6 +86,8 @@ struct hdi_server {
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Ticket *> q_inp, q_ton, q_all;
+    std::deque<EngineSolve *> q_solve;   // inner solves of tonal requests
+    std::vector<hipEvent_t> worker_events;   // two per tonal worker
     std::unordered_map<uint64_t, std::unique_ptr<Ticket>> tickets;
     std::vector<std::thread> threads;
     uint64_t next_id = 1;
@@ -147,12 +165,67 @@ struct hdi_server {
         cv.notify_all();
     }
 
-    void run_tonal(Ticket *t, hipStream_t s) {
+    // The tonal workers' inner solves, handed to the engine thread.
+    struct Hook : SolveHook {
+        hdi_server *srv;
+        hipEvent_t ready, done;
+        int max_running = 0;
+        int32_t solve(Hierarchy &h, int overlap, int W, int H, int C, const uint8_t *mask, const double *data,
+                      const double *src, double *x, bool warm, const SolveCfg &cfg, hdi_solve_report *rep,
+                      hipStream_t s) override {
+            EngineSolve es;
+            es.ej.job = hdi_job{HDI_JOB_INPAINT, hdi_image{W, H, C}, mask, nullptr, x, nullptr, nullptr};
+            es.ej.kind = data ? EK_DATA_F64 : EK_SRC_F64;
+            es.ej.data_d = data;
+            es.ej.src = src;
+            es.ej.warm = warm;
+            es.ej.cfg = cfg;
+            es.ej.overlap = overlap;
+            es.ej.h = h;
+            es.ej.user = &es;
+            es.ready = ready;
+            es.done = done;
+            if (hipEventRecord(ready, s) != hipSuccess) {
+                set_error("recording an inner solve's start failed");
+                return HDI_ERR_HIP;
+            }
+            {
+                std::unique_lock<std::mutex> lk(srv->mu);
+                srv->q_solve.push_back(&es);
+                srv->cv.notify_all();
+                srv->cv.wait(lk, [&] { return es.finished; });
+            }
+            max_running = std::max(max_running, es.max_running);
+            if (es.status != HDI_OK) {
+                set_error("the batch engine failed during an inner solve");
+                return es.status;
+            }
+            if (hipStreamWaitEvent(s, done, 0) != hipSuccess) {
+                set_error("waiting for an inner solve failed");
+                return HDI_ERR_HIP;
+            }
+            const EJob &j = es.ej;
+            for (int c = 0; c < 3; ++c) rep->rel_residual[c] = c < C ? j.rel[c] : 0.0;
+            rep->outer_iters = j.rounds;
+            rep->vcycles = j.rounds;
+            rep->ms = 0.f;
+            if (j.status == HDI_ERR_NO_CONVERGENCE) {
+                set_error("relative residual %.3e above tolerance %.3e after %d rounds",
+                          std::max(j.rel[0], std::max(j.rel[1], j.rel[2])), cfg.rel_tol, j.rounds);
+            } else if (j.status == HDI_ERR_ARG) {
+                set_error("non-finite residual: the input holds NaN/Inf or the iteration diverged");
+            }
+            return j.status;
+        }
+    };
+
+    void run_tonal(Ticket *t, hipStream_t s, Hook *hook = nullptr) {
         int32_t st = place(t, s);
         hdi_tonal_report tr{};
         if (!st) {
             t->tonal.flags |= HDI_TONAL_INIT_FROM_F;
-            st = tonal_optimize(t->req.img, t->mask, t->f, t->out, nullptr, t->ws, t->ws_bytes, &t->tonal, &tr, s);
+            st = tonal_optimize_hooked(t->req.img, t->mask, t->f, t->out, nullptr, t->ws, t->ws_bytes, &t->tonal, &tr,
+                                       s, hook);
         }
         const std::string msg = st ? hdi_last_error() : "";
         bool sealed = false;
@@ -161,8 +234,13 @@ struct hdi_server {
             else sealed = true;
         }
         if (!sealed) quiesce(t, s);
+        t->tonal_rep = tr;
         t->rep.outer_iters = tr.outer_iters;
         t->rep.inner_solves = tr.inner_solves;
+        if (hook) {
+            t->rep.max_running = hook->max_running;
+            hook->max_running = 0;
+        }
         t->rep.rel_residual[0] = tr.rel_normal_residual;
         t->rep.mse_initial = tr.mse_initial;
         t->rep.mse_final = tr.mse_final;
@@ -215,6 +293,10 @@ struct hdi_server {
 
     void tonal_loop(int w) {
         (void)hipSetDevice(device);
+        Hook hook;
+        hook.srv = this;
+        hook.ready = worker_events[2 * w];
+        hook.done = worker_events[2 * w + 1];
         for (;;) {
             Ticket *t = nullptr;
             {
@@ -222,33 +304,56 @@ struct hdi_server {
                 cv.wait(lk, [&] { return (t = take(q_ton)) != nullptr || (stop && q_ton.empty()); });
             }
             if (!t) return;
-            run_tonal(t, tonal_streams[w]);
+            run_tonal(t, tonal_streams[w], &hook);
         }
+    }
+
+    // End an inner solve (under the lock): its waiting worker may go on.
+    void end_solve(EngineSolve *es, int32_t status) {
+        std::lock_guard<std::mutex> lk(mu);
+        es->status = status;
+        es->finished = true;
+        cv.notify_all();
     }
 
     void engine_loop() {
         (void)hipSetDevice(device);
         std::vector<Ticket *> sealed;   // device work enqueued, waiting for its event
-        std::vector<Ticket *> live;     // requests in the engine
+        std::vector<EJob *> live;       // jobs in the engine (requests and inner solves)
         for (;;) {
             std::vector<Ticket *> admitted;
+            std::vector<EngineSolve *> solves;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 for (;;) {
                     std::vector<int> slots = eng.free_slots();
                     size_t k = 0;
+                    // inner solves first: their requests hold memory already
+                    while (k < slots.size() && !q_solve.empty()) {
+                        EngineSolve *es = q_solve.front();
+                        q_solve.pop_front();
+                        es->ej.slot = slots[k++];
+                        solves.push_back(es);
+                    }
                     while (k < slots.size()) {
                         Ticket *t = take(q_inp);
                         if (!t) break;
                         t->ej.slot = slots[k++];
                         admitted.push_back(t);
                     }
-                    if (!admitted.empty() || eng.running() > 0 || !sealed.empty()) break;
+                    if (!admitted.empty() || !solves.empty() || eng.running() > 0 || !sealed.empty()) break;
                     if (stop && q_inp.empty()) return;
                     cv.wait(lk);
                 }
             }
             std::vector<EJob *> news, ended;
+            for (EngineSolve *es : solves) {
+                if (hipStreamWaitEvent(compute, es->ready, 0) != hipSuccess) {
+                    end_solve(es, HDI_ERR_HIP);
+                    continue;
+                }
+                news.push_back(&es->ej);
+            }
             for (Ticket *t : admitted) {
                 int32_t st = place(t, compute);
                 if (st) {
@@ -258,7 +363,7 @@ struct hdi_server {
                     continue;
                 }
                 EJob &j = t->ej;
-                j.job = hdi_job{t->req.img, t->mask, t->f, t->out};
+                j.job = hdi_job{HDI_JOB_INPAINT, t->req.img, t->mask, t->f, t->out, nullptr, nullptr};
                 j.user = t;
                 Arena a{t->ws, t->ws_bytes, 0};
                 plan_hierarchy(j.h, a, t->req.img.width, t->req.img.height, t->req.img.channels, j.overlap, t->mask,
@@ -268,23 +373,43 @@ struct hdi_server {
             int32_t st = eng.admit(news, ended, compute);
             if (!st) st = eng.round(ended, compute);
             if (st) {
-                // a HIP failure leaves the batch undefined: end every running request
+                // a HIP failure leaves the batch undefined: end every running job
                 const std::string msg = hdi_last_error();
                 eng.abort_all(ended);
                 live.clear();
+                (void)hipStreamSynchronize(compute);
                 for (EJob *j : ended) {
+                    if (j->kind != EK_DATA_F32) {
+                        end_solve((EngineSolve *)j->user, st);
+                        continue;
+                    }
                     Ticket *t = (Ticket *)j->user;
                     quiesce(t, compute);
                     finish(t, st, msg.c_str());
                 }
                 continue;
             }
-            // this round ran every live request, the ones that just ended included
-            for (EJob *j : news) live.push_back((Ticket *)j->user);
+            // this round ran every live job, the ones that just ended included
+            for (EJob *j : news) live.push_back(j);
             const int nround = (int)live.size();
-            for (Ticket *t : live) t->rep.max_running = std::max(t->rep.max_running, nround);
-            for (EJob *j : ended) live.erase(std::find(live.begin(), live.end(), (Ticket *)j->user));
+            for (EJob *j : live) {
+                if (j->kind == EK_DATA_F32) {
+                    Ticket *t = (Ticket *)j->user;
+                    t->rep.max_running = std::max(t->rep.max_running, nround);
+                } else {
+                    EngineSolve *es = (EngineSolve *)j->user;
+                    es->max_running = std::max(es->max_running, nround);
+                }
+            }
+            for (EJob *j : ended) live.erase(std::find(live.begin(), live.end(), j));
             for (EJob *j : ended) {
+                if (j->kind != EK_DATA_F32) {
+                    // an inner solve: its solution (copied back on the compute
+                    // stream) is in place once `done` has passed
+                    EngineSolve *es = (EngineSolve *)j->user;
+                    end_solve(es, hipEventRecord(es->done, compute) == hipSuccess ? HDI_OK : HDI_ERR_HIP);
+                    continue;
+                }
                 Ticket *t = (Ticket *)j->user;
                 t->rep.outer_iters = j->rounds;
                 for (int c = 0; c < 3; ++c) t->rep.rel_residual[c] = c < j->h.C ? j->rel[c] : 0.0;
@@ -360,6 +485,14 @@ hdi_server *hdi_server_create(void *arena, size_t arena_bytes, int32_t max_slots
             return nullptr;
         }
         srv->tonal_streams.push_back(s);
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t e;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                set_error("event creation failed");
+                return nullptr;
+            }
+            srv->worker_events.push_back(e);
+        }
     }
     hdi_server *p = srv.get();
     if (flags & HDI_SERVER_PLAIN) {
@@ -391,6 +524,18 @@ int32_t hdi_server_submit(hdi_server *srv, const hdi_request *req, uint64_t *tic
     t->req.tonal = nullptr;
     int32_t st = fill_cfg(&t->req.solve, t->ej.cfg, t->ej.overlap);
     if (st) return st;
+    if (req->kind == HDI_REQ_TONAL) {
+        TonalCfg tc;
+        SolveCfg inner;
+        int ov = 0;
+        st = fill_tonal_cfg(req->tonal, tc, inner, ov);
+        if (st) return st;
+        if ((inner.flags & HDI_FLAG_CG) && !(srv->flags & HDI_SERVER_PLAIN)) {
+            set_error("tonal requests' inner solves run in the batch engine, which runs the multigrid solver only "
+                      "(HDI_FLAG_CG is for single solves)");
+            return HDI_ERR_ARG;
+        }
+    }
     if (t->ej.cfg.flags & HDI_FLAG_CG) {
         set_error("the server runs the multigrid solver only (HDI_FLAG_CG is for single solves)");
         return HDI_ERR_ARG;
@@ -470,6 +615,7 @@ void hdi_server_destroy(hdi_server *srv) {
     }
     for (std::thread &th : srv->threads) th.join();
     for (auto &kv : srv->tickets) (void)hipEventDestroy(kv.second->ev);
+    for (hipEvent_t e : srv->worker_events) (void)hipEventDestroy(e);
     for (hipStream_t s : srv->tonal_streams) (void)hipStreamDestroy(s);
     (void)hipStreamDestroy(srv->copy);
     (void)hipStreamDestroy(srv->compute);
@@ -477,3 +623,81 @@ void hdi_server_destroy(hdi_server *srv) {
 }
 
 }  // extern "C"
+
+namespace hdi {
+
+size_t batch_served_bytes(int n, const hdi_job *jobs) {
+    Engine e;
+    Arena a{nullptr, 0, 0};
+    e.plan(a, n);
+    size_t total = up256(a.used);
+    for (int i = 0; i < n; ++i) {
+        hdi_request r{};
+        r.kind = jobs[i].kind == HDI_JOB_TONAL ? HDI_REQ_TONAL : HDI_REQ_INPAINT;
+        r.img = jobs[i].img;
+        const size_t b = hdi_request_bytes(&r);
+        if (!b) return 0;
+        total += up256(b);
+    }
+    return total + 256;
+}
+
+int32_t solve_batch_served(int n, const hdi_job *jobs, void *ws, size_t ws_bytes, const hdi_solve_params *params,
+                           hdi_solve_report *reports, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    // the jobs' inputs were written on the caller's stream
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        set_error("synchronising the caller's stream failed");
+        return HDI_ERR_HIP;
+    }
+    int ntonal = 0;
+    for (int i = 0; i < n; ++i) ntonal += jobs[i].kind == HDI_JOB_TONAL;
+    hdi_server *srv = hdi_server_create(ws, ws_bytes, n, std::min(ntonal, 16), 0);
+    if (!srv) return HDI_ERR_HIP;
+    std::vector<uint64_t> tickets(n, 0);
+    int32_t st = HDI_OK;
+    for (int i = 0; i < n && st == HDI_OK; ++i) {
+        hdi_request r{};
+        r.kind = jobs[i].kind == HDI_JOB_TONAL ? HDI_REQ_TONAL : HDI_REQ_INPAINT;
+        r.img = jobs[i].img;
+        r.mask = jobs[i].mask;
+        r.f = jobs[i].f;
+        r.out = jobs[i].out;
+        if (params) r.solve = params[i];
+        r.tonal = jobs[i].tonal;
+        st = hdi_server_submit(srv, &r, &tickets[i]);
+    }
+    hdi_server_drain(srv);
+    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int32_t worst = st;
+    std::string first_msg = st ? hdi_last_error() : "";
+    for (int i = 0; i < n; ++i) {
+        if (!tickets[i]) continue;
+        Ticket *t = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            auto it = srv->tickets.find(tickets[i]);
+            if (it != srv->tickets.end()) t = it->second.get();
+        }
+        if (!t) continue;
+        if (reports) {
+            for (int c = 0; c < 3; ++c) reports[i].rel_residual[c] = t->rep.rel_residual[c];
+            reports[i].outer_iters = t->rep.outer_iters;
+            reports[i].vcycles = t->req.kind == HDI_REQ_TONAL ? t->tonal_rep.inner_vcycles : t->rep.outer_iters;
+            reports[i].ms = ms;
+        }
+        if (t->req.kind == HDI_REQ_TONAL && jobs[i].tonal_report) {
+            *jobs[i].tonal_report = t->tonal_rep;
+            jobs[i].tonal_report->ms = ms;
+        }
+        if (t->rep.status != HDI_OK && worst == HDI_OK) {
+            worst = t->rep.status;
+            first_msg = "job " + std::to_string(i) + ": " + t->message;
+        }
+    }
+    hdi_server_destroy(srv);
+    if (worst != HDI_OK) set_error("%s", first_msg.c_str());
+    return worst;
+}
+
+}  // namespace hdi

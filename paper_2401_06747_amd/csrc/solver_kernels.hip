@@ -419,8 +419,9 @@ __device__ __forceinline__ void lds_get(const float *src, float *v) {
 }
 
 template <int MODE, int T>
-__device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, int sx, int sy, int iters,
-                                              const uint8_t *__restrict__ mask, const float *__restrict__ r,
+__device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, int sx, int sy, int iters, float robin,
+                                              float stop_sq, const uint8_t *__restrict__ mask,
+                                              const float *__restrict__ r,
                                               const float *__restrict__ e_in, const float *__restrict__ ec, int Wc,
                                               int Hc, float *__restrict__ e_out, const int t, const int c) {
     using G = TileGeom<T>;
@@ -544,7 +545,12 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
                     res -= d * e0 - sn;
                 }
             }
-            dg[k] = d;
+            // local operator: an edge to a pixel outside the block (not the
+            // image border) adds 1 - robin to the diagonal (Robin transmission
+            // condition; robin = 0 is a zero Dirichlet value outside)
+            const int cross = (lx == 0 && x > 0) + (lx == Tx - 1 && x < W - 1) + (ly == 0 && y > 0) +
+                              (ly == Ty - 1 && y < H - 1);
+            dg[k] = d > 0.f ? d - robin * (float)cross : 0.f;
             v[k] = e0;
             rl[k] = res;
         }
@@ -564,9 +570,10 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     // block operator to the residual and takes both inner products, (r, r) and
     // (A r, r), in one merged wavefront reduction; the directions follow from
     // the recurrences p = r + beta p, s = A r + beta s (s = A p). It stops after
-    // `iters` steps or once the block residual has fallen to the FP32 rounding
-    // floor (squared norm 1e-14 of the start); the reciprocals also need normal
-    // (not denormal) divisors.
+    // `iters` steps, once the block residual has fallen to the FP32 rounding
+    // floor (squared norm 1e-14 of the start), or once its squared norm is at
+    // most stop_sq (the global-relative stop of Sec. 3.3; 0: off); the
+    // reciprocals also need normal (not denormal) divisors.
     float p[NPX], sv[NPX];
 #pragma unroll
     for (int k = 0; k < NPX; ++k) p[k] = sv[k] = 0.f;
@@ -598,7 +605,7 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
                 delta += w[k] * rl[k];
             }
         wave_sum2(gamma, delta);
-        if (it == 0) rr_floor = gamma * 1e-14f;
+        if (it == 0) rr_floor = fmaxf(gamma * 1e-14f, stop_sq);
         if (!(gamma > rr_floor && gamma >= FLT_MIN)) break;
         const float beta = it == 0 ? 0.f : gamma * __builtin_amdgcn_rcpf(gamma_prev);
         const float denom = delta - beta * gamma * __builtin_amdgcn_rcpf(alpha_prev);
@@ -634,13 +641,20 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
         }
 }
 
+// Squared-residual level below which a block's local CG stops: the fraction
+// `frac` of the channel's global squared residual norm (gnorm[c * stride],
+// FP64), or 0 without one (Sec. 3.3).
+__device__ __forceinline__ float local_stop_sq(const double *__restrict__ gnorm, int stride, float frac, int c) {
+    return gnorm && frac > 0.f ? (float)((double)frac * gnorm[(size_t)c * stride]) : 0.f;
+}
+
 template <int MODE, int T>
 __global__ void __launch_bounds__(64)
-k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters,
-          const uint8_t *__restrict__ mask, const float *__restrict__ r, const float *__restrict__ e_in,
+k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters, float robin, const double *gnorm,
+          float frac, const uint8_t *__restrict__ mask, const float *__restrict__ r, const float *__restrict__ e_in,
           const float *__restrict__ ec, int Wc, int Hc, float *__restrict__ e_out) {
-    schwarz_block<MODE, T>(W, H, ntx, nty, sx, sy, iters, mask, r, e_in, ec, Wc, Hc, e_out,
-                           xcd_remap(blockIdx.x, ntx * nty), blockIdx.y);
+    schwarz_block<MODE, T>(W, H, ntx, nty, sx, sy, iters, robin, local_stop_sq(gnorm, 2, frac, blockIdx.y), mask,
+                           r, e_in, ec, Wc, Hc, e_out, xcd_remap(blockIdx.x, ntx * nty), blockIdx.y);
 }
 
 // ------------------------------------------------------------------ reduced FMG (Sec. 3.2)
@@ -758,29 +772,32 @@ void launch_update(int W, int H, int C, const uint8_t *mask, const float *e, dou
 }
 
 template <int MODE>
-static void launch_schwarz(const Level &L, int C, int iters, const float *r, const float *e_in, const float *ec,
-                           int Wc, int Hc, float *e_out, hipStream_t s) {
+static void launch_schwarz(const Level &L, int C, int iters, float robin, const double *gnorm, float frac,
+                           const float *r, const float *e_in, const float *ec, int Wc, int Hc, float *e_out,
+                           hipStream_t s) {
     const dim3 g(L.bx.count * L.by.count, C);
     if (L.tile == 16)
         hipLaunchKernelGGL((k_schwarz<MODE, 16>), g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count,
-                           L.bx.stride, L.by.stride, iters, L.mask, r, e_in, ec, Wc, Hc, e_out);
+                           L.bx.stride, L.by.stride, iters, robin, gnorm, frac, L.mask, r, e_in, ec, Wc, Hc, e_out);
     else
         hipLaunchKernelGGL((k_schwarz<MODE, 32>), g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count,
-                           L.bx.stride, L.by.stride, iters, L.mask, r, e_in, ec, Wc, Hc, e_out);
+                           L.bx.stride, L.by.stride, iters, robin, gnorm, frac, L.mask, r, e_in, ec, Wc, Hc, e_out);
 }
 
-void launch_smooth_pre(const Level &L, int C, int iters, float *e_out, hipStream_t s) {
-    launch_schwarz<0>(L, C, iters, L.r, nullptr, nullptr, 1, 1, e_out, s);
+void launch_smooth_pre(const Level &L, int C, int iters, float robin, const double *gnorm, float frac, float *e_out,
+                       hipStream_t s) {
+    launch_schwarz<0>(L, C, iters, robin, gnorm, frac, L.r, nullptr, nullptr, 1, 1, e_out, s);
 }
 
-void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, const float *e_in, const float *ec,
-                        float *e_out, hipStream_t s) {
-    launch_schwarz<1>(L, C, iters, L.r, e_in, ec, Lc.W, Lc.H, e_out, s);
+void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, float robin, const double *gnorm,
+                        float frac, const float *e_in, const float *ec, float *e_out, hipStream_t s) {
+    launch_schwarz<1>(L, C, iters, robin, gnorm, frac, L.r, e_in, ec, Lc.W, Lc.H, e_out, s);
 }
 
-void launch_smooth_fmg(const Level &L, int C, int iters, const float *e_in, float *e_out, hipStream_t s) {
+void launch_smooth_fmg(const Level &L, int C, int iters, float robin, const float *e_in, float *e_out,
+                       hipStream_t s) {
     // the full problem A u = C d has a zero right-hand side on unknown pixels
-    launch_schwarz<2>(L, C, iters, nullptr, e_in, nullptr, 1, 1, e_out, s);
+    launch_schwarz<2>(L, C, iters, robin, nullptr, 0.f, nullptr, e_in, nullptr, 1, 1, e_out, s);
 }
 
 void launch_restrict_residual(const Level &L, const Level &Lc, int C, const float *e, hipStream_t s) {
@@ -1070,10 +1087,17 @@ kb_count(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L, con
     }
 }
 
+// Starting iterate: the data (or 0 for a source problem) on known pixels;
+// unknown pixels 0, or kept for a warm start.
 __global__ void kb_init_u(const int4 *__restrict__ seg, int nseg, const BImg *__restrict__ I) {
     const SegItem it = seg_item(seg, nseg, blockIdx.x);
     const BImg &im = I[it.img];
-    init_u_at<float>(it.a * 256 + threadIdx.x, im.W * im.H, im.C, im.mask, im.f, nullptr, im.u);
+    const int i = it.a * 256 + threadIdx.x, N = im.W * im.H;
+    if (i >= N || (im.warm && !im.mask[i])) return;
+    if (im.kind == EK_DATA_F32)
+        init_u_at<float>(i, N, im.C, im.mask, im.f, nullptr, im.u);
+    else
+        init_u_at<double>(i, N, im.C, im.mask, im.kind == EK_DATA_F64 ? im.data_d : nullptr, nullptr, im.u);
 }
 
 // flags[img]: bit 1 = apply the last V-cycle's correction, bit 2 = the current
@@ -1092,8 +1116,16 @@ kb_residual(const int4 *__restrict__ seg, int nseg, const BImg *__restrict__ I, 
     // the last V-cycle's correction is the finest level's post-smoothing
     // output (or the single level's smoothing output)
     const float *e = use_e ? (im.nlev > 1 ? l0.eb : l0.ea) : nullptr;
-    residual_block<float, C, false>(im.W, im.H, im.mask, u_in, e, use_e ? u_out : nullptr, im.f, nullptr, l0.r,
-                             im.partials, im.nblk, it.a, it.b, im.gx);
+    double *uo = use_e ? u_out : nullptr;
+    if (im.kind == EK_DATA_F32)
+        residual_block<float, C, false>(im.W, im.H, im.mask, u_in, e, uo, im.f, nullptr, l0.r, im.partials, im.nblk,
+                                        it.a, it.b, im.gx);
+    else if (im.kind == EK_DATA_F64)
+        residual_block<double, C, false>(im.W, im.H, im.mask, u_in, e, uo, im.data_d, nullptr, l0.r, im.partials,
+                                         im.nblk, it.a, it.b, im.gx);
+    else
+        residual_block<double, C, true>(im.W, im.H, im.mask, u_in, e, uo, (const double *)nullptr, im.src, l0.r,
+                                        im.partials, im.nblk, it.a, it.b, im.gx);
 }
 
 __global__ void __launch_bounds__(1024)
@@ -1109,16 +1141,19 @@ kb_schwarz(const int4 *__restrict__ seg, int nseg, int n, const BLev *__restrict
     const SegItem it = seg_item(seg, nseg, xcd_remap(blockIdx.x, n));
     const BImg &im = I[it.img];
     const BLev &l = L[it.img * MAX_LEVELS + it.lev];
-    const int iters = COARSEST ? im.coarse_iters : im.local_iters;
+    const int iters = COARSEST ? im.coarse_iters : it.lev == 0 ? im.local_iters : im.mid_iters;
+    // the global-relative local stop on the finest level of a V-cycle (the
+    // residual sweep before it left the global norms in im.norms)
+    const float stop_sq = MODE != 2 && !COARSEST && it.lev == 0 ? local_stop_sq(im.norms, 2, im.local_stop, it.b) : 0.f;
     if (MODE == 0)
-        schwarz_block<0, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, nullptr, nullptr, 1, 1, l.ea,
-                            it.a, it.b);
-    else if (MODE == 1)
-        schwarz_block<1, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, l.r, l.ea, l.ec, l.Wc, l.Hc, l.eb,
-                            it.a, it.b);
-    else
-        schwarz_block<2, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, l.mask, nullptr, COARSEST ? l.aux : l.eb,
+        schwarz_block<0, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, im.robin, stop_sq, l.mask, l.r, nullptr,
                             nullptr, 1, 1, l.ea, it.a, it.b);
+    else if (MODE == 1)
+        schwarz_block<1, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, im.robin, stop_sq, l.mask, l.r, l.ea, l.ec,
+                            l.Wc, l.Hc, l.eb, it.a, it.b);
+    else
+        schwarz_block<2, T>(l.W, l.H, l.ntx, l.nty, l.sx, l.sy, iters, im.robin, 0.f, l.mask, nullptr,
+                            COARSEST ? l.aux : l.eb, nullptr, 1, 1, l.ea, it.a, it.b);
 }
 
 __global__ void kb_restrict(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L,
@@ -1135,8 +1170,12 @@ __global__ void kb_data_restrict(const int4 *__restrict__ seg, int nseg, const B
     const SegItem it = seg_item(seg, nseg, blockIdx.x);
     const BImg &im = I[it.img];
     const BLev &l = L[it.img * MAX_LEVELS + it.lev];
-    const float *src = FROM_F ? im.f : l.aux;
-    data_restrict_at<float>(it.a * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, src, l.Wc, l.Hc, l.mask_c, l.aux_c);
+    if (FROM_F && im.kind == EK_DATA_F64)
+        data_restrict_at<double>(it.a * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, im.data_d, l.Wc, l.Hc, l.mask_c,
+                                 l.aux_c);
+    else
+        data_restrict_at<float>(it.a * 256 + threadIdx.x, l.W, l.H, im.C, l.mask, FROM_F ? im.f : l.aux, l.Wc, l.Hc,
+                                l.mask_c, l.aux_c);
 }
 
 __global__ void kb_fmg_prolong(const int4 *__restrict__ seg, int nseg, const BLev *__restrict__ L,

@@ -103,17 +103,26 @@ struct TonalCtx {
     SolveCfg inner;
     hipStream_t s;
     Prof *prof;
+    SolveHook *hook;   // runs the inner solves when set
+    int overlap;       // block overlap of the inner solves' hierarchy
     int solves = 0, vcycles = 0;
 
+    // One inner solve on this thread, or through the hook. x: a workspace
+    // buffer, which on this thread may trade places with the hierarchy's
+    // second iterate buffer instead of receiving a copy.
+    int32_t inner_solve(const double *data, const double *src, double *&x, bool warm, const SolveCfg &c,
+                        hdi_solve_report &rep) {
+        if (hook) return hook->solve(t.h, overlap, W, H, C, mask, data, src, x, warm, c, &rep, s);
+        return solve_system<double>(t.h, W, H, C, mask, data, src, x, warm, c, &rep, s, prof, &x);
+    }
+
     // u = B x for x given on K (compact); cold start with FMG unless warm.
-    // u: a workspace buffer, which may trade places with the hierarchy's
-    // second iterate buffer instead of receiving a copy
     int32_t apply_B(const double *xK, double *&u, bool warm, double tol) {
         launch_scatter_K(m, C, N, t.idx, xK, t.img_d, s);
         SolveCfg c = inner;
         c.rel_tol = tol;
         hdi_solve_report rep;
-        int32_t st = solve_system<double>(t.h, W, H, C, mask, t.img_d, nullptr, u, warm, c, &rep, s, prof, &u);
+        int32_t st = inner_solve(t.img_d, nullptr, u, warm, c, rep);
         if (st) set_error("inner B solve (tol %.1e, warm %d): %s", tol, (int)warm, hdi_last_error());
         ++solves;
         vcycles += (c.flags & HDI_FLAG_CG) ? rep.outer_iters : rep.vcycles;
@@ -127,8 +136,7 @@ struct TonalCtx {
         SolveCfg c = inner;
         c.rel_tol = tol;
         hdi_solve_report rep;
-        int32_t st =
-            solve_system<double>(t.h, W, H, C, mask, (const double *)nullptr, ysrc, w, warm, c, &rep, s, prof, &w);
+        int32_t st = inner_solve(nullptr, ysrc, w, warm, c, rep);
         if (st) set_error("inner B^T solve (tol %.1e, warm %d): %s", tol, (int)warm, hdi_last_error());
         ++solves;
         vcycles += (c.flags & HDI_FLAG_CG) ? rep.outer_iters : rep.vcycles;
@@ -180,13 +188,6 @@ __global__ void k_gather_d(int m, int C, int N, const int *__restrict__ idx, con
     if (j >= m) return;
     for (int c = 0; c < C; ++c) v[(size_t)c * m + j] = img[(size_t)c * N + idx[j]];
 }
-
-struct TonalCfg {
-    double rel_tol;
-    int max_outer, mode, overlap, local_outer, local_inner, flags;
-    double mse_gain;   // > 0: stop when an iteration improves the MSE by less than this fraction
-    int block;         // RAS block edge, 32 or 64
-};
 
 static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double *u_out, hdi_tonal_report *rep) {
     TonalWs &t = X.t;
@@ -471,12 +472,14 @@ size_t hdi_tonal_workspace_bytes(hdi_image img) {
 
 int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, double *g, double *u, void *ws,
                        size_t ws_bytes, const hdi_tonal_params *params, hdi_tonal_report *report, void *stream) {
-    if (!check_image(img)) return HDI_ERR_ARG;
-    if (!mask || !f || !g) {
-        set_error("mask, f and g must be non-null device pointers");
-        return HDI_ERR_ARG;
-    }
-    TonalCfg tc;
+    return tonal_optimize_hooked(img, mask, f, g, u, ws, ws_bytes, params, report, stream, nullptr);
+}
+
+}  // extern "C"
+
+namespace hdi {
+
+int32_t fill_tonal_cfg(const hdi_tonal_params *params, TonalCfg &tc, SolveCfg &inner, int &ov_inner) {
     tc.rel_tol = (params && params->rel_tol > 0) ? params->rel_tol : 1e-6;
     tc.max_outer = (params && params->max_outer > 0) ? params->max_outer : 500;
     tc.mode = params ? params->mode : HDI_TONAL_PCG_RAS;
@@ -493,10 +496,26 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
                   "even overlap 2..block/2)");
         return HDI_ERR_ARG;
     }
+    return fill_cfg(params ? &params->inner : nullptr, inner, ov_inner);
+}
+
+int32_t tonal_optimize_hooked(hdi_image img, const uint8_t *mask, const float *f, double *g, double *u, void *ws,
+                              size_t ws_bytes, const hdi_tonal_params *params, hdi_tonal_report *report, void *stream,
+                              SolveHook *hook) {
+    if (!check_image(img)) return HDI_ERR_ARG;
+    if (!mask || !f || !g) {
+        set_error("mask, f and g must be non-null device pointers");
+        return HDI_ERR_ARG;
+    }
+    TonalCfg tc;
     SolveCfg inner;
     int ov_inner;
-    int32_t st = fill_cfg(params ? &params->inner : nullptr, inner, ov_inner);
+    int32_t st = fill_tonal_cfg(params, tc, inner, ov_inner);
     if (st) return st;
+    if (hook && (inner.flags & HDI_FLAG_CG)) {
+        set_error("inner solves by the batch engine run the multigrid solver only (HDI_FLAG_CG is for single solves)");
+        return HDI_ERR_ARG;
+    }
     const size_t need = tonal_ws_bytes(img.width, img.height, img.channels);
     if (!ws || ws_bytes < need) {
         set_error("workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
@@ -523,7 +542,7 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
     T_TRY(hipGetLastError());
     inner.known = t.h.known[0];
     Prof *prof = prof_for_call();
-    TonalCtx X{t, img.width, img.height, C, N, m, mask, f, inner, s, prof};
+    TonalCtx X{t, img.width, img.height, C, N, m, mask, f, inner, s, prof, hook, ov_inner};
     st = run_tonal(X, tc, g, u, report);
     if (prof) {
         prof->flush();
@@ -535,4 +554,4 @@ int32_t tonal_optimize(hdi_image img, const uint8_t *mask, const float *f, doubl
     return st;
 }
 
-}  // extern "C"
+}  // namespace hdi

@@ -67,10 +67,17 @@ static void sizes(void) {
     CHECK(hdi_labels_workspace_bytes(1920, 1080) > 0 && hdi_initial_mask_workspace_bytes(big) > 0);
     CHECK(hdi_noalloc_scratch_bytes() == ((size_t)HDI_NOALLOC_SCRATCH_MB << 20));
 
-    hdi_job jobs[2] = {{{64, 48, 1}, DEV, DEV, DEV}, {{100, 70, 3}, DEV, DEV, DEV}};
+    hdi_job jobs[2] = {{HDI_JOB_INPAINT, {64, 48, 1}, DEV, DEV, DEV, NULL, NULL},
+                       {HDI_JOB_INPAINT, {100, 70, 3}, DEV, DEV, DEV, NULL, NULL}};
     const size_t two = hdi_batch_workspace_bytes(2, jobs);
     CHECK(two >= hdi_inpaint_workspace_bytes(jobs[0].img) + hdi_inpaint_workspace_bytes(jobs[1].img));
     CHECK(hdi_batch_workspace_bytes(1, jobs) < two);
+    /* a tonal job runs with its tonal workspace (plus staging-free request state) */
+    jobs[1].kind = HDI_JOB_TONAL;
+    CHECK(hdi_batch_workspace_bytes(2, jobs) >= hdi_tonal_workspace_bytes(jobs[1].img));
+    jobs[1].kind = 5;
+    CHECK(hdi_batch_workspace_bytes(2, jobs) == 0);
+    jobs[1].kind = HDI_JOB_INPAINT;
     jobs[1].img.channels = 2;
     CHECK(hdi_batch_workspace_bytes(2, jobs) == 0);
     CHECK(hdi_batch_workspace_bytes(0, jobs) == 0);
@@ -106,6 +113,15 @@ static void argument_errors(void) {
     sp.rel_tol = 2.0;
     FAILS(HDI_ERR_ARG, inpaint_solve(img, DEV, DEV, DEV, NULL, DEV, 1 << 30, &sp, &rep, NULL));
     sp.rel_tol = 0.0;
+    sp.robin = 0.95f; /* Robin weight above 0.9 */
+    FAILS(HDI_ERR_ARG, inpaint_solve(img, DEV, DEV, DEV, NULL, DEV, 1 << 30, &sp, &rep, NULL));
+    sp.robin = 0.5f;
+    sp.local_stop = 1.0f; /* local stop fraction must be below 1 */
+    FAILS(HDI_ERR_ARG, inpaint_solve(img, DEV, DEV, DEV, NULL, DEV, 1 << 30, &sp, &rep, NULL));
+    sp.local_stop = -0.5f;
+    FAILS(HDI_ERR_ARG, inpaint_solve(img, DEV, DEV, DEV, NULL, DEV, 1 << 30, &sp, &rep, NULL));
+    sp.robin = 0.0f;
+    sp.local_stop = 0.0f;
     FAILS(HDI_ERR_WORKSPACE, inpaint_solve(img, DEV, DEV, DEV, NULL, DEV, 16, &sp, &rep, NULL));
     FAILS(HDI_ERR_WORKSPACE, inpaint_solve(img, DEV, DEV, DEV, NULL, NULL, 1 << 30, &sp, &rep, NULL));
     FAILS(HDI_ERR_WORKSPACE, inpaint_solve_noalloc((hdi_image){3840, 2160, 3}, DEV, DEV, DEV, NULL, NULL, &rep, NULL));
@@ -154,9 +170,19 @@ static void argument_errors(void) {
     float best_ms = 0.f;
     FAILS(HDI_ERR_ARG, hdi_autotune(img, DEV, DEV, DEV, 1 << 30, &sp, 0, 1, &best, &best_ms, NULL));
 
-    hdi_job job = {{40, 30, 3}, DEV, DEV, DEV};
+    hdi_job job = {HDI_JOB_INPAINT, {40, 30, 3}, DEV, DEV, DEV, NULL, NULL};
     FAILS(HDI_ERR_ARG, hdi_solve_batch(-1, &job, DEV, 1 << 30, NULL, NULL, NULL));
     FAILS(HDI_ERR_WORKSPACE, hdi_solve_batch(1, &job, DEV, 64, NULL, NULL, NULL));
+    job.kind = 7;
+    FAILS(HDI_ERR_ARG, hdi_solve_batch(1, &job, DEV, 1 << 30, NULL, NULL, NULL));
+    job.kind = HDI_JOB_TONAL;
+    hdi_tonal_params bad_tp;
+    memset(&bad_tp, 0, sizeof bad_tp);
+    bad_tp.inner.flags = HDI_FLAG_CG; /* the engine runs the multigrid solver only */
+    job.tonal = &bad_tp;
+    FAILS(HDI_ERR_ARG, hdi_solve_batch(1, &job, DEV, 1 << 30, NULL, NULL, NULL));
+    job.tonal = NULL;
+    job.kind = HDI_JOB_INPAINT;
     job.img.channels = 4;
     FAILS(HDI_ERR_ARG, hdi_solve_batch(1, &job, DEV, 1 << 30, NULL, NULL, NULL));
 

@@ -7,9 +7,12 @@ from paper_2401_06747_amd import autotune
 def test_candidates_are_valid_parameter_sets():
     c = autotune.candidates()
     assert len(c) == (len(autotune.OVERLAPS) * len(autotune.LOCAL_ITERS) * len(autotune.COARSE_ITERS)
-                      * len(autotune.SMALL_FROM))
+                      * len(autotune.SMALL_FROM) * len(autotune.ROBIN) * len(autotune.LOCAL_STOP))
     assert all(p.overlap % 2 == 0 and 2 <= p.overlap <= 16 for p in c)
-    assert len({(p.overlap, p.local_iters, p.coarse_iters, p.small_from) for p in c}) == len(c)
+    assert all(p.robin < 0 or 0 < p.robin <= 0.9 for p in c) and all(0 <= p.local_stop < 1 for p in c)
+    # both the Dirichlet and the Robin boundary, and both local stopping rules, are tried
+    assert {p.robin < 0 for p in c} == {True, False} and {p.local_stop > 0 for p in c} == {True, False}
+    assert len({(p.overlap, p.local_iters, p.coarse_iters, p.small_from, p.robin, p.local_stop) for p in c}) == len(c)
 
 
 def test_bucket_groups_similar_images():

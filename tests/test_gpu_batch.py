@@ -41,6 +41,32 @@ def test_batch_equals_single_solves_bitwise():
         assert torch.equal(u, u1)
 
 
+def test_mixed_inpaint_and_tonal_jobs_equal_single_calls():
+    """hdi_job.kind: inpainting and tonal jobs in one batch. The tonal jobs'
+    inner solves run in the shared launches with the inpainting jobs; every
+    result is bit-for-bit that of inpaint_solve or tonal_optimize alone."""
+    items = _batch_items(6, seed=2)
+    fs, ms = _t(items)
+    kinds = [hdi.TONAL if i % 2 else hdi.INPAINT for i in range(len(fs))]
+    tp = hdi.TonalParams(rel_tol=1e-7)
+    outs, reps = hdi.solve_batch(fs, ms, kinds=kinds, tonal_params=tp)
+    for f, m, k, out, rep in zip(fs, ms, kinds, outs, reps):
+        assert rep["status"] == 0, rep
+        if k == hdi.INPAINT:
+            u1, r1 = hdi.inpaint_solve(f, m)
+            assert torch.equal(out, u1) and rep["outer_iters"] == r1["outer_iters"]
+        else:
+            g1, r1 = hdi.tonal_optimize(f, m, params=tp)
+            assert torch.equal(out, g1)
+            assert rep["outer_iters"] == r1["outer_iters"] and rep["inner_solves"] == r1["inner_solves"]
+            assert rep["mse_final"] == r1["mse_final"] and rep["rel_normal_residual"] <= 1e-7
+    # a batch of tonal jobs only, with per-job parameters
+    tps = [hdi.TonalParams(rel_tol=1e-7, mode=md) for md in (hdi.PCG_RAS, hdi.RAS, hdi.CGNR)]
+    outs, reps = hdi.solve_batch(fs[:3], ms[:3], kinds=[hdi.TONAL] * 3, tonal_params=tps)
+    for f, m, p, out in zip(fs[:3], ms[:3], tps, outs):
+        assert torch.equal(out, hdi.tonal_optimize(f, m, params=p)[0])
+
+
 def test_result_independent_of_batch_mix():
     items = _batch_items(6, seed=1)
     fs, ms = _t(items)
@@ -107,15 +133,14 @@ def test_autotune_picks_a_converging_candidate_and_caches(tmp_path):
     path = tmp_path / "tune.json"
     tuner = autotune.Autotuner(str(path), reps=1)
     p = tuner.params_for(ft, mt)
-    assert (p.overlap, p.local_iters, p.coarse_iters, p.small_from) in {
-        (c.overlap, c.local_iters, c.coarse_iters, c.small_from) for c in autotune.candidates()}
+    key = lambda q: (q.overlap, q.local_iters, q.coarse_iters, q.small_from, q.robin, q.local_stop)  # noqa: E731
+    assert key(p) in {key(c) for c in autotune.candidates()}
     u, rep = hdi.inpaint_solve(ft, mt, params=p)
     assert rep["status"] == 0
     assert oi.relres(u.cpu().numpy(), f, m).max() <= 1e-6 * 1.0001
     # a second tuner reads the cache instead of measuring again
     again = autotune.Autotuner(str(path)).params_for(ft, mt)
-    assert (again.overlap, again.local_iters, again.coarse_iters, again.small_from) == (
-        p.overlap, p.local_iters, p.coarse_iters, p.small_from)
+    assert key(again) == key(p)
 
 
 def test_full_uneven_batch_equals_plain_solves():

@@ -1,6 +1,7 @@
 """GPU tests of the request loop (hdi_server_*): requests of mixed kinds and
 sizes that run together give, each, bit-for-bit the result of running alone
-(inpainting through the batch engine, tonal through tonal_optimize on a worker
+(inpainting requests and the inner solves of tonal requests share the batch
+engine's rounds; each tonal request's outer iteration runs on a worker
 stream); admission waits for arena memory; bad requests fail alone."""
 import time
 
@@ -58,8 +59,34 @@ def test_mixed_requests_equal_their_solo_results():
         assert rep["status"] == 0, rep
         assert torch.equal(out, _alone(kind, f, m)), (kind, tuple(f.shape))
         assert rep["t_submit_ms"] <= rep["t_start_ms"] <= rep["t_done_ms"]
-    # the inpainting requests shared rounds
+    # inpainting requests and tonal inner solves shared rounds
     assert max(rep["max_running"] for (_, kind), (_, rep) in zip(reqs, res) if kind == hdi.INPAINT) >= 2
+    assert max(rep["max_running"] for (_, kind), (_, rep) in zip(reqs, res) if kind == hdi.TONAL) >= 2
+
+
+@pytest.mark.parametrize("mode", [hdi.PCG_RAS, hdi.RAS, hdi.CGNR])
+def test_tonal_requests_share_engine_rounds(mode):
+    """Several tonal requests at once (each outer method): their inner solves
+    (B g and the symmetrised B^T solve, cold and warm-started) run in the
+    engine's shared rounds, together and with inpainting requests, and every
+    result equals tonal_optimize alone bit for bit."""
+    ton = [_inst(90 + 16 * i, 140, 1 + 2 * (i % 2), 0.03, 90 + i) for i in range(4)]
+    inp = [_inst(200, 260, 3, 0.04, 95 + i) for i in range(2)]
+    params = hdi.TonalParams(mode=mode, rel_tol=1e-7)
+    with hdi.Server(2 * GiB, max_slots=16, tonal_workers=4) as srv:
+        tt = [srv.submit(hdi.TONAL, f, m, params=params) for f, m in ton]
+        ti = [srv.submit(hdi.INPAINT, f, m) for f, m in inp]
+        srv.drain()
+        rt = [srv.poll(t) for t in tt]
+        ri = [srv.poll(t) for t in ti]
+    for (f, m), (g, rep) in zip(ton, rt):
+        alone, arep = hdi.tonal_optimize(f, m, params=params)
+        assert rep["status"] == 0 and torch.equal(g, alone), (tuple(f.shape), rep)
+        assert rep["outer_iters"] == arep["outer_iters"] and rep["inner_solves"] == arep["inner_solves"]
+        assert rep["mse_final"] == arep["mse_final"]
+    for (f, m), (u, rep) in zip(inp, ri):
+        assert rep["status"] == 0 and torch.equal(u, hdi.inpaint_solve(f, m)[0])
+    assert max(r["max_running"] for _, r in rt) >= 2, [r["max_running"] for _, r in rt]
 
 
 def test_requests_join_a_running_batch():

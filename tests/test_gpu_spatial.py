@@ -68,11 +68,15 @@ def test_loop_steps_match_oracle(partition, t):
 
 def test_error_maps_are_the_solutions_errors():
     """The error map each step sees is fp32 of the squared error of a solution
-    of the inpainting system for the mask before that step."""
+    of the inpainting system for the mask before that step. The solves run to
+    rel-res 1e-10 here, so that the map is compared, not the solver's accuracy
+    (at the default 1e-6 a solution may differ from the oracle's by up to the
+    1e-5 solution bar, more than this pointwise bar on the map allows)."""
     C, H, W = 1, 96, 128
     f, r, ft, rt = _inputs(H, W, C, 8)
     seen = []
-    hdi.spatial_optimize(ft, rt, 0.06, n_steps=3, hook=lambda k, m, e, a: seen.append((m, e)))
+    hdi.spatial_optimize(ft, rt, 0.06, n_steps=3, solve=hdi.SolveParams(rel_tol=1e-10),
+                         hook=lambda k, m, e, a: seen.append((m, e)))
     for m, e in seen:
         u = oi.inpaint(f.astype(np.float32).astype(np.float64), m)
         ref = osp.error_map(u, f.astype(np.float32))
