@@ -450,10 +450,11 @@ def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=1000, seed=5, tonal_w
     gaps = rng.exponential(1.0, n_requests)
     torch.cuda.synchronize()
 
-    def run(load, plain):
+    def run(load, plain, tonal_shared=False):
         lam = load * mu_plain
         arrive = np.cumsum(gaps) / lam
-        srv = hdi.Server(32 << 30, max_slots=32, tonal_workers=tonal_workers, plain=plain, device=dev)
+        srv = hdi.Server(32 << 30, max_slots=32, tonal_workers=tonal_workers, plain=plain,
+                         tonal_shared=tonal_shared, device=dev)
         try:
             tickets = []
             t0 = time.perf_counter()
@@ -484,7 +485,7 @@ def serve_bench(torch, hdi, synth, dev, inst4k, n_requests=1000, seed=5, tonal_w
            "mu_plain_per_s": round(mu_plain, 2), "calibration_requests": n_calibration, "tonal_workers": tonal_workers}
     for load in (0.8, 1.5):
         res[f"load_{load}"] = {"lambda_per_s": round(load * mu_plain, 2), "served": run(load, False),
-                               "plain": run(load, True)}
+                               "served_tonal_shared": run(load, False, True), "plain": run(load, True)}
         log(f"serving at {load}x plain capacity: {res[f'load_{load}']}")
     return res
 
@@ -572,6 +573,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-comparators", action="store_true", help="skip the paper-comparator measurement")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--tonal-block", type=int, default=0, choices=(0, 32, 64),
+                    help="edge of the tonal RAS blocks (0: the default, 64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
@@ -598,7 +601,7 @@ def main():
     img = _lib.hdi_image(f.shape[2], f.shape[1], f.shape[0])
     ws_i = hdi.workspace(L.hdi_inpaint_workspace_bytes(img), dev)
     ws_t = hdi.workspace(L.hdi_tonal_workspace_bytes(img), dev)
-    tonal_params = hdi.TonalParams(mode=hdi.PCG_RAS, rel_tol=1e-6)
+    tonal_params = hdi.TonalParams(mode=hdi.PCG_RAS, rel_tol=1e-6, block=args.tonal_block)
 
     def step():
         _, ri = hdi.inpaint_solve(f, m, ws=ws_i, out=u)

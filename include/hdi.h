@@ -63,7 +63,7 @@ typedef struct {
  *   overlap      overlap of the 32x32 subdomain blocks of the Schwarz smoother
  *                (Sec. 3.1, 3.3; default 6 as in Sec. 3.3, valid 2..16, even)
  *   local_iters  conjugate-gradient iterations per block and smoothing step
- *                on the finest level (Sec. 3.3; default 8)
+ *                on the finest level (Sec. 3.3; default 10)
  *   coarse_iters CG iterations on the coarsest level, which is a single block
  *                (Sec. 3.3; default 64)
  *   flags        HDI_FLAG_* bits
@@ -88,7 +88,7 @@ typedef struct {
  *                Coarse levels always run their fixed step counts.
  *   mid_iters    conjugate-gradient iterations per block and smoothing step on
  *                the levels between the finest and the coarsest, and in the
- *                full-multigrid start (default: local_iters)
+ *                full-multigrid start (default 6)
  * Each refinement round applies one V-cycle with one pre- and one
  * post-smoothing step (Sec. 3.3).                                            */
 typedef struct {
@@ -334,29 +334,32 @@ int32_t voronoi_init(hdi_image img, const uint8_t *mask, const float *f, double 
 /* ------------------------------------------------------------------ serving */
 
 /* A request loop over one device: inpainting and tonal requests of any sizes
- * are submitted as they arrive and run with continuous batching. Every
- * inpainting solve joins the shared launches of the batch engine between
- * refinement rounds: the inpainting requests, and the inner solves of the
- * tonal requests (B g, and the symmetrised solve behind B^T, Sec. 5.1). Each
- * solve keeps its own rounds and tolerance. A tonal request's outer iteration
- * runs on a worker thread with a stream of its own (its gathers, RAS sweeps and
- * vector updates overlap the engine's rounds), waits for its inner solves in
- * the engine, and gives bit for bit what tonal_optimize gives; an inpainting
- * request gives what inpaint_solve gives. Every request is admitted when its
- * memory in the caller's arena is free (inpainting requests also need an
- * engine slot), in arrival order per kind, and its state stays in device
- * memory until it ends. */
+ * are submitted as they arrive and run with continuous batching. Inpainting
+ * requests join the shared launches of the batch engine between refinement
+ * rounds; each keeps its own rounds and tolerance and gives bit for bit what
+ * inpaint_solve gives. A tonal request runs on a worker thread with a stream of
+ * its own, so its kernels overlap the engine's rounds, and gives bit for bit
+ * what tonal_optimize gives. With HDI_SERVER_TONAL_SHARED its inner solves (B g
+ * and the symmetrised solve behind B^T, Sec. 5.1) join the engine's shared
+ * rounds too, while its gathers, RAS sweeps and vector updates stay on its
+ * stream. Every request is admitted when its memory in the caller's arena is
+ * free (inpainting requests also need an engine slot), in arrival order per
+ * kind, and its state stays in device memory until it ends. */
 #define HDI_REQ_INPAINT 0
 #define HDI_REQ_TONAL 1
 #define HDI_REQ_HOST_IO 1   /* request flags: mask, f and out are pinned host memory
                                (copied in and out on the server's copy stream) */
 #define HDI_SERVER_PLAIN 1  /* server flags: one request at a time through
                                inpaint_solve / tonal_optimize (the control) */
+#define HDI_SERVER_TONAL_SHARED 2  /* server flags: tonal requests hand their inner
+                               solves to the engine's shared rounds instead of
+                               running them on their worker's own stream (same
+                               results; more sharing, longer tonal latency) */
 
 /* One request. Without HDI_REQ_HOST_IO the pointers are device memory that
  * must stay valid and unchanged until the request is done. Tonal requests
- * start from g = f on the mask; their inner parameters must not set
- * HDI_FLAG_CG (the engine runs the multigrid solver).
+ * start from g = f on the mask; with HDI_SERVER_TONAL_SHARED their inner
+ * parameters must not set HDI_FLAG_CG (the engine runs the multigrid solver).
  *   out   u (inpaint, C x H x W float64) or g (tonal, 0 off the mask)      */
 typedef struct {
     int32_t kind, flags;
@@ -373,7 +376,8 @@ typedef struct {
     int32_t outer_iters;       /* refinement rounds (inpaint) or outer iterations (tonal) */
     int32_t inner_solves;      /* tonal: inpainting solves */
     int32_t max_running;       /* most solves sharing one engine round with it (tonal:
-                                  with any of its inner solves) */
+                                  with any of its inner solves; 0 when they ran on
+                                  the worker's stream) */
     double rel_residual[3];    /* inpaint: per channel; tonal: [0] relative normal residual */
     double mse_initial, mse_final;
     double t_submit_ms, t_start_ms, t_done_ms;   /* host clock, ms since hdi_server_create */

@@ -35,13 +35,13 @@ class SolveParams:
     rel_tol: float = 0.0       # 0 -> 1e-6
     max_outer: int = 0         # 0 -> 40
     overlap: int = 0           # 0 -> 6
-    local_iters: int = 0       # 0 -> 8
+    local_iters: int = 0       # 0 -> 10
     coarse_iters: int = 0      # 0 -> 64
     flags: int = 0
     small_from: int = 0        # first level with 16x16 blocks: 0 automatic, -1 none, k level k
     robin: float = 0.0         # Robin weight at inner block boundaries (0 -> 0.6, < 0: Dirichlet), up to 0.9
     local_stop: float = 0.0    # > 0: finest-level local CG stops at this fraction of the global squared residual
-    mid_iters: int = 0         # local CG steps on the levels between finest and coarsest (0 -> local_iters)
+    mid_iters: int = 0         # local CG steps on the levels between finest and coarsest (0 -> 6)
 
     def c(self):
         return _lib.hdi_solve_params(self.rel_tol, self.max_outer, self.overlap, self.local_iters,
@@ -379,18 +379,19 @@ def solve_batch(fs, masks, params=None, ws: torch.Tensor | None = None, outs=Non
 class Server:
     """Request loop over one GPU (hdi_server_*): continuous batching of
     inpainting requests, tonal requests on worker streams, admission by the
-    bytes of a caller-owned arena. `plain=True` runs one request at a time
-    through inpaint_solve / tonal_optimize (the control)."""
+    bytes of a caller-owned arena. `tonal_shared=True` runs the tonal requests'
+    inner solves in the engine's shared rounds; `plain=True` runs one request
+    at a time through inpaint_solve / tonal_optimize (the control)."""
 
     def __init__(self, arena_bytes: int, max_slots: int = 64, tonal_workers: int = 3, plain: bool = False,
-                 device="cuda:0"):
+                 tonal_shared: bool = False, device="cuda:0"):
         L = _lib.lib()
         self.device = torch.device(device)
         self.arena = workspace(arena_bytes, self.device)
         torch.cuda.synchronize(self.device)
+        flags = (_lib.HDI_SERVER_PLAIN if plain else 0) | (_lib.HDI_SERVER_TONAL_SHARED if tonal_shared else 0)
         with torch.cuda.device(self.device):
-            h = L.hdi_server_create(_ptr(self.arena), self.arena.numel(), int(max_slots), int(tonal_workers),
-                                    _lib.HDI_SERVER_PLAIN if plain else 0)
+            h = L.hdi_server_create(_ptr(self.arena), self.arena.numel(), int(max_slots), int(tonal_workers), flags)
         if not h:
             raise HdiError(_lib.HDI_ERR_ARG, L.hdi_last_error().decode())
         self._h = ctypes.c_void_p(h)

@@ -91,6 +91,7 @@ HDI_STEP_HOOK = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.POINTER(ctypes.c_u
 HDI_REQ_INPAINT, HDI_REQ_TONAL = 0, 1
 HDI_REQ_HOST_IO = 1
 HDI_SERVER_PLAIN = 1
+HDI_SERVER_TONAL_SHARED = 2
 HDI_TONAL_PCG_RAS, HDI_TONAL_RAS, HDI_TONAL_CGNR = 0, 1, 2
 HDI_TONAL_INIT_FROM_F = 1
 HDI_TONAL_TRACE = 2

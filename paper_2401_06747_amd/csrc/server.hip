@@ -1,16 +1,15 @@
 // Request loop with continuous batching over one device.
 //
-// All inpainting solves go through the batch engine: an engine thread admits
+// Inpainting requests go through the batch engine: an engine thread admits
 // waiting work between refinement rounds (as slots and arena memory free up),
 // runs one round over everything running, and hands back the solves that met
-// their tolerance. Work comes from inpainting requests and from tonal
-// requests: each tonal request's outer iteration (Sec. 5) runs on a tonal
-// worker thread and stream, and its inner solves (x = B g and the symmetrised
-// solve of B^T) join the engine's shared rounds like inpainting requests do,
-// while its own kernels (gathers, the RAS sweep, vector updates) run on the
-// worker's stream. Events order the two streams. With HDI_SERVER_PLAIN one
-// worker runs the requests one at a time through inpaint_solve and
-// tonal_optimize: the one-request-per-launch control.
+// their tolerance. Each tonal request's outer iteration (Sec. 5) runs on a
+// tonal worker thread and stream. Its inner solves (x = B g and the
+// symmetrised solve of B^T) run on that stream too, overlapping the engine's
+// rounds on the device, or, with HDI_SERVER_TONAL_SHARED, join the engine's
+// shared rounds like inpainting requests do (events order the two streams).
+// With HDI_SERVER_PLAIN one worker runs the requests one at a time through
+// inpaint_solve and tonal_optimize: the one-request-per-launch control.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -304,7 +303,7 @@ struct hdi_server {
                 cv.wait(lk, [&] { return (t = take(q_ton)) != nullptr || (stop && q_ton.empty()); });
             }
             if (!t) return;
-            run_tonal(t, tonal_streams[w], &hook);
+            run_tonal(t, tonal_streams[w], (flags & HDI_SERVER_TONAL_SHARED) ? &hook : nullptr);
         }
     }
 
@@ -530,7 +529,7 @@ int32_t hdi_server_submit(hdi_server *srv, const hdi_request *req, uint64_t *tic
         int ov = 0;
         st = fill_tonal_cfg(req->tonal, tc, inner, ov);
         if (st) return st;
-        if ((inner.flags & HDI_FLAG_CG) && !(srv->flags & HDI_SERVER_PLAIN)) {
+        if ((inner.flags & HDI_FLAG_CG) && (srv->flags & HDI_SERVER_TONAL_SHARED) && !(srv->flags & HDI_SERVER_PLAIN)) {
             set_error("tonal requests' inner solves run in the batch engine, which runs the multigrid solver only "
                       "(HDI_FLAG_CG is for single solves)");
             return HDI_ERR_ARG;
@@ -652,7 +651,7 @@ int32_t solve_batch_served(int n, const hdi_job *jobs, void *ws, size_t ws_bytes
     }
     int ntonal = 0;
     for (int i = 0; i < n; ++i) ntonal += jobs[i].kind == HDI_JOB_TONAL;
-    hdi_server *srv = hdi_server_create(ws, ws_bytes, n, std::min(ntonal, 16), 0);
+    hdi_server *srv = hdi_server_create(ws, ws_bytes, n, std::min(ntonal, 16), HDI_SERVER_TONAL_SHARED);
     if (!srv) return HDI_ERR_HIP;
     std::vector<uint64_t> tickets(n, 0);
     int32_t st = HDI_OK;

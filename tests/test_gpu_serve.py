@@ -1,8 +1,8 @@
 """GPU tests of the request loop (hdi_server_*): requests of mixed kinds and
 sizes that run together give, each, bit-for-bit the result of running alone
-(inpainting requests and the inner solves of tonal requests share the batch
-engine's rounds; each tonal request's outer iteration runs on a worker
-stream); admission waits for arena memory; bad requests fail alone."""
+(inpainting requests share the batch engine's rounds; each tonal request runs
+on a worker stream, with its inner solves on that stream or, shared, in the
+engine's rounds); admission waits for arena memory; bad requests fail alone."""
 import time
 
 import numpy as np
@@ -51,17 +51,19 @@ def _run(server, reqs, gap_s=0.0):
     return out
 
 
-def test_mixed_requests_equal_their_solo_results():
+@pytest.mark.parametrize("shared", [False, True])
+def test_mixed_requests_equal_their_solo_results(shared):
     reqs = _mix()
-    with hdi.Server(2 * GiB, max_slots=8, tonal_workers=2) as srv:
+    with hdi.Server(2 * GiB, max_slots=8, tonal_workers=2, tonal_shared=shared) as srv:
         res = _run(srv, reqs)
     for ((f, m), kind), (out, rep) in zip(reqs, res):
         assert rep["status"] == 0, rep
         assert torch.equal(out, _alone(kind, f, m)), (kind, tuple(f.shape))
         assert rep["t_submit_ms"] <= rep["t_start_ms"] <= rep["t_done_ms"]
-    # inpainting requests and tonal inner solves shared rounds
+    # inpainting requests shared rounds, and with `shared` the tonal inner solves too
     assert max(rep["max_running"] for (_, kind), (_, rep) in zip(reqs, res) if kind == hdi.INPAINT) >= 2
-    assert max(rep["max_running"] for (_, kind), (_, rep) in zip(reqs, res) if kind == hdi.TONAL) >= 2
+    tonal_running = [rep["max_running"] for (_, kind), (_, rep) in zip(reqs, res) if kind == hdi.TONAL]
+    assert max(tonal_running) >= 2 if shared else max(tonal_running) == 0
 
 
 @pytest.mark.parametrize("mode", [hdi.PCG_RAS, hdi.RAS, hdi.CGNR])
@@ -73,7 +75,7 @@ def test_tonal_requests_share_engine_rounds(mode):
     ton = [_inst(90 + 16 * i, 140, 1 + 2 * (i % 2), 0.03, 90 + i) for i in range(4)]
     inp = [_inst(200, 260, 3, 0.04, 95 + i) for i in range(2)]
     params = hdi.TonalParams(mode=mode, rel_tol=1e-7)
-    with hdi.Server(2 * GiB, max_slots=16, tonal_workers=4) as srv:
+    with hdi.Server(2 * GiB, max_slots=16, tonal_workers=4, tonal_shared=True) as srv:
         tt = [srv.submit(hdi.TONAL, f, m, params=params) for f, m in ton]
         ti = [srv.submit(hdi.INPAINT, f, m) for f, m in inp]
         srv.drain()
