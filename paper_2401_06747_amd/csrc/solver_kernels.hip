@@ -418,6 +418,29 @@ __device__ __forceinline__ void lds_get(const float *src, float *v) {
     }
 }
 
+// Cell-centred bilinear prolongation of a coarse correction: 3/4 of the parent
+// cell, 1/4 of the next cell on each side of x and y (a = parent, b and c the
+// next cells along x and along y, d the diagonal one).
+__device__ __forceinline__ float bilinear(float a, float b, float c, float d) {
+    return 0.5625f * a + 0.1875f * (b + c) + 0.0625f * d;
+}
+
+// P ec at a lane's PS x PS pixels from the (PS/2 + 2)^2 coarse cells around
+// them, cc[0][0] being the cell left of and above the first pixel's parent;
+// PX, PY: the parity of the first pixel's x and y (every lane of a block has
+// the same).
+template <int PS, int PX, int PY>
+__device__ __forceinline__ void prolong_patch(const float (&cc)[PS / 2 + 2][PS / 2 + 2], float *out) {
+#pragma unroll
+    for (int j = 0; j < PS; ++j)
+#pragma unroll
+        for (int i = 0; i < PS; ++i) {
+            const int X = ((i + PX) >> 1) + 1, Xn = ((i + PX) & 1) ? X + 1 : X - 1;
+            const int Y = ((j + PY) >> 1) + 1, Yn = ((j + PY) & 1) ? Y + 1 : Y - 1;
+            out[j * PS + i] = bilinear(cc[Y][X], cc[Y][Xn], cc[Yn][X], cc[Yn][Xn]);
+        }
+}
+
 template <int MODE, int T>
 __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, int sx, int sy, int iters, float robin,
                                               float stop_sq, const uint8_t *__restrict__ mask,
@@ -429,7 +452,7 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     // s_p: the vector of the current CG step with a zero ring; before that it
     // holds the starting correction with its 1-pixel halo (MODE 1/2)
     __shared__ __attribute__((aligned(16))) float s_p[T + 2][LW];
-    __shared__ uint8_t s_m[T + 2][T + 2];
+    __shared__ uint8_t s_m[MODE == 2 ? T + 2 : 1][T + 2];
     __shared__ float s_c[MODE == 1 ? NC : 1][NC];   // coarse correction around the block (MODE 1)
 
     const int tx = t % ntx, ty = t / ntx;
@@ -442,13 +465,19 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
 
     // The lane's own right-hand side goes straight to registers (8 lanes
     // cover a block row); addresses are clamped so every load is unconditional.
+    // MODE 0 and 1 take the lane's own mask values (and in MODE 1 its part of
+    // the pre-smoothed correction) the same way.
     float rown[NPX];
+    uint8_t mown[MODE != 2 ? NPX : 1];
+    float eown[MODE == 1 ? NPX : 1];
 #pragma unroll
     for (int j = 0; j < PS; ++j)
 #pragma unroll
         for (int i = 0; i < PS; ++i) {
             const int xc = min(x0 + PS * bx + i, W - 1), yc = min(y0 + PS * by + j, H - 1);
             rown[j * PS + i] = r ? rc[yc * W + xc] : 0.f;
+            if constexpr (MODE != 2) mown[j * PS + i] = mask[yc * W + xc];
+            if constexpr (MODE == 1) eown[j * PS + i] = e_in[(size_t)c * N + yc * W + xc];
         }
     // MODE 1: the coarse correction around the block, with clamped coordinates
     // so that the clamped bilinear lookup becomes plain indexing; its loads are
@@ -456,8 +485,24 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
     const int X0 = ((x0 - 1) >> 1) - 1, Y0 = ((y0 - 1) >> 1) - 1;
     constexpr int NCS = NC * NC;
     constexpr int NCV = (NCS + 63) / 64;
+    // MODE 1: the block's 1-pixel halo ring (4T + 4 pixels: rows 0 and T + 1
+    // of the tile, then the two halo columns of rows 1..T), loaded with the
+    // rest so that every load is in flight at once.
+    constexpr int NRING = 4 * T + 4;
+    constexpr int NRV = (NRING + 63) / 64;
     float cv[MODE == 1 ? NCV : 1];
-    if (MODE == 1) {
+    int rmk[MODE == 1 ? NRV : 1];
+    float rev[MODE == 1 ? NRV : 1];
+    auto ring_pos = [&](int k, int &lx, int &ly) {
+        if (k < 2 * (T + 2)) {
+            ly = k < T + 2 ? 0 : T + 1;
+            lx = k % (T + 2);
+        } else {
+            ly = 1 + (k - 2 * (T + 2)) / 2;
+            lx = (k & 1) ? T + 1 : 0;
+        }
+    };
+    if constexpr (MODE == 1) {
         const float *ecc = ec + (size_t)c * Wc * Hc;
 #pragma unroll
         for (int h = 0; h < NCV; ++h) {
@@ -465,16 +510,77 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
             const int X = min(max(X0 + k % NC, 0), Wc - 1), Y = min(max(Y0 + k / NC, 0), Hc - 1);
             cv[h] = ecc[Y * Wc + X];
         }
+#pragma unroll
+        for (int h = 0; h < NRV; ++h) {
+            int lx, ly;
+            ring_pos(min(lane + 64 * h, NRING - 1), lx, ly);
+            const int pc = min(max(y0 + ly - 1, 0), H - 1) * W + min(max(x0 + lx - 1, 0), W - 1);
+            rmk[h] = mask[pc];
+            rev[h] = e_in[(size_t)c * N + pc];
+        }
     }
-    // Stage mask and (MODE 1/2) the starting correction for the block and a
-    // 1-pixel halo, in coalesced rows of T + 2. s_m: 0 unknown, 1 known, 2
-    // outside the image. In MODE 1, e_in is exactly 0 on known pixels; in
-    // MODE 2 it holds the data there. MODE 0 starts from zero.
+    // MODE 1: the starting correction e_in + P ec on unknown pixels (0 on
+    // known ones and outside the image). e_in is exactly 0 on known pixels.
+    // The ring goes to the tile pixel by pixel; the lane's own pixels are
+    // computed in registers from the coarse cells around them and published.
+    float e_st[MODE == 1 ? NPX : 1];
+    if constexpr (MODE == 1) {
+#pragma unroll
+        for (int h = 0; h < NCV; ++h) {
+            const int k = lane + 64 * h;
+            if (k < NCS) s_c[k / NC][k % NC] = cv[h];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < NRV; ++h) {
+            const int k = lane + 64 * h;
+            if (k < NRING) {
+                int lx, ly;
+                ring_pos(k, lx, ly);
+                const int x = x0 + lx - 1, y = y0 + ly - 1;
+                float v = 0.f;
+                if (x >= 0 && x < W && y >= 0 && y < H && rmk[h] == 0) {
+                    const int X = (x >> 1) - X0, Y = (y >> 1) - Y0;
+                    const int Xn = (x & 1) ? X + 1 : X - 1, Yn = (y & 1) ? Y + 1 : Y - 1;
+                    v = rev[h] + bilinear(s_c[Y][X], s_c[Y][Xn], s_c[Yn][X], s_c[Yn][Xn]);
+                }
+                s_p[ly][COL0 - 1 + lx] = v;
+            }
+        }
+        constexpr int NCC = PS / 2 + 2;
+        const int xs = x0 + PS * bx, ys = y0 + PS * by;
+        const int Xb = (xs >> 1) - 1 - X0, Yb = (ys >> 1) - 1 - Y0;
+        float cc[NCC][NCC];
+#pragma unroll
+        for (int a = 0; a < NCC; ++a)
+#pragma unroll
+            for (int b = 0; b < NCC; ++b) cc[a][b] = s_c[Yb + a][Xb + b];
+        switch ((xs & 1) | ((ys & 1) << 1)) {
+            case 0: prolong_patch<PS, 0, 0>(cc, e_st); break;
+            case 1: prolong_patch<PS, 1, 0>(cc, e_st); break;
+            case 2: prolong_patch<PS, 0, 1>(cc, e_st); break;
+            default: prolong_patch<PS, 1, 1>(cc, e_st); break;
+        }
+#pragma unroll
+        for (int j = 0; j < PS; ++j)
+#pragma unroll
+            for (int i = 0; i < PS; ++i) {
+                const int k = j * PS + i;
+                const bool act = PS * bx + i < Tx && PS * by + j < Ty && mown[k] == 0;
+                e_st[k] = act ? eown[k] + e_st[k] : 0.f;
+            }
+#pragma unroll
+        for (int j = 0; j < PS; ++j) lds_put<PS>(&s_p[PS * by + j + 1][COL0 + PS * bx], &e_st[j * PS]);
+    }
+
+    // MODE 2: stage mask and the starting correction (the data on known
+    // pixels) for the block and a 1-pixel halo, in coalesced rows of T + 2.
+    // s_m: 0 unknown, 1 known, 2 outside the image.
     constexpr int NST = (T + 2) * (T + 2);
     constexpr int NIT = (NST + 63) / 64;
     constexpr int HALF = (NIT + 1) / 2;      // staged in two batches to bound register use
 #pragma unroll
-    for (int batch = 0; batch < 2; ++batch) {
+    for (int batch = 0; batch < (MODE == 2 ? 2 : 0); ++batch) {
         int mraw[HALF];
         float ev[HALF];
 #pragma unroll
@@ -486,14 +592,6 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
             mraw[h] = mask[pc];
             ev[h] = MODE != 0 ? e_in[(size_t)c * N + pc] : 0.f;
         }
-        if (MODE == 1 && batch == 0) {
-#pragma unroll
-            for (int h = 0; h < NCV; ++h) {
-                const int k = lane + 64 * h;
-                if (k < NCS) s_c[k / NC][k % NC] = cv[h];
-            }
-            __syncthreads();
-        }
 #pragma unroll
         for (int h = 0; h < HALF; ++h) {
             const int k = lane + 64 * (batch * HALF + h);
@@ -501,27 +599,12 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
                 const int ly = k / (T + 2), lx = k % (T + 2);
                 const int x = x0 + lx - 1, y = y0 + ly - 1;
                 const bool in = x >= 0 && x < W && y >= 0 && y < H;
-                const int mk = in ? (mraw[h] != 0) : 2;
-                s_m[ly][lx] = (uint8_t)mk;
-                float v = 0.f;
-                if (MODE != 0) {
-                    v = in ? ev[h] : 0.f;
-                    if (MODE == 1) {
-                        if (mk == 0) {
-                            // cell-centred bilinear: 3/4 parent, 1/4 next cell on each side of x and y
-                            const int X = (x >> 1) - X0, Y = (y >> 1) - Y0;
-                            const int Xn = (x & 1) ? X + 1 : X - 1, Yn = (y & 1) ? Y + 1 : Y - 1;
-                            v += 0.5625f * s_c[Y][X] + 0.1875f * (s_c[Y][Xn] + s_c[Yn][X]) + 0.0625f * s_c[Yn][Xn];
-                        } else {
-                            v = 0.f;
-                        }
-                    }
-                }
-                s_p[ly][COL0 - 1 + lx] = v;
+                s_m[ly][lx] = (uint8_t)(in ? (mraw[h] != 0) : 2);
+                s_p[ly][COL0 - 1 + lx] = in ? ev[h] : 0.f;
             }
         }
     }
-    __syncthreads();
+    if constexpr (MODE != 0) __syncthreads();
 
     // Local right-hand side r - A e_start on the block's unknown pixels; the
     // CG iterate v starts at e_start (so it is the final correction), and the
@@ -535,8 +618,14 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
             const int x = x0 + lx, y = y0 + ly;
             float res = 0.f, d = 0.f, e0 = 0.f;
             const bool inside = lx < Tx && ly < Ty;
-            if (MODE != 0 && inside) e0 = s_p[ly + 1][COL0 + lx];
-            if (inside && s_m[ly + 1][lx + 1] == 0) {
+            if constexpr (MODE == 1) e0 = e_st[k];
+            if (MODE == 2 && inside) e0 = s_p[ly + 1][COL0 + lx];
+            bool unknown;
+            if constexpr (MODE != 2)
+                unknown = inside && mown[k] == 0;
+            else
+                unknown = inside && s_m[ly + 1][lx + 1] == 0;
+            if (unknown) {
                 d = (float)deg_of(x, y, W, H);
                 res = rown[k];
                 if (MODE != 0) {
@@ -554,16 +643,15 @@ __device__ __forceinline__ void schwarz_block(int W, int H, int ntx, int nty, in
             v[k] = e0;
             rl[k] = res;
         }
-    __syncthreads();   // every lane has read the starting correction before the ring is cleared
-    if (MODE != 0) {
-        // zero ring (Dirichlet values outside the block): rows 0 and T + 1, and
-        // the two halo columns of rows 1..T
-        for (int k = lane; k < 2 * (T + 2) + 2 * T; k += 64) {
-            if (k < 2 * (T + 2))
-                s_p[k < T + 2 ? 0 : T + 1][COL0 - 1 + k % (T + 2)] = 0.f;
-            else
-                s_p[1 + (k - 2 * (T + 2)) / 2][(k & 1) ? COL0 + T : COL0 - 1] = 0.f;
-        }
+    if constexpr (MODE != 0) __syncthreads();   // every lane has read the starting correction
+    // zero ring (Dirichlet values outside the block): rows 0 and T + 1, and the
+    // two halo columns of rows 1..T (the first step's barrier orders it before
+    // any read)
+    for (int k = lane; k < 2 * (T + 2) + 2 * T; k += 64) {
+        if (k < 2 * (T + 2))
+            s_p[k < T + 2 ? 0 : T + 1][COL0 - 1 + k % (T + 2)] = 0.f;
+        else
+            s_p[1 + (k - 2 * (T + 2)) / 2][(k & 1) ? COL0 + T : COL0 - 1] = 0.f;
     }
 
     // Local CG in the Chronopoulos-Gear arrangement: each step applies the
