@@ -194,7 +194,7 @@ int32_t Engine::admit(const std::vector<EJob *> &news, std::vector<EJob *> &ende
     B_TRY(hipGetLastError());
     B_TRY(hipMemcpyAsync(h_counts_.data(), d_counts_, sizeof(unsigned int) * h_counts_.size(), hipMemcpyDeviceToHost,
                          s));
-    B_TRY(hipStreamSynchronize(s));
+    B_TRY(wait_for(s));
 
     // 2. levels in use: the same rule as the single-image solve
     std::vector<EJob *> go;

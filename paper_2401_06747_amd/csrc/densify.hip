@@ -577,7 +577,7 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
     if (added && na > 0) hipLaunchKernelGGL(k_copy_i32, gd(na), dim3(256), 0, s, na, d.seed_idx, added);
     if (max_d2) D_TRY(hipMemcpyAsync(max_d2, d.maxd2, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     D_TRY(hipGetLastError());
-    D_TRY(hipStreamSynchronize(s));
+    D_TRY(wait_for(s));
     *n_added = na;
     return HDI_OK;
 }
@@ -703,7 +703,7 @@ int32_t hdi_voronoi_labels(int32_t width, int32_t height, const uint8_t *mask, i
         D_TRY(hipMemcpyAsync(max_d2, slot, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     }
     D_TRY(hipGetLastError());
-    D_TRY(hipStreamSynchronize(s));
+    D_TRY(wait_for(s));
     return HDI_OK;
 }
 

@@ -77,6 +77,7 @@ struct SolveCfg {
     float local_stop;  // global-relative local stop (hdi_solve_params::local_stop)
     int small_from;  // hdi_solve_params::small_from (0 automatic, -1 none)
     int64_t known;   // number of known pixels (for the byte accounting)
+    bool untimed = false;   // no device time in the report (no wait for the stream at the end)
 };
 
 // A call that must not allocate (inpaint_solve_noalloc) holds one of these on
@@ -92,6 +93,11 @@ bool no_alloc_active();
 // Device time of one call: the start and stop events live as long as the
 // object, so every return path releases them. Under a NoAllocScope it makes no
 // events and measures host time from start() to the end of the stream's work.
+// Waits for a stream or an event by polling for up to 5 ms, then blocks (a
+// blocking wait wakes the host tens of microseconds after the device is done).
+hipError_t wait_for(hipStream_t s);
+hipError_t wait_for(hipEvent_t ev);
+
 struct CallTimer {
     hipEvent_t a = nullptr, b = nullptr;
     bool host = false;
@@ -110,12 +116,12 @@ struct CallTimer {
     // records the stop event, waits for it, and stores the elapsed time in *ms
     hipError_t stop(hipStream_t s, float *ms) {
         if (host) {
-            const hipError_t e = hipStreamSynchronize(s);
+            const hipError_t e = wait_for(s);
             *ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
             return e;
         }
         hipError_t e = hipEventRecord(b, s);
-        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = wait_for(b);
         if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
         return e;
     }
@@ -145,6 +151,12 @@ struct Prof {
             recs[n - 1].lds = lds;
         }
     }
+    // The record the last begin()/end() pair made is left out of the counters
+    // (a launch that turned out to be unneeded); its events are still freed.
+    void drop_last() {
+        if (on && ended) recs[n - 1].id = -1;
+        ended = false;
+    }
 };
 Prof *prof_for_call();   // nullptr when timing is off
 
@@ -165,8 +177,12 @@ void launch_update(int W, int H, int C, const uint8_t *mask, const float *e, dou
 // gnorm, frac: a block's local CG also stops once its squared residual is at
 // most frac times the channel's global squared residual gnorm[2 c] (nullptr or
 // 0: fixed step count).
+// guard >= 0 (finest level): every block returns at once when the residual
+// norms in gnorm (rr, bb per channel) already give rr <= guard^2 bb in every
+// channel (rr <= guard^2 where bb = 0); the launch can then be queued before
+// the host has tested them.
 void launch_smooth_pre(const Level &L, int C, int iters, float robin, const double *gnorm, float frac, float *e_out,
-                       hipStream_t s);
+                       hipStream_t s, double guard = -1.0);
 void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, float robin, const double *gnorm,
                         float frac, const float *e_in, const float *ec, float *e_out, hipStream_t s);
 void launch_restrict_residual(const Level &L, const Level &Lc, int C, const float *e, hipStream_t s);

@@ -55,7 +55,8 @@ void Prof::flush() {
     std::lock_guard<std::mutex> lk(g_stats_mu);
     for (int i = 0; i < n; ++i) {
         float ms = 0.f;
-        if (hipEventSynchronize(recs[i].b) == hipSuccess && hipEventElapsedTime(&ms, recs[i].a, recs[i].b) == hipSuccess) {
+        if (recs[i].id >= 0 && hipEventSynchronize(recs[i].b) == hipSuccess &&
+            hipEventElapsedTime(&ms, recs[i].a, recs[i].b) == hipSuccess) {
             g_stats[recs[i].id].launches += 1;
             g_stats[recs[i].id].ms += ms;
             g_stats[recs[i].id].bytes += recs[i].bytes;
@@ -75,7 +76,7 @@ constexpr size_t STAGING_BYTES = 16384;
 static thread_local void *t_staging = nullptr;
 static thread_local bool t_staging_failed = false;
 
-static hipError_t wait_for(hipStream_t s) {
+hipError_t wait_for(hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
         const hipError_t e = hipStreamQuery(s);
@@ -84,20 +85,34 @@ static hipError_t wait_for(hipStream_t s) {
     }
 }
 
+hipError_t wait_for(hipEvent_t ev) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e != hipErrorNotReady) return e;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(5)) return hipEventSynchronize(ev);
+    }
+}
+
 static thread_local int t_no_alloc = 0;
 NoAllocScope::NoAllocScope() { ++t_no_alloc; }
 NoAllocScope::~NoAllocScope() { --t_no_alloc; }
 bool no_alloc_active() { return t_no_alloc > 0; }
 
-hipError_t read_to_host(void *dst, const void *src, size_t bytes, hipStream_t s) {
-    if (bytes <= STAGING_BYTES && !t_staging && !t_staging_failed && !no_alloc_active()) {
+static void *staging(size_t bytes) {
+    if (bytes > STAGING_BYTES) return nullptr;
+    if (!t_staging && !t_staging_failed && !no_alloc_active()) {
         if (hipHostMalloc(&t_staging, STAGING_BYTES, hipHostMallocPortable) != hipSuccess) {
             t_staging = nullptr;
             t_staging_failed = true;
             (void)hipGetLastError();
         }
     }
-    if (bytes <= STAGING_BYTES && t_staging) {
+    return t_staging;
+}
+
+hipError_t read_to_host(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (staging(bytes)) {
         hipError_t e = hipMemcpyAsync(t_staging, src, bytes, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = wait_for(s);
         if (e == hipSuccess) std::memcpy(dst, t_staging, bytes);
@@ -105,6 +120,38 @@ hipError_t read_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
     }
     const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
     return e == hipSuccess ? wait_for(s) : e;
+}
+
+// The event behind the last read_begin of this host thread (made once, kept
+// for the life of the process like the staging buffer).
+static thread_local hipEvent_t t_read_ev = nullptr;
+static thread_local bool t_read_ev_failed = false;
+
+// Queues a copy of `bytes` from device memory into the thread's pinned staging
+// buffer and an event behind it. read_end then waits for that event only, so
+// work queued on s after read_begin keeps the device busy while the host
+// waits. Returns false with nothing queued when the staging buffer or the
+// event is unavailable (use read_to_host then); err reports a failed queueing.
+static bool read_begin(const void *src, size_t bytes, hipStream_t s, hipError_t &err) {
+    err = hipSuccess;
+    if (!staging(bytes)) return false;
+    if (!t_read_ev && !t_read_ev_failed && !no_alloc_active()) {
+        if (hipEventCreateWithFlags(&t_read_ev, hipEventDisableTiming) != hipSuccess) {
+            t_read_ev = nullptr;
+            t_read_ev_failed = true;
+            (void)hipGetLastError();
+        }
+    }
+    if (!t_read_ev) return false;
+    err = hipMemcpyAsync(t_staging, src, bytes, hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipEventRecord(t_read_ev, s);
+    return err == hipSuccess;
+}
+
+static hipError_t read_end(void *dst, size_t bytes) {
+    const hipError_t e = wait_for(t_read_ev);
+    if (e == hipSuccess) std::memcpy(dst, t_staging, bytes);
+    return e;
 }
 
 Prof *prof_for_call() {
@@ -210,10 +257,30 @@ static void vcycle_cost(const Hierarchy &h, int l, const SolveCfg &cfg, double &
     }
 }
 
+// The pre-smoothing launch of a V-cycle on level l < nlev - 1. guard >= 0 (level
+// 0 only): the launch is queued before the host has seen the residual norms
+// in h.norms, and its blocks return at once when those norms already meet
+// the relative tolerance guard.
+static void smooth_pre(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Prof *prof, double guard = -1.0) {
+    Level &L = h.lev[l];
+    const int C = h.C;
+    const double N = (double)L.W * L.H;
+    const double blk_px = (double)L.bx.count * L.by.count * std::min(L.tile, L.W) * std::min(L.tile, L.H) * C;
+    const int iters = l == 0 ? cfg.local_iters : cfg.mid_iters;
+    if (prof) prof->begin(1, N * (1 + 8.0 * C), s, 15.0 * blk_px * iters);
+    // the global-relative local stop on the finest level, against the norms
+    // of the residual sweep that precedes the V-cycle
+    const double *gnorm = l == 0 ? h.norms : nullptr;
+    launch_smooth_pre(L, C, iters, cfg.robin, gnorm, cfg.local_stop, L.ea, s, guard);
+    if (prof) prof->end(s);
+}
+
 // One V-cycle for A e = r on level l (r in lev[l].r); returns the buffer with e.
-// With `prof`, the finest level's launches are timed one by one and the whole
-// coarse recursion as one record.
-static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Prof *prof = nullptr) {
+// pre_queued: smooth_pre of level l is already on the stream. With `prof`, the
+// finest level's launches are timed one by one and the whole coarse recursion
+// as one record.
+static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Prof *prof = nullptr,
+                     bool pre_queued = false) {
     Level &L = h.lev[l];
     const int C = h.C;
     if (l == h.nlev - 1) {
@@ -225,12 +292,9 @@ static float *vcycle(Hierarchy &h, int l, const SolveCfg &cfg, hipStream_t s, Pr
     const double blk_px = (double)L.bx.count * L.by.count * std::min(L.tile, L.W) * std::min(L.tile, L.H) * C;
     const int iters = l == 0 ? cfg.local_iters : cfg.mid_iters;
     const double cg_flops = 15.0 * blk_px * iters;
-    if (prof) prof->begin(1, N * (1 + 8.0 * C), s, cg_flops);
-    // the global-relative local stop on the finest level, against the norms
-    // of the residual sweep that precedes the V-cycle
     const double *gnorm = l == 0 ? h.norms : nullptr;
-    launch_smooth_pre(L, C, iters, cfg.robin, gnorm, cfg.local_stop, L.ea, s);
-    if (prof) { prof->end(s); prof->begin(3, N * (1 + 8.0 * C) + Nc * (1 + 4.0 * C), s); }
+    if (!pre_queued) smooth_pre(h, l, cfg, s, prof);
+    if (prof) prof->begin(3, N * (1 + 8.0 * C) + Nc * (1 + 4.0 * C), s);
     launch_restrict_residual(L, Lc, C, L.ea, s);
     if (prof) {
         prof->end(s);
@@ -327,7 +391,7 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         return HDI_ERR_ARG;
     }
     CallTimer tm;
-    HIP_TRY(tm.start(s));
+    if (!cfg.untimed) HIP_TRY(tm.start(s));
     if (cfg.flags & HDI_FLAG_CG) {
         if (h.u_alt_moved) {
             set_error("internal: a CG solve after a multigrid solve handed over its buffer");
@@ -338,7 +402,7 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         int steps = 0;
         const int32_t st = solve_cg<TD>(h, W, H, C, mask, data, src, u, cfg, rel, steps, s, prof);
         float ms = 0.f;
-        HIP_TRY(tm.stop(s, &ms));
+        if (!cfg.untimed) HIP_TRY(tm.stop(s, &ms));
         if (prof) prof->flush();
         if (rep) {
             for (int c = 0; c < 3; ++c) rep->rel_residual[c] = c < C ? rel[c] : 0.0;
@@ -373,7 +437,21 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         launch_residual<TD>(W, H, C, mask, cur, e, e ? oth : nullptr, data, src, h.lev[0].r, h.partials, h.norms, s);
         if (prof) prof->end(s);
         if (e) std::swap(cur, oth);
-        HIP_TRY(read_to_host(norms, h.norms, sizeof(double) * 2 * C, s));
+        // When a V-cycle may follow, its first launch is queued behind the copy
+        // of the norms, guarded on the device by the same test with a margin
+        // (so that a guarded exit implies the host's stop below), and the host
+        // waits for the copy alone: the device smooths while the host decides.
+        bool queued = false;
+        if (h.nlev > 1 && rounds < cfg.max_outer) {
+            hipError_t err;
+            queued = read_begin(h.norms, sizeof(double) * 2 * C, s, err);
+            HIP_TRY(err);
+            if (queued) {
+                smooth_pre(h, 0, cfg, s, prof, cfg.rel_tol * (1.0 - 1e-12));
+                HIP_TRY(read_end(norms, sizeof(double) * 2 * C));
+            }
+        }
+        if (!queued) HIP_TRY(read_to_host(norms, h.norms, sizeof(double) * 2 * C, s));
         double worst = 0.0;
         bool finite = true;
         for (int c = 0; c < C; ++c) {
@@ -381,6 +459,10 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
             finite = finite && std::isfinite(rr) && std::isfinite(bb);
             rel[c] = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
             worst = std::fmax(worst, rel[c]);
+        }
+        if (!finite || worst <= cfg.rel_tol) {
+            // the queued pre-smoothing returned at once or is left unused
+            if (queued && prof) prof->drop_last();
         }
         if (!finite) {
             set_error("non-finite residual: the input holds NaN/Inf or the iteration diverged");
@@ -393,7 +475,7 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
             status = HDI_ERR_NO_CONVERGENCE;
             break;
         }
-        e = vcycle(h, 0, cfg, s, prof);
+        e = vcycle(h, 0, cfg, s, prof, queued);
         ++rounds;
         ++vcycles;
     }
@@ -408,7 +490,7 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     }
     HIP_TRY(hipGetLastError());
     float ms = 0.f;
-    HIP_TRY(tm.stop(s, &ms));
+    if (!cfg.untimed) HIP_TRY(tm.stop(s, &ms));
     if (prof) prof->flush();
     if (rep) {
         for (int c = 0; c < 3; ++c) rep->rel_residual[c] = c < C ? rel[c] : 0.0;

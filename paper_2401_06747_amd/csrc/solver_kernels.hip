@@ -736,11 +736,31 @@ __device__ __forceinline__ float local_stop_sq(const double *__restrict__ gnorm,
     return gnorm && frac > 0.f ? (float)((double)frac * gnorm[(size_t)c * stride]) : 0.f;
 }
 
+// The refinement's stopping test on the norms of a residual sweep (rr, bb per
+// channel, C <= 3), squared: rr <= tol^2 bb for every channel (rr <= tol^2
+// where bb = 0). A NaN fails it. The caller passes tol with a relative margin
+// far above rounding, so that a met test here implies the host's test
+// sqrt(rr / bb) <= its tolerance on the same norms.
+__device__ __forceinline__ bool residual_met(const double *norms, int C, double tol) {
+    const double t2 = tol * tol;
+    double rr[3], bb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        rr[c] = c < C ? norms[2 * c] : 0.0;
+        bb[c] = c < C ? norms[2 * c + 1] : 0.0;
+    }
+    bool met = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) met = met && (bb[c] > 0.0 ? rr[c] <= t2 * bb[c] : rr[c] <= t2);
+    return met;
+}
+
 template <int MODE, int T>
 __global__ void __launch_bounds__(64)
 k_schwarz(int W, int H, int C, int ntx, int nty, int sx, int sy, int iters, float robin, const double *gnorm,
-          float frac, const uint8_t *__restrict__ mask, const float *__restrict__ r, const float *__restrict__ e_in,
-          const float *__restrict__ ec, int Wc, int Hc, float *__restrict__ e_out) {
+          float frac, double guard, const uint8_t *__restrict__ mask, const float *__restrict__ r,
+          const float *__restrict__ e_in, const float *__restrict__ ec, int Wc, int Hc, float *__restrict__ e_out) {
+    if (MODE == 0 && guard >= 0.0 && residual_met(gnorm, C, guard)) return;
     schwarz_block<MODE, T>(W, H, ntx, nty, sx, sy, iters, robin, local_stop_sq(gnorm, 2, frac, blockIdx.y), mask,
                            r, e_in, ec, Wc, Hc, e_out, xcd_remap(blockIdx.x, ntx * nty), blockIdx.y);
 }
@@ -861,31 +881,34 @@ void launch_update(int W, int H, int C, const uint8_t *mask, const float *e, dou
 
 template <int MODE>
 static void launch_schwarz(const Level &L, int C, int iters, float robin, const double *gnorm, float frac,
-                           const float *r, const float *e_in, const float *ec, int Wc, int Hc, float *e_out,
-                           hipStream_t s) {
+                           double guard, const float *r, const float *e_in, const float *ec, int Wc, int Hc,
+                           float *e_out, hipStream_t s) {
     const dim3 g(L.bx.count * L.by.count, C);
     if (L.tile == 16)
         hipLaunchKernelGGL((k_schwarz<MODE, 16>), g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count,
-                           L.bx.stride, L.by.stride, iters, robin, gnorm, frac, L.mask, r, e_in, ec, Wc, Hc, e_out);
+                           L.bx.stride, L.by.stride, iters, robin, gnorm, frac, guard, L.mask, r, e_in, ec, Wc, Hc,
+                           e_out);
     else
         hipLaunchKernelGGL((k_schwarz<MODE, 32>), g, dim3(64), 0, s, L.W, L.H, C, L.bx.count, L.by.count,
-                           L.bx.stride, L.by.stride, iters, robin, gnorm, frac, L.mask, r, e_in, ec, Wc, Hc, e_out);
+                           L.bx.stride, L.by.stride, iters, robin, gnorm, frac, guard, L.mask, r, e_in, ec, Wc, Hc,
+                           e_out);
 }
 
 void launch_smooth_pre(const Level &L, int C, int iters, float robin, const double *gnorm, float frac, float *e_out,
-                       hipStream_t s) {
-    launch_schwarz<0>(L, C, iters, robin, gnorm, frac, L.r, nullptr, nullptr, 1, 1, e_out, s);
+                       hipStream_t s, double guard) {
+    if (guard >= 0.0 && !gnorm) guard = -1.0;
+    launch_schwarz<0>(L, C, iters, robin, gnorm, frac, guard, L.r, nullptr, nullptr, 1, 1, e_out, s);
 }
 
 void launch_smooth_post(const Level &L, const Level &Lc, int C, int iters, float robin, const double *gnorm,
                         float frac, const float *e_in, const float *ec, float *e_out, hipStream_t s) {
-    launch_schwarz<1>(L, C, iters, robin, gnorm, frac, L.r, e_in, ec, Lc.W, Lc.H, e_out, s);
+    launch_schwarz<1>(L, C, iters, robin, gnorm, frac, -1.0, L.r, e_in, ec, Lc.W, Lc.H, e_out, s);
 }
 
 void launch_smooth_fmg(const Level &L, int C, int iters, float robin, const float *e_in, float *e_out,
                        hipStream_t s) {
     // the full problem A u = C d has a zero right-hand side on unknown pixels
-    launch_schwarz<2>(L, C, iters, robin, nullptr, 0.f, nullptr, e_in, nullptr, 1, 1, e_out, s);
+    launch_schwarz<2>(L, C, iters, robin, nullptr, 0.f, -1.0, nullptr, e_in, nullptr, 1, 1, e_out, s);
 }
 
 void launch_restrict_residual(const Level &L, const Level &Lc, int C, const float *e, hipStream_t s) {

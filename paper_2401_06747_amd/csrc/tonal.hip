@@ -113,7 +113,11 @@ struct TonalCtx {
     int32_t inner_solve(const double *data, const double *src, double *&x, bool warm, const SolveCfg &c,
                         hdi_solve_report &rep) {
         if (hook) return hook->solve(t.h, overlap, W, H, C, mask, data, src, x, warm, c, &rep, s);
-        return solve_system<double>(t.h, W, H, C, mask, data, src, x, warm, c, &rep, s, prof, &x);
+        // the inner solves' own device times are not reported, so the host
+        // goes on queueing as soon as the last convergence test is read
+        SolveCfg cu = c;
+        cu.untimed = true;
+        return solve_system<double>(t.h, W, H, C, mask, data, src, x, warm, cu, &rep, s, prof, &x);
     }
 
     // u = B x for x given on K (compact); cold start with FMG unless warm.
@@ -447,7 +451,7 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
     hipLaunchKernelGGL(k_image_from_K, dim3((X.N + 255) / 256), dim3(256), 0, s, X.N, C, m, t.pos, t.gK, g_out);
     if (u_out) T_TRY(hipMemcpyAsync(u_out, t.ug, sizeof(double) * C * X.N, hipMemcpyDeviceToDevice, s));
     T_TRY(hipGetLastError());
-    T_TRY(hipStreamSynchronize(s));
+    T_TRY(wait_for(s));
     if (rep) {
         rep->mse_initial = mse0;
         rep->mse_final = mse1;
