@@ -431,7 +431,9 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     double *cur = u, *oth = h.u_alt;
     const float *e = nullptr;
     for (;;) {
-        const double res_bytes = N * (1 + 12.0 * C) + C * nK * sizeof(TD) + (src ? 8.0 * C * nU : 0.0) +
+        // mask, u in, r out; the source off the mask; e in and u out after a
+        // V-cycle (the data is not read: u holds it on the mask)
+        const double res_bytes = N * (1 + 12.0 * C) + (src ? 8.0 * C * nU : 0.0) +
                                  (e ? 12.0 * C * N : 0.0);
         if (prof) prof->begin(0, res_bytes, s);
         launch_residual<TD>(W, H, C, mask, cur, e, e ? oth : nullptr, data, src, h.lev[0].r, h.partials, h.norms, s);

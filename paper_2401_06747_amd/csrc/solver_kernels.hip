@@ -86,10 +86,12 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
     const int bid = by * gx + bx;
 
     // Rows of u (+ e) at column xs: prev (y-1), cur (y), next (y+1), and the
-    // prefetched y+2; mask rows y and y+1; data/src of row y. Loads are issued
-    // one or two rows ahead, and everything row y needs was issued in an
-    // earlier iteration, so the in-order memory counter never makes the wave
-    // wait for its own prefetch.
+    // prefetched y+2; mask rows y and y+1; src of row y. Loads are issued one
+    // or two rows ahead, and everything row y needs was issued in an earlier
+    // iteration, so the in-order memory counter never makes the wave wait for
+    // its own prefetch. The data on known pixels is not read: there the
+    // iterate holds it exactly (set at the start, and every correction is 0
+    // there), so b = u on known pixels.
     auto fetch = [&](int c, int y, double &uv, float &ev) {
         const int yc = min(max(y, 0), H - 1);
         const size_t j = (size_t)c * N + (size_t)yc * W + xs;
@@ -97,25 +99,14 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
         ev = e ? e[j] : 0.f;
     };
     auto fetch_mask = [&](int y) -> int { return mask[(size_t)min(y, H - 1) * W + xs]; };
-    // right-hand side of row y: data on known pixels only (the mask of row y
-    // is already in a register, loaded an iteration earlier, so waiting for
-    // it never waits for a later row's prefetch), or src elsewhere
-    auto fetch_b = [&](int y, int mk, TD *dk, double *sv) {
+    // source term of row y (source problems; 0 otherwise)
+    auto fetch_b = [&](int y, double *sv) {
         const size_t i = (size_t)min(y, H - 1) * W + xs;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            if constexpr (SRC) {
-                dk[c] = TD(0);
-                sv[c] = src[(size_t)c * N + i];
-            } else {
-                dk[c] = mk ? data[(size_t)c * N + i] : TD(0);
-                sv[c] = 0.0;
-            }
-        }
+        for (int c = 0; c < C; ++c) sv[c] = SRC ? src[(size_t)c * N + i] : 0.0;
     };
     double pu[C], cu[C], nu[C], qu[C];
     float pe[C], ce[C], ne[C], qe[C];
-    TD dcur[C], dnxt[C];
     double scur[C], snxt[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -124,7 +115,7 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
         fetch(c, y0 + 1, nu[c], ne[c]);
     }
     int mcur = fetch_mask(y0), mnxt = fetch_mask(y0 + 1);
-    fetch_b(y0, mcur, dcur, scur);
+    fetch_b(y0, scur);
     double rr[C], bb[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) rr[c] = bb[c] = 0.0;
@@ -133,7 +124,7 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
 #pragma unroll
         for (int c = 0; c < C; ++c) fetch(c, y + 2, qu[c], qe[c]);
         const int mq = fetch_mask(y + 2);
-        fetch_b(y + 1, mnxt, dnxt, snxt);
+        fetch_b(y + 1, snxt);
         // then compute row y from registers
         const size_t i = (size_t)y * W + xs;
         const bool known = mcur != 0;
@@ -146,7 +137,7 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
             const double ul = wave_from_left(u0), ur = wave_from_right(u0);
             const double uu = pu[c] + (double)pe[c], ud = nu[c] + (double)ne[c];
             const double au = dgv * u0 - (wl * ul + wr * ur + wu * uu + wd * ud);
-            const double b = known ? (double)dcur[c] : scur[c];
+            const double b = known ? u0 : scur[c];
             const double res = known ? b - u0 : b - au;
             if (owner) {
                 if (e) u_out[o + i] = u0;
@@ -157,7 +148,6 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
             pu[c] = cu[c]; pe[c] = ce[c];
             cu[c] = nu[c]; ce[c] = ne[c];
             nu[c] = qu[c]; ne[c] = qe[c];
-            dcur[c] = dnxt[c];
             scur[c] = snxt[c];
         }
         mcur = mnxt;
@@ -350,10 +340,13 @@ __device__ __forceinline__ void restrict_residual_at(int i, int W, int H, int C,
     }
 }
 
+// Consecutive workgroups (coarse rows, in order) go to one XCD, so the fine
+// rows that neighbouring coarse rows share are read from that XCD's L2.
 __global__ void k_restrict_residual(int W, int H, int C, const uint8_t *__restrict__ m,
                                     const float *__restrict__ r, const float *__restrict__ e,
                                     int Wc, int Hc, const uint8_t *__restrict__ mc, float *__restrict__ rc) {
-    restrict_residual_at(blockIdx.x * blockDim.x + threadIdx.x, W, H, C, m, r, e, Wc, Hc, mc, rc);
+    restrict_residual_at(xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x, W, H, C, m, r, e, Wc, Hc, mc,
+                         rc);
 }
 
 // Cell-centred bilinear prolongation weights: fine x maps to coarse position
