@@ -103,6 +103,23 @@ def test_empty_mask_is_an_error():
     assert ei.value.status == 2
 
 
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_non_finite_data_is_an_error_and_the_next_solve_is_clean(bad):
+    """A non-finite value on the mask makes the residual norms non-finite: the
+    solve stops with HDI_ERR_ARG (the smoothing launch queued behind the norms
+    runs on them and is discarded), and the next solve on the same stream is
+    unaffected."""
+    inst = synth.config2(96, 128, 3, 0.05, item=7)
+    f = inst.f.copy()
+    ys, xs = np.nonzero(inst.mask)
+    f[1, ys[0], xs[0]] = bad
+    with pytest.raises(hdi.HdiError) as ei:
+        _run(f, inst.mask)
+    assert ei.value.status == 1
+    u, rep = _run(inst.f, inst.mask)
+    _check(inst.f, inst.mask, u, rep)
+
+
 def test_no_convergence_reports_last_iterate():
     inst = synth.config2(128, 160, 1, 0.03, item=5)
     u, rep = _run(inst.f, inst.mask, max_outer=1, flags=1)
