@@ -61,13 +61,15 @@ typedef struct {
  *                (FP64 residual; default 1e-6)
  *   max_outer    cap on refinement rounds (default 40)
  *   overlap      overlap of the 32x32 subdomain blocks of the Schwarz smoother
- *                (Sec. 3.1, 3.3; default 6 as in Sec. 3.3, valid 2..16, even)
+ *                on the finest level (Sec. 3.1, 3.3; default 6 as in Sec. 3.3,
+ *                valid 2..16, even); the coarser levels use half of it (even,
+ *                at least 2)
  *   local_iters  conjugate-gradient iterations per block and smoothing step
  *                on the finest level (Sec. 3.3; default 10)
  *   coarse_iters CG iterations on the coarsest level, which is a single block
  *                (Sec. 3.3; default 64)
  *   flags        HDI_FLAG_* bits
- *   small_from   first level smoothed with 16x16 blocks (half the overlap):
+ *   small_from   first level smoothed with 16x16 blocks:
  *                0 automatic (from level 1, the first level with fewer than
  *                4096 blocks of 32x32 over all channels, where the smoother is
  *                bound by the latency of its steps), -1 none, k >= 1 level k

@@ -62,12 +62,12 @@ struct Hierarchy {
 constexpr int CG_BLOCKS = 4096;   // workgroups of the CG kernels (grid-stride)
 
 // Lay out the hierarchy in the arena (base == nullptr: size query only).
-// small_from: the first level smoothed with 16x16 blocks, which use half the
-// overlap (even, at least 2); 0 picks it from the block counts, -1 keeps
-// 32x32 blocks on every level
+// overlap: of the finest level's blocks; the coarser levels use half of it
+// (even, at least 2). small_from: the first level smoothed with 16x16 blocks;
+// 0 picks it from the block counts, -1 keeps 32x32 blocks on every level
 bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, const uint8_t *mask0,
                     int small_from = -1);
-inline int small_overlap(int overlap) { return overlap / 2 >= 2 ? (overlap / 2) & ~1 : 2; }
+inline int coarse_overlap(int overlap) { return overlap / 2 >= 2 ? (overlap / 2) & ~1 : 2; }
 
 struct SolveCfg {
     double rel_tol;

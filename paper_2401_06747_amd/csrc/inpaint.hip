@@ -208,7 +208,10 @@ bool plan_hierarchy(Hierarchy &h, Arena &a, int W, int H, int C, int overlap, co
         }
         const bool small = small_from > 0 && l >= small_from;
         L.tile = small ? TILE_SMALL : TILE;
-        const int ov = small ? small_overlap(overlap) : overlap;
+        // the coarse levels smooth with half the overlap (even, at least 2):
+        // their blocks only need to pass the correction on, and the coarse-grid
+        // correction below does what more overlap would
+        const int ov = l >= 1 ? coarse_overlap(overlap) : overlap;
         L.bx = make_blocks(w, ov, L.tile);
         L.by = make_blocks(hh, ov, L.tile);
         const size_t n = (size_t)w * hh;
