@@ -229,10 +229,11 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
     // inexact-Krylov factor of the inner tolerances; tightened when the outer
     // residual stalls (the products' errors then limit what the recurrence
     // can reach, which happens for sparse masks, where A^{-1} is large).
-    // Krylov products are relaxed as 3e-2 * rel_tol / ||r||_rel (a sweep over
-    // 1e-3 .. 1e-1 kept the iteration counts and the final true residuals);
+    // Krylov products are relaxed as 1e-1 * rel_tol / ||r||_rel (against 3e-2,
+    // fewer V-cycles at the same outer iteration counts on most masks; on a
+    // sparse 1% mask one more outer iteration);
     // the stationary RAS residual evaluation keeps 1e-3.
-    double fac = tc.mode == HDI_TONAL_RAS ? 1e-3 : 3e-2, best = 1e300;
+    double fac = tc.mode == HDI_TONAL_RAS ? 1e-3 : 1e-1, best = 1e300;
     int stall = 0;
     // stationary RAS step length: halved whenever the residual grows (with
     // 32x32 blocks on sparse masks the undamped iteration can diverge)
