@@ -65,7 +65,7 @@ typedef struct {
  *                valid 2..16, even); the coarser levels use half of it (even,
  *                at least 2)
  *   local_iters  conjugate-gradient iterations per block and smoothing step
- *                on the finest level (Sec. 3.3; default 10)
+ *                on the finest level (Sec. 3.3; default 12)
  *   coarse_iters CG iterations on the coarsest level, which is a single block
  *                (Sec. 3.3; default 64)
  *   flags        HDI_FLAG_* bits
@@ -90,7 +90,7 @@ typedef struct {
  *                Coarse levels always run their fixed step counts.
  *   mid_iters    conjugate-gradient iterations per block and smoothing step on
  *                the levels between the finest and the coarsest, and in the
- *                full-multigrid start (default 6)
+ *                full-multigrid start (default 8)
  * Each refinement round applies one V-cycle with one pre- and one
  * post-smoothing step (Sec. 3.3).                                            */
 typedef struct {

@@ -35,13 +35,13 @@ class SolveParams:
     rel_tol: float = 0.0       # 0 -> 1e-6
     max_outer: int = 0         # 0 -> 40
     overlap: int = 0           # 0 -> 6
-    local_iters: int = 0       # 0 -> 10
+    local_iters: int = 0       # 0 -> 12
     coarse_iters: int = 0      # 0 -> 64
     flags: int = 0
     small_from: int = 0        # first level with 16x16 blocks: 0 automatic, -1 none, k level k
     robin: float = 0.0         # Robin weight at inner block boundaries (0 -> 0.6, < 0: Dirichlet), up to 0.9
     local_stop: float = 0.0    # > 0: finest-level local CG stops at this fraction of the global squared residual
-    mid_iters: int = 0         # local CG steps on the levels between finest and coarsest (0 -> 6)
+    mid_iters: int = 0         # local CG steps on the levels between finest and coarsest (0 -> 8)
 
     def c(self):
         return _lib.hdi_solve_params(self.rel_tol, self.max_outer, self.overlap, self.local_iters,

@@ -20,7 +20,7 @@ from . import SolveParams, _check_inputs, _img, _ptr, _stream_ptr, workspace
 from ._lib import check
 
 OVERLAPS = (4, 6)
-LOCAL_ITERS = (6, 8, 10, 12)
+LOCAL_ITERS = (8, 10, 12, 14)
 COARSE_ITERS = (32, 64)
 SMALL_FROM = (0, -1)          # 16x16 blocks on the coarse levels: automatic rule, or none
 ROBIN = (-1.0, 0.6)           # Dirichlet block boundaries, or the Robin condition with weight 0.6

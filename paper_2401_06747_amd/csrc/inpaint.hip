@@ -529,8 +529,8 @@ bool check_image(const hdi_image &img) {
 int32_t fill_cfg(const hdi_solve_params *p, SolveCfg &cfg, int &overlap) {
     cfg.rel_tol = (p && p->rel_tol > 0) ? p->rel_tol : 1e-6;
     cfg.max_outer = (p && p->max_outer > 0) ? p->max_outer : 40;
-    cfg.local_iters = (p && p->local_iters > 0) ? p->local_iters : 10;
-    cfg.mid_iters = (p && p->mid_iters > 0) ? p->mid_iters : 6;
+    cfg.local_iters = (p && p->local_iters > 0) ? p->local_iters : 12;
+    cfg.mid_iters = (p && p->mid_iters > 0) ? p->mid_iters : 8;
     cfg.coarse_iters = (p && p->coarse_iters > 0) ? p->coarse_iters : 64;
     cfg.vcycles = 1;
     cfg.flags = p ? p->flags : 0;
