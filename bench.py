@@ -31,7 +31,7 @@ ALU_BOUND = {"schwarz_pre", "schwarz_post", "tonal_ras_sweep"}
 TRAFFIC = {
     "tonal_ras_sweep": {"read": 2 * 24619.82 * 1024, "written": 6059.26 * 1024,
                         "source": "paper_2401_06747_amd/csrc/tonal_kernels.hip", "sha256": "8e8f926eff8e548e"},
-    "schwarz_post": {"read": 2 * 124835.12 * 1024, "written": 97608.45 * 1024,
+    "schwarz_post": {"read": 2 * 124833.22 * 1024, "written": 97349.71 * 1024,
                      "source": "paper_2401_06747_amd/csrc/solver_kernels.hip", "sha256": "82c0bfcd33c3d403"},
 }
 
