@@ -180,29 +180,28 @@ __device__ __forceinline__ long long orient(int W, int a, int b, int c) {
     return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
 }
 
-__device__ __forceinline__ void emit(int W, int a, int b, int c, unsigned int *count, int *ta, int *tb, int *tc) {
-    // sort the triple
-    if (a > b) { const int t = a; a = b; b = t; }
-    if (b > c) { const int t = b; b = c; c = t; }
-    if (a > b) { const int t = a; a = b; b = t; }
-    if (orient(W, a, b, c) == 0) return;
-    const unsigned int k = atomicAdd(count, 1u);
-    ta[k] = a;
-    tb[k] = b;
-    tc[k] = c;
+// A candidate triangle: its labels in increasing order; false if collinear.
+__device__ __forceinline__ bool make_tri(int W, int a, int b, int c, int3 &t) {
+    if (a > b) { const int u = a; a = b; b = u; }
+    if (b > c) { const int u = b; b = c; c = u; }
+    if (a > b) { const int u = a; a = b; b = u; }
+    t = make_int3(a, b, c);
+    return orient(W, a, b, c) != 0;
 }
 
-__global__ void k_quads(int W, int H, const int *__restrict__ labels, unsigned int *__restrict__ count,
-                        int *__restrict__ ta, int *__restrict__ tb, int *__restrict__ tc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Each quad of 2x2 pixels with three distinct labels gives one triangle, with
+// four (l0 l1 l2 l3 around the quad) the two triangles l0 l1 l2 and l0 l2 l3.
+__device__ __forceinline__ void quad_tris(int W, int H, const int *__restrict__ labels, int i, int3 &t0, int3 &t1,
+                                          bool &e0, bool &e1) {
+    e0 = e1 = false;
     if (i >= (W - 1) * (H - 1)) return;
     const int x = i % (W - 1), y = i / (W - 1);
     const int l0 = labels[y * W + x], l1 = labels[y * W + x + 1];
     const int l2 = labels[(y + 1) * W + x + 1], l3 = labels[(y + 1) * W + x];
     const int nd = 1 + (l1 != l0) + (l2 != l0 && l2 != l1) + (l3 != l0 && l3 != l1 && l3 != l2);
     if (nd == 4) {
-        emit(W, l0, l1, l2, count, ta, tb, tc);
-        emit(W, l0, l2, l3, count, ta, tb, tc);
+        e0 = make_tri(W, l0, l1, l2, t0);
+        e1 = make_tri(W, l0, l2, l3, t1);
     } else if (nd == 3) {
         // the three distinct labels
         int a = l0, b, c;
@@ -211,8 +210,58 @@ __global__ void k_quads(int W, int H, const int *__restrict__ labels, unsigned i
         c = a;
         for (int k = 0; k < 3; ++k)
             if (cands[k] != a && cands[k] != b) c = cands[k];
-        emit(W, a, b, c, count, ta, tb, tc);
+        e0 = make_tri(W, a, b, c, t0);
     }
+}
+
+// The triangles are listed without a shared counter (same-address atomics
+// serialise): k_quads_count counts each workgroup's triangles, an exclusive
+// scan gives every workgroup its offset, and k_quads_write evaluates the quads
+// again and writes the triangles there, wavefront by wavefront (the order in
+// the list is arbitrary: the triangles are sorted and merged afterwards).
+// Every lane takes part in the ballots, also those past the last quad.
+__global__ void __launch_bounds__(256)
+k_quads_count(int W, int H, const int *__restrict__ labels, int *__restrict__ block_count) {
+    int3 t0, t1;
+    bool e0, e1;
+    quad_tris(W, H, labels, blockIdx.x * blockDim.x + threadIdx.x, t0, t1, e0, e1);
+    const int n = __popcll(__ballot(e0)) + __popcll(__ballot(e1));
+    __shared__ int s_n[4];
+    if ((threadIdx.x & 63) == 0) s_n[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) block_count[blockIdx.x] = s_n[0] + s_n[1] + s_n[2] + s_n[3];
+}
+
+__global__ void __launch_bounds__(256)
+k_quads_write(int W, int H, const int *__restrict__ labels, const int *__restrict__ block_count,
+              const int *__restrict__ block_off, int *__restrict__ ta, int *__restrict__ tb, int *__restrict__ tc,
+              unsigned int *__restrict__ total) {
+    int3 t0 = make_int3(0, 0, 0), t1 = make_int3(0, 0, 0);
+    bool e0, e1;
+    quad_tris(W, H, labels, blockIdx.x * blockDim.x + threadIdx.x, t0, t1, e0, e1);
+    const unsigned long long m0 = __ballot(e0), m1 = __ballot(e1);
+    const int n0 = __popcll(m0), n = n0 + __popcll(m1);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ int s_n[4];
+    if (lane == 0) s_n[w] = n;
+    __syncthreads();
+    int base = block_off[blockIdx.x];
+    for (int k = 0; k < w; ++k) base += s_n[k];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (e0) {
+        const int k = base + __popcll(m0 & below);
+        ta[k] = t0.x;
+        tb[k] = t0.y;
+        tc[k] = t0.z;
+    }
+    if (e1) {
+        const int k = base + n0 + __popcll(m1 & below);
+        ta[k] = t1.x;
+        tb[k] = t1.y;
+        tc[k] = t1.z;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        *total = (unsigned int)(block_off[blockIdx.x] + block_count[blockIdx.x]);
 }
 
 __global__ void k_iota(int n, int *__restrict__ v) {
@@ -283,44 +332,84 @@ __global__ void k_count_set(int N, const uint8_t *__restrict__ m, unsigned long 
 
 // Closed-triangle coverage with the smallest rank winning (ranks follow the
 // key order). One thread per triangle walks its bounding box.
+// Ownership: every pixel inside or on a triangle takes the smallest index of
+// those triangles. RASTER_LANES lanes share a triangle and stride over the
+// pixels of its bounding box, so large triangles (sparse regions) do not hold
+// a whole wavefront up. I: the integer type of the edge functions; int suffices
+// while 2 W H < 2^31 (each product of coordinate differences is at most W H).
+constexpr int RASTER_LANES = 16;
+template <typename I>
 __global__ void k_raster(int W, int T, const int *__restrict__ ua, const int *__restrict__ ub,
                          const int *__restrict__ uc, int *__restrict__ owner) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = (int)(g / RASTER_LANES), sub = (int)(g % RASTER_LANES);
     if (r >= T) return;
-    long long ax = ua[r] % W, ay = ua[r] / W, bx = ub[r] % W, by = ub[r] / W, cx = uc[r] % W, cy = uc[r] / W;
+    I ax = ua[r] % W, ay = ua[r] / W, bx = ub[r] % W, by = ub[r] / W, cx = uc[r] % W, cy = uc[r] / W;
     if ((bx - ax) * (cy - ay) - (by - ay) * (cx - ax) < 0) {
-        long long t = bx; bx = cx; cx = t;
+        I t = bx; bx = cx; cx = t;
         t = by; by = cy; cy = t;
     }
-    const long long x0 = min(ax, min(bx, cx)), x1 = max(ax, max(bx, cx));
-    const long long y0 = min(ay, min(by, cy)), y1 = max(ay, max(by, cy));
-    for (long long y = y0; y <= y1; ++y)
-        for (long long x = x0; x <= x1; ++x) {
-            const long long e0 = (bx - ax) * (y - ay) - (by - ay) * (x - ax);
-            const long long e1 = (cx - bx) * (y - by) - (cy - by) * (x - bx);
-            const long long e2 = (ax - cx) * (y - cy) - (ay - cy) * (x - cx);
-            if (e0 >= 0 && e1 >= 0 && e2 >= 0) atomicMin(&owner[y * W + x], r);
-        }
+    const I x0 = min(ax, min(bx, cx)), x1 = max(ax, max(bx, cx));
+    const I y0 = min(ay, min(by, cy)), y1 = max(ay, max(by, cy));
+    const I bw = x1 - x0 + 1, area = bw * (y1 - y0 + 1);
+    for (I k = sub; k < area; k += RASTER_LANES) {
+        const I y = y0 + k / bw, x = x0 + k % bw;
+        const I e0 = (bx - ax) * (y - ay) - (by - ay) * (x - ax);
+        const I e1 = (cx - bx) * (y - by) - (cy - by) * (x - bx);
+        const I e2 = (ax - cx) * (y - cy) - (ay - cy) * (x - cx);
+        if (e0 >= 0 && e1 >= 0 && e2 >= 0) atomicMin(&owner[y * W + x], r);
+    }
 }
 
 // ------------------------------------------------------------------ 4 cell errors and argmax
 
+__device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long v, int d) {
+    const int lo = __shfl_up((int)(unsigned)v, d, 64), hi = __shfl_up((int)(unsigned)(v >> 32), d, 64);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// Each pixel adds its error (fixed point, 2^-20) to its cell and offers its
+// argmax key. Runs of lanes with the same cell (cells are spatially coherent,
+// so neighbouring pixels mostly share one) are combined first by a segmented
+// scan in lane order, and only the last lane of a run issues the atomics:
+// integer sums and maxima, so the result does not depend on how the pixels
+// are grouped.
 __global__ void k_cells(int N, int T, const int *__restrict__ owner, const int *__restrict__ labels,
                         const int *__restrict__ seed_pos, const uint8_t *__restrict__ mask, const float *__restrict__ err,
                         unsigned long long *__restrict__ E, unsigned long long *__restrict__ best) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int o = owner ? owner[i] : INT_MAX;
-    const int cell = o < T ? o : T + seed_pos[labels[i]];
-    const float e = err[i];
-    const unsigned long long q = (unsigned long long)rint(ldexp((double)e, 20));
-    if (q) atomicAdd(&E[cell], q);
-    if (!mask[i]) {
-        // larger error first, then smaller index; e >= 0 so its bits order like its value,
-        // once -0 (accepted as e >= 0, but with the sign bit set) is made +0
-        const unsigned eb = e == 0.f ? 0u : __float_as_uint(e);
-        const unsigned long long key = ((unsigned long long)eb << 32) | (0xFFFFFFFFu - (unsigned)i);
-        atomicMax(&best[cell], key);
+    const int lane = threadIdx.x & 63;
+    int cell = -1 - lane;   // lanes past the end: a run of their own each
+    unsigned long long q = 0, key = 0;
+    if (i < N) {
+        const int o = owner ? owner[i] : INT_MAX;
+        cell = o < T ? o : T + seed_pos[labels[i]];
+        const float e = err[i];
+        q = (unsigned long long)rint(ldexp((double)e, 20));
+        if (!mask[i]) {
+            // larger error first, then smaller index; e >= 0 so its bits order like its value,
+            // once -0 (accepted as e >= 0, but with the sign bit set) is made +0
+            const unsigned eb = e == 0.f ? 0u : __float_as_uint(e);
+            key = ((unsigned long long)eb << 32) | (0xFFFFFFFFu - (unsigned)i);
+        }
+    }
+    // (every lane executes every shuffle: a lane that skipped one would leave
+    // its value undefined for the lanes reading it)
+    const int cprev = __shfl_up(cell, 1, 64), cnext = __shfl_down(cell, 1, 64);
+    int head = lane == 0 || cprev != cell;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int ho = __shfl_up(head, d, 64);
+        const unsigned long long qo = shfl_up_u64(q, d), ko = shfl_up_u64(key, d);
+        if (lane >= d && !head) {
+            q += qo;
+            key = ko > key ? ko : key;
+            head = ho;
+        }
+    }
+    const bool last = lane == 63 || cnext != cell;
+    if (last && cell >= 0) {
+        if (q) atomicAdd(&E[cell], q);
+        if (key) atomicMax(&best[cell], key);
     }
 }
 
@@ -524,9 +613,15 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
     int T = 0;
     if (partition == HDI_PART_DELAUNAY && W > 1 && H > 1) {
         // 2 triangles: emit, sort by (a, b, c) with two stable radix passes, merge duplicates
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, 1, 0, (int *)d.count);
-        hipLaunchKernelGGL(k_quads, gd((long)(W - 1) * (H - 1)), dim3(256), 0, s, W, H, d.labels, d.count, d.ta, d.tb,
-                           d.tc);
+        // (the block counts and offsets use the triangle flag and offset arrays,
+        // free until the merge below)
+        const long nq = (long)(W - 1) * (H - 1);
+        const int nqb = (int)((nq + 255) / 256);
+        hipLaunchKernelGGL(k_quads_count, dim3(nqb), dim3(256), 0, s, W, H, d.labels, d.flag);
+        size_t tq = d.tmp_bytes;
+        D_TRY(scan_exclusive(d.tmp, tq, d.flag, d.off, nqb, s));
+        hipLaunchKernelGGL(k_quads_write, dim3(nqb), dim3(256), 0, s, W, H, d.labels, d.flag, d.off, d.ta, d.tb, d.tc,
+                           d.count);
         unsigned int nt = 0;
         D_TRY(read_to_host(&nt, d.count, sizeof(unsigned int), s));
         if (nt > 0) {
@@ -550,7 +645,12 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
         }
         // 3 ownership
         hipLaunchKernelGGL(k_fill_i32, gd(N), dim3(256), 0, s, N, INT_MAX, d.owner);
-        if (T > 0) hipLaunchKernelGGL(k_raster, gd(T), dim3(256), 0, s, W, T, d.ua, d.ub, d.uc, d.owner);
+        if (T > 0 && 2LL * W * H < (1LL << 31))
+            hipLaunchKernelGGL(k_raster<int>, gd((long)T * RASTER_LANES), dim3(256), 0, s, W, T, d.ua, d.ub, d.uc,
+                               d.owner);
+        else if (T > 0)
+            hipLaunchKernelGGL(k_raster<long long>, gd((long)T * RASTER_LANES), dim3(256), 0, s, W, T, d.ua, d.ub,
+                               d.uc, d.owner);
     }
     // 4 cell sums and argmax
     const int ncell = T + m;
