@@ -264,6 +264,11 @@ k_quads_write(int W, int H, const int *__restrict__ labels, const int *__restric
         *total = (unsigned int)(block_off[blockIdx.x] + block_count[blockIdx.x]);
 }
 
+// out = a[0] + b[0] (the last exclusive offset plus the last flag: a count)
+__global__ void k_last_sum(const int *__restrict__ a, const int *__restrict__ b, int *__restrict__ out) {
+    if (threadIdx.x == 0) *out = *a + *b;
+}
+
 __global__ void k_iota(int n, int *__restrict__ v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) v[i] = i;
@@ -638,10 +643,9 @@ static int32_t run_densify(DensWs &d, int W, int H, uint8_t *mask, const float *
             D_TRY(scan_exclusive(d.tmp, tb, d.flag, d.off, n, s));
             hipLaunchKernelGGL(k_uniq_scatter, gd(n), dim3(256), 0, s, n, d.ord0, d.flag, d.off, d.ta, d.tb, d.tc,
                                d.ua, d.ub, d.uc);
-            int last_off = 0, last_flag = 0;
-            D_TRY(read_to_host(&last_off, d.off + n - 1, sizeof(int), s));
-            D_TRY(read_to_host(&last_flag, d.flag + n - 1, sizeof(int), s));
-            T = last_off + last_flag;
+            // the number of distinct triangles, read back in one copy
+            hipLaunchKernelGGL(k_last_sum, dim3(1), dim3(64), 0, s, d.off + n - 1, d.flag + n - 1, (int *)d.count);
+            D_TRY(read_to_host(&T, d.count, sizeof(int), s));
         }
         // 3 ownership
         hipLaunchKernelGGL(k_fill_i32, gd(N), dim3(256), 0, s, N, INT_MAX, d.owner);
