@@ -148,11 +148,16 @@ void Engine::describe(const EJob &j) {
     m.counts = d_counts_ + (size_t)i * MAX_LEVELS;
 }
 
-int32_t Engine::upload_desc(const EJob &j, hipStream_t s) {
-    const int i = j.slot;
-    B_TRY(hipMemcpyAsync(d_lev_ + (size_t)i * MAX_LEVELS, &h_lev_[(size_t)i * MAX_LEVELS], sizeof(BLev) * MAX_LEVELS,
-                         hipMemcpyHostToDevice, s));
-    B_TRY(hipMemcpyAsync(d_img_ + i, &h_img_[i], sizeof(BImg), hipMemcpyHostToDevice, s));
+// The descriptors of the slots lo..hi in two copies (each small copy from
+// host memory costs the host tens of microseconds, so the slots of a whole
+// admission go together; slots in between that are running hold the same
+// descriptors on both sides).
+int32_t Engine::upload_desc(int lo, int hi, hipStream_t s) {
+    if (lo > hi) return HDI_OK;
+    const size_t n = (size_t)(hi - lo + 1);
+    B_TRY(hipMemcpyAsync(d_lev_ + (size_t)lo * MAX_LEVELS, &h_lev_[(size_t)lo * MAX_LEVELS],
+                         sizeof(BLev) * MAX_LEVELS * n, hipMemcpyHostToDevice, s));
+    B_TRY(hipMemcpyAsync(d_img_ + lo, &h_img_[lo], sizeof(BImg) * n, hipMemcpyHostToDevice, s));
     return HDI_OK;
 }
 
@@ -171,7 +176,11 @@ int32_t Engine::admit(const std::vector<EJob *> &news, std::vector<EJob *> &ende
         j->where = 0;
         maxL = std::max(maxL, j->h.nlev_full);
         describe(*j);
-        int32_t st = upload_desc(*j, s);
+    }
+    {
+        int lo = nslots_, hi = -1;
+        for (EJob *j : news) { lo = std::min(lo, j->slot); hi = std::max(hi, j->slot); }
+        const int32_t st = upload_desc(lo, hi, s);
         if (st) return st;
     }
     hipLaunchKernelGGL(kb_zero_counts, dim3((nslots_ * MAX_LEVELS + 255) / 256), dim3(256), 0, s,
@@ -216,11 +225,15 @@ int32_t Engine::admit(const std::vector<EJob *> &news, std::vector<EJob *> &ende
             }
         }
         describe(*j);
-        int32_t st = upload_desc(*j, s);
-        if (st) return st;
         go.push_back(j);
     }
     if (go.empty()) return HDI_OK;
+    {
+        int lo = nslots_, hi = -1;
+        for (EJob *j : go) { lo = std::min(lo, j->slot); hi = std::max(hi, j->slot); }
+        const int32_t st = upload_desc(lo, hi, s);
+        if (st) return st;
+    }
 
     // 3. starting iterate: the data on the mask, and elsewhere the reduced FMG
     // (Sec. 3.2) for cold data problems, the caller's start for warm ones, 0

@@ -60,7 +60,7 @@ private:
         void add(BPhase &ph, int img, int lev, long count, int unit);
     };
     void describe(const EJob &j);
-    int32_t upload_desc(const EJob &j, hipStream_t s);
+    int32_t upload_desc(int lo, int hi, hipStream_t s);
 
     int nslots_ = 0;
     BLev *d_lev_ = nullptr;
