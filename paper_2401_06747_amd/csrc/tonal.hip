@@ -193,6 +193,12 @@ __global__ void k_gather_d(int m, int C, int N, const int *__restrict__ idx, con
     for (int c = 0; c < C; ++c) v[(size_t)c * m + j] = img[(size_t)c * N + idx[j]];
 }
 
+// Loosest tolerance of an inner solve inside a Krylov product. Late outer
+// iterations reach it: from 1e-3 to 3e-2, a loose product takes one V-cycle
+// fewer (4K RGB, 3% mask: 47 -> 43 V-cycles per call at the same 6 outer
+// iterations; the final residual is certified with tight solves either way).
+constexpr double KRYLOV_TOL_CAP = 3e-2;
+
 static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double *u_out, hdi_tonal_report *rep) {
     TonalWs &t = X.t;
     const int C = X.C, m = X.m;
@@ -231,7 +237,7 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
     // can reach, which happens for sparse masks, where A^{-1} is large).
     // Krylov products are relaxed as 1e-1 * rel_tol / ||r||_rel (against 3e-2,
     // fewer V-cycles at the same outer iteration counts on most masks; on a
-    // sparse 1% mask one more outer iteration);
+    // sparse 1% mask one more outer iteration), at most KRYLOV_TOL_CAP;
     // the stationary RAS residual evaluation keeps 1e-3.
     double fac = tc.mode == HDI_TONAL_RAS ? 1e-3 : 1e-1, best = 1e300;
     int stall = 0;
@@ -259,7 +265,7 @@ static int32_t run_tonal(TonalCtx &X, const TonalCfg &tc, double *g_out, double 
         const double tol_in =
             tc.mode == HDI_TONAL_RAS
                 ? std::min(1e-4, std::max(tight, fac * rmin))
-                : std::min(1e-3, std::max(tight, fac * tc.rel_tol / std::max(rmin, 1e-300)));
+                : std::min(KRYLOV_TOL_CAP, std::max(tight, fac * tc.rel_tol / std::max(rmin, 1e-300)));
 
         const Blocks1D tbx = make_blocks(X.W, tc.overlap, tc.block), tby = make_blocks(X.H, tc.overlap, tc.block);
         const double block_px = (double)std::min(tc.block, X.W) * std::min(tc.block, X.H);
