@@ -308,3 +308,16 @@ def test_rgb_270x480_default_tolerance():
     g, rep, u = _run(inst.f, inst.mask)
     err, nres = _check(inst.f, inst.mask, g, rep, u, tol=1e-6)
     print("270x480 rgb at 1e-6", err, nres, rep)
+
+
+@pytest.mark.parametrize("density,C", [(0.005, 1), (0.014, 1), (0.01, 3)])
+def test_sparse_masks_default_tolerance(density, C):
+    """Sparse masks at the default tolerance (1e-6): the loose inner solves of
+    the late outer iterations (inexact Krylov products) and the tight final
+    check still give the oracle's optimum to the 1e-5 bar on g, its MSE to
+    1e-4, and a normal residual that the oracle measures within the tolerance."""
+    f = synth.textured_image(270, 480, C, 5, 61 + C)
+    m = synth.gradient_mask(f, density)
+    g, rep, u = _run(f, m, max_outer=400)
+    err, nres = _check(f, m, g, rep, u, tol=1e-6)
+    print("sparse at 1e-6", density, C, err, nres, rep)
