@@ -419,7 +419,11 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     (void)nU;
     if (prof) prof->begin(5, 0.0, s);
     const bool fmg = !warm && !(cfg.flags & HDI_FLAG_NO_FMG) && src == nullptr && h.nlev > 1;
-    launch_init_u<TD>(W, H, C, mask, data, warm || fmg, u, s);
+    // A cold source problem starts from u = 0 everywhere: instead of filling u,
+    // the first residual pass and the first refinement step take a null
+    // iterate (read as zero), and the first step writes the whole iterate.
+    bool zero = !warm && src != nullptr;
+    if (!zero) launch_init_u<TD>(W, H, C, mask, data, warm || fmg, u, s);
     if (fmg) fmg_init<TD>(h, W, H, C, mask, data, u, cfg, s);
     if (prof) prof->end(s);
     HIP_TRY(hipGetLastError());
@@ -436,12 +440,16 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
     for (;;) {
         // mask, u in, r out; the source off the mask; e in and u out after a
         // V-cycle (the data is not read: u holds it on the mask)
-        const double res_bytes = N * (1 + 12.0 * C) + (src ? 8.0 * C * nU : 0.0) +
+        const double res_bytes = N * (1 + (zero ? 4.0 : 12.0) * C) + (src ? 8.0 * C * nU : 0.0) +
                                  (e ? 12.0 * C * N : 0.0);
         if (prof) prof->begin(0, res_bytes, s);
-        launch_residual<TD>(W, H, C, mask, cur, e, e ? oth : nullptr, data, src, h.lev[0].r, h.partials, h.norms, s);
+        launch_residual<TD>(W, H, C, mask, zero ? nullptr : cur, e, e ? oth : nullptr, data, src, h.lev[0].r,
+                            h.partials, h.norms, s);
         if (prof) prof->end(s);
-        if (e) std::swap(cur, oth);
+        if (e) {
+            std::swap(cur, oth);
+            zero = false;
+        }
         // When a V-cycle may follow, its first launch is queued behind the copy
         // of the norms, guarded on the device by the same test with a margin
         // (so that a guarded exit implies the host's stop below), and the host
@@ -484,6 +492,8 @@ int32_t solve_system(Hierarchy &h, int W, int H, int C, const uint8_t *mask, con
         ++rounds;
         ++vcycles;
     }
+    // stopped before the first refinement step: the zero iterate was never written
+    if (zero) launch_init_u<TD>(W, H, C, mask, data, false, u, s);
     if (cur != u) {
         if (swap && *swap == u) {
             *swap = cur;

@@ -42,7 +42,8 @@ __global__ void k_init_u(int N, int C, const uint8_t *__restrict__ mask, const T
 // Fused refinement step and FP64 residual. With e != nullptr the iterate is
 // first advanced, u_out = u_in + e (e is exactly 0 on known pixels, so known
 // values stay bit-exact), and the residual is taken at u_out; u_out must not
-// alias u_in because neighbours read u_in. Then r = b - A u in FP64 with
+// alias u_in because neighbours read u_in. A null u_in is the zero iterate
+// (nothing is read for it; the values are those of a zero-filled u_in). Then r = b - A u in FP64 with
 // b = data on known pixels and src (or 0) elsewhere, stored as FP32 for the
 // inner solve, plus per-workgroup FP64 partial sums of r^2 and b^2 per channel.
 //
@@ -95,7 +96,7 @@ __device__ __forceinline__ void residual_block(int W, int H, const uint8_t *__re
     auto fetch = [&](int c, int y, double &uv, float &ev) {
         const int yc = min(max(y, 0), H - 1);
         const size_t j = (size_t)c * N + (size_t)yc * W + xs;
-        uv = u_in[j];
+        uv = u_in ? u_in[j] : 0.0;
         ev = e ? e[j] : 0.f;
     };
     auto fetch_mask = [&](int y) -> int { return mask[(size_t)min(y, H - 1) * W + xs]; };
